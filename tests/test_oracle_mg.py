@@ -1,0 +1,225 @@
+"""Pins of the oracle's multigrid (Sec. 3 and 4): transfer operators, Galerkin
+identities, solvers and the full K-cycle solve against exact solutions."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.special import i0, i1
+
+from oracle.staggered import Lattice, epsilon_dof, gauge_rotate, gauge_matrix
+from oracle.kd import KDOperator
+from oracle.mg import (MGParams, LevelParams, Hierarchy, Solver, cg, gcr, cgne,
+                       mr, thin_qr_positive, global_orthonormalise,
+                       relax_null_vectors)
+from oracle.exact import dense_solve, cg_eo, free_fft_solve
+from synth import (u1_heatbath, unit_gauge, gaussian_vectors,
+                   gauge_transform_field, u1_plaquette)
+
+
+def build(lat, U, m, params, seed):
+    psi0 = []
+    n = lat.ndof
+    for k, lp in enumerate(params.levels):
+        psi0.append(gaussian_vectors(lp.nvec, n, seed, tag=1 + k))
+        if k == 0:
+            ncs = lat.volume // int(np.prod([2 * a for a in lp.agg]))
+        else:
+            ncs = ncs // int(np.prod(lp.agg))
+        n = ncs * 2 * lp.nvec
+    return Hierarchy(lat, U, m, params, psi0)
+
+
+@pytest.fixture(scope="module")
+def h2():
+    lat = Lattice((16, 16))
+    U, _ = u1_heatbath((16, 16), 3.0, 50, 101)
+    params = MGParams(levels=[LevelParams((4, 4), 8)])
+    return build(lat, U, 0.1, params, 7), U
+
+
+@pytest.fixture(scope="module")
+def h3():
+    lat = Lattice((32, 32))
+    U, _ = u1_heatbath((32, 32), 6.0, 50, 102)
+    params = MGParams(levels=[LevelParams((2, 2), 8), LevelParams((2, 2), 8)])
+    return build(lat, U, 0.02, params, 8), U
+
+
+def test_thin_qr_positive_is_cholesky_qr():
+    """Sec. 5 (eq. thinqr): Gram-Schmidt = thin QR = Cholesky-QR."""
+    M = gaussian_vectors(6, 20, 1)[:, :].T
+    Q = thin_qr_positive(M)
+    R = Q.conj().T @ M
+    assert np.allclose(np.tril(R, -1), 0, atol=1e-13)
+    assert np.all(np.abs(np.diagonal(R).imag) < 1e-13) and np.all(np.diagonal(R).real > 0)
+    Lc = np.linalg.cholesky(M.conj().T @ M)
+    Qc = M @ np.linalg.inv(Lc.conj().T)
+    assert np.allclose(Q, Qc, atol=1e-12)
+
+
+def test_global_mgs_orthonormal():
+    V = global_orthonormalise(gaussian_vectors(5, 30, 2))
+    assert np.allclose(V.conj() @ V.T, np.eye(5), atol=1e-13)
+
+
+def test_prolongator_properties(h2, h3):
+    """Sec. 3: P^dag P = 1; chiral doubling gives epsilon P = P sigma_3 (level 1)
+    and sigma_3 P_hat = P_hat sigma_3 (coarser levels)."""
+    for h, _ in (h2, h3):
+        for k, P in enumerate(h.P):
+            nc = P.shape[1]
+            assert abs(P.conj().T @ P - sp.identity(nc)).max() < 1e-13
+            nv = h.params.levels[k].nvec
+            s3c = np.tile(np.r_[np.ones(nv), -np.ones(nv)], nc // (2 * nv))
+            if k == 0:
+                s3f = epsilon_dof(h.lat)
+            else:
+                nvp = h.params.levels[k - 1].nvec
+                s3f = np.tile(np.r_[np.ones(nvp), -np.ones(nvp)], P.shape[0] // (2 * nvp))
+            assert abs(sp.diags(s3f) @ P - P @ sp.diags(s3c)).max() < 1e-14
+
+
+def test_prolongator_spans_null_vectors(h2):
+    """Each chirally projected null vector lies in the range of P."""
+    h, _ = h2
+    P = h.P[0].toarray()
+    eps = epsilon_dof(h.lat)
+    for v in h.nullvecs[0]:
+        for s in (+1, -1):
+            w = 0.5 * (1 + s * eps) * v
+            assert np.linalg.norm(w - P @ (P.conj().T @ w)) < 1e-11 * np.linalg.norm(w)
+
+
+def test_galerkin_identities(h2):
+    """A_hat = P^dag A P (dense check); P^dag (B^-1 D) P = sigma_3 A_hat^dag sigma_3;
+    A_hat couples only nearest-neighbour coarse sites."""
+    h, _ = h2
+    kd = h.kd
+    P = h.P[0].toarray()
+    A = kd.A.toarray()
+    Ahat = h.ops[1].toarray()
+    assert np.allclose(P.conj().T @ A @ P, Ahat, atol=1e-13)
+    left = P.conj().T @ (kd.Binv.toarray() @ kd.D.toarray()) @ P
+    nv = h.params.levels[0].nvec
+    s3 = np.diag(np.tile(np.r_[np.ones(nv), -np.ones(nv)], Ahat.shape[0] // (2 * nv)))
+    assert np.allclose(left, s3 @ Ahat.conj().T @ s3, atol=1e-13)
+
+
+def test_coarse_nearest_neighbour(h3):
+    h, _ = h3
+    for k in (1, 2):
+        op = h.ops[k].tocoo()
+        dims = h.aggr[k - 1].coarse_dims
+        ndof = op.shape[0] // int(np.prod(dims))
+        sr, sc = op.row // ndof, op.col // ndof
+        xr = np.stack([sr % dims[0], sr // dims[0]], 1)
+        xc = np.stack([sc % dims[0], sc // dims[0]], 1)
+        d = np.abs(xr - xc)
+        d = np.minimum(d, np.array(dims) - d)
+        assert np.all(d.sum(axis=1) <= 1)
+
+
+def test_oblique_projector_annihilates_coarse_space(h2):
+    """Sec. 3.2: (1 - P (R A P)^-1 R A) P R = 0 with R = P^dag."""
+    h, _ = h2
+    P = h.P[0].toarray()
+    R = P.conj().T
+    A = h.kd.A.toarray()
+    Pob = np.eye(A.shape[0]) - P @ np.linalg.solve(R @ A @ P, R @ A)
+    assert np.abs(Pob @ P @ R).max() < 1e-10
+
+
+def test_null_vectors_are_near_null(h2):
+    """Parity unpinned values; property: relaxed vectors have a far smaller
+    Rayleigh quotient of A A^dag than their Gaussian starts."""
+    h, _ = h2
+    A = h.kd.A
+    psi0 = gaussian_vectors(8, h.lat.ndof, 7, tag=1)
+    for v, v0 in zip(h.nullvecs[0], psi0):
+        rq = lambda u: np.linalg.norm(A.conj().T @ u) ** 2 / np.linalg.norm(u) ** 2
+        assert rq(v) < 0.2 * rq(v0)
+
+
+def test_krylov_solvers_on_random_system():
+    rng = np.random.default_rng(3)
+    n = 60
+    M = np.eye(n) * 3 + rng.standard_normal((n, n)) * 0.2 + 1j * rng.standard_normal((n, n)) * 0.2
+    b = gaussian_vectors(1, n, 4)[0]
+    x_ref = np.linalg.solve(M, b)
+    x, its, _ = gcr(lambda v: M @ v, b, lambda v: v, 10, 200, 1e-12 * np.linalg.norm(b))
+    assert np.allclose(x, x_ref, atol=1e-10)
+    x, its = cgne(sp.csr_matrix(M), b, 1e-12, 500)
+    assert np.allclose(x, x_ref, atol=1e-10)
+    H = M @ M.conj().T
+    y, its = cg(lambda v: H @ v, b, 1e-12, 500)
+    assert np.allclose(H @ y, b, atol=1e-9)
+    # MR reduces the residual of a positive-real operator
+    xm, r = mr(lambda v: M @ v, b, 2, 0.85)
+    assert np.linalg.norm(b - M @ xm) < np.linalg.norm(b)
+    assert np.allclose(r, b - M @ xm, atol=1e-12)
+
+
+def test_two_level_solve_matches_dense_lu(h2):
+    """C1-shaped: 16^2, beta=3, m=0.1, 2-level, n_vec 8: true residual <= 1e-10
+    and the solution agrees with dense LU to 1e-8."""
+    h, U = h2
+    b = gaussian_vectors(1, h.lat.ndof, 55)[0]
+    x, info = Solver(h).solve(b, 1e-10)
+    assert info["true_rel_resid"] <= 1e-10
+    xd = dense_solve(h.lat, U, 0.1, b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-8
+    assert info["outer_its"] < 60
+
+
+def test_three_level_solve_matches_cg_eo(h3):
+    h, U = h3
+    b = gaussian_vectors(1, h.lat.ndof, 56)[0]
+    x, info = Solver(h).solve(b, 1e-10)
+    assert info["true_rel_resid"] <= 1e-10
+    xr, _ = cg_eo(h.lat, U, 0.02, b, tol=1e-14)
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) < 1e-8
+    assert len(info["level_avg_its"]) == 2
+
+
+def test_free_field_solve_matches_fft():
+    lat = Lattice((32, 32))
+    params = MGParams(levels=[LevelParams((4, 4), 8)])
+    h = build(lat, unit_gauge((32, 32)), 0.01, params, 9)
+    b = gaussian_vectors(1, lat.ndof, 57)[0]
+    x, info = Solver(h).solve(b, 1e-10)
+    xf = free_fft_solve(lat, 0.01, b)
+    assert info["true_rel_resid"] <= 1e-10
+    assert np.linalg.norm(x - xf) / np.linalg.norm(xf) < 1e-8
+
+
+def test_solution_gauge_covariance():
+    """x[U^g, G b] = G x[U, b]: the MG solve commutes with gauge rotations
+    (rotated null-vector starts make the hierarchies gauge-equivalent)."""
+    lat = Lattice((16, 16))
+    U, _ = u1_heatbath((16, 16), 3.0, 30, 103)
+    g = gauge_transform_field(lat.volume, 1, 5)
+    G = gauge_matrix(lat, g)
+    params = MGParams(levels=[LevelParams((4, 4), 8)])
+    psi0 = gaussian_vectors(8, lat.ndof, 10, tag=1)
+    h = Hierarchy(lat, U, 0.1, params, [psi0])
+    # the relaxation is covariant only up to rounding amplified by CG, so the
+    # rotated hierarchy starts from the rotated relaxed vectors
+    hg = Hierarchy(lat, gauge_rotate(lat, U, g), 0.1, params,
+                   [("relaxed", (G @ h.nullvecs[0].T).T)])
+    b = gaussian_vectors(1, lat.ndof, 58)[0]
+    x, _ = Solver(h).solve(b, 1e-12)
+    xg, _ = Solver(hg).solve(G @ b, 1e-12)
+    assert np.linalg.norm(xg - G @ x) / np.linalg.norm(x) < 1e-9
+    # the coarse operators agree exactly (gauge-invariant up to rounding)
+    assert abs(hg.ops[1] - h.ops[1]).max() < 1e-10
+
+
+@pytest.mark.parametrize("beta", [3.0, 6.0])
+def test_heatbath_plaquette(beta):
+    """Quenched 2D compact U(1): <Re U_P> -> I1(beta)/I0(beta) (textbook closed
+    form of the 2D U(1) Wilson action, infinite volume)."""
+    plaq = []
+    for c in range(3):
+        U, info = u1_heatbath((32, 32), beta, 60, 500 + c)
+        plaq.append(info["plaquette"])
+    expect = i1(beta) / i0(beta)
+    assert abs(np.mean(plaq) - expect) < 0.01
