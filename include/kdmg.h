@@ -1,0 +1,210 @@
+/*
+ * kdmg.h - Kahler-Dirac-preconditioned adaptive multigrid for the staggered
+ * Dirac operator on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The problem (Brower, Clark, Strelchenko, Weinberg, "Multigrid for staggered
+ * lattice fermions", arXiv:1801.07823, Sec. 1): solve D(U, m) x = b with the
+ * staggered operator of eq. "staggeredD",
+ *
+ *   (D psi)(x) = m psi(x) + 1/2 sum_mu eta_mu(x) [ U_mu(x) psi(x+mu)
+ *                                                - U_mu(x-mu)^dag psi(x-mu) ],
+ *   eta_mu(x) = (-1)^{x_1 + ... + x_{mu-1}},
+ *
+ * periodic in every direction except the last (time), which is antiperiodic.
+ * The solver right-preconditions D by its 2^d Kahler-Dirac blocks B
+ * (A = D B^-1 = 1 + C B^-1, Sec. 2.1 eq. "defA"), coarsens A by Galerkin
+ * projection on chirally doubled, block-orthonormalised near-null vectors
+ * (Sec. 3, 4), and runs flexible GCR on the KD-block-parity Schur operator
+ * 1 - A_eo A_oe preconditioned by a K-cycle (Sec. 4, Table 1).
+ *
+ * Conventions shared by every call
+ *   - Site index: x_1 + L_1*(x_2 + L_2*(...)), x_1 fastest, time = last axis.
+ *   - Fine vectors: complex [rhs][site][colour]; complex128 (interleaved re,im
+ *     doubles) unless a call says complex64.  Device pointers, caller-owned,
+ *     never freed by the library.
+ *   - Gauge links (host, copied at create): complex128 [mu][site][a][b],
+ *     U_mu(x) the link from x to x+mu.
+ *   - Coarse vectors on coarsening level k (k = 1 is the first coarse lattice):
+ *     complex [rhs][Z][c*nvec_k + i], Z the coarse site (x_1 fastest), c = 0 for
+ *     chirality +1 and 1 for -1 (sigma_3 = diag(1..1, -1..-1)), i the vector.
+ *   - Even-block vectors (Schur space): the sites whose Kahler-Dirac block
+ *     (floor(x_mu/2)) has even parity, in increasing site index.
+ *   - Every call is stream-ordered on `stream` (a hipStream_t; NULL = default
+ *     stream) and returns without waiting unless it says so.
+ *   - Errors: every call returns a kdmg_status; nothing aborts or throws across
+ *     the ABI.  kdmg_last_error() gives a thread-local message for the last
+ *     failure.  Invalid sizes return KDMG_EINVAL before any device work.
+ *
+ * Supported geometry: nd = 2 with ncolor = 1 (U(1)), extents divisible by
+ * 4 and by twice the first aggregate extent; nd = 4 with ncolor = 3 (SU(3)).
+ */
+#ifndef KDMG_H
+#define KDMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KDMG_OK = 0,
+  KDMG_EINVAL = -1,       /* bad argument or unsupported shape */
+  KDMG_ENOMEM = -2,       /* device allocation failed / over the memory budget */
+  KDMG_EHIP = -3,         /* HIP runtime error */
+  KDMG_ENOCONV = -4,      /* solver hit its iteration cap; outputs hold the best iterate */
+  KDMG_EBUSY = -5,        /* object in use */
+  KDMG_EUNSUPPORTED = -6  /* valid request the library does not implement */
+} kdmg_status;
+
+typedef enum {
+  KDMG_FP64 = 0,  /* every level in FP64 */
+  KDMG_MIXED = 1  /* FP64 outer FGCR, V-cycle in FP32 with FP16-stored links and
+                     null vectors, FP64 coarsest solve */
+} kdmg_prec;
+
+typedef struct kdmg_lattice kdmg_lattice;     /* geometry + gauge field, device-resident */
+typedef struct kdmg_hierarchy kdmg_hierarchy; /* KD blocks, P and coarse operators at one mass */
+
+/* One coarsening (Table 1 rows "number of null vectors" / "size of aggregate block"). */
+typedef struct {
+  int agg[4]; /* aggregate extent per direction: KD blocks on the first coarsening
+                 (so 4 means 8 fine sites), coarse sites on later ones */
+  int nvec;   /* near-null vectors; the coarse lattice carries 2*nvec dofs per site */
+} kdmg_level_params;
+
+/* The K-cycle parameter set of Table 1. */
+typedef struct {
+  int nlevels;                /* total levels including the fine one: 2..4 */
+  kdmg_level_params lvl[3];   /* lvl[k] builds level k+1 from level k */
+  double setup_tol;           /* CG relative tolerance per null vector (1e-4) */
+  int setup_maxit;            /* CG iterations per null vector (250) */
+  int outer_restart;          /* fine FGCR restart length (32) */
+  int outer_maxit;            /* fine FGCR iteration cap (KDMG_ENOCONV beyond) */
+  int mr_its;                 /* MR pre/post-smoothing iterations (2) */
+  double mr_omega;            /* MR relaxation parameter (0.85) */
+  int inter_restart;          /* intermediate GCR restart (8) */
+  int inter_maxit;            /* intermediate GCR iteration cap (16) */
+  double inter_tol;           /* intermediate GCR relative tolerance (0.2) */
+  double coarse_tol;          /* coarsest CGNE relative tolerance (0.2) */
+  int coarse_maxit;           /* coarsest CGNE iteration cap (256) */
+} kdmg_mg_params;
+
+/* Per right-hand side result of kdmg_solve. */
+typedef struct {
+  int converged;              /* true residual <= tol */
+  int outer_its;              /* fine FGCR iterations */
+  int fine_applies;           /* applications of the Schur operator (one counts as one A) */
+  double level_avg_its[3];    /* average Krylov iterations per call on levels 2.. */
+  double true_rel_resid;      /* ||b - D x|| / ||b||, recomputed in FP64 */
+  double seconds;             /* wall time of the batched solve this rhs was part of */
+} kdmg_solve_info;
+
+/* Table 1 defaults with a three-level hierarchy (4^2 then 2^2 aggregates,
+   n_vec 8 then 12). */
+void kdmg_default_params(kdmg_mg_params* p);
+
+/* Binds the library to HIP device `device` (call once per process before any
+   other call; idempotent). */
+kdmg_status kdmg_init(int device);
+
+/* Uploads a gauge field.  links_host: complex128 [nd][volume][ncolor][ncolor]
+   (copied; the caller keeps ownership).  antiperiodic_time != 0 applies the
+   antiperiodic sign to hops that cross the last axis' boundary. */
+kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
+                                const double* links_host, int antiperiodic_time,
+                                kdmg_lattice** out);
+void kdmg_lattice_destroy(kdmg_lattice* lat);
+/* Device bytes held by the lattice. */
+kdmg_status kdmg_lattice_footprint(const kdmg_lattice* lat, size_t* bytes);
+
+/* out = D(U, mass) in  (eq. "staggeredD"), natural site order.
+   prec = KDMG_FP64: complex128 vectors and FP64 links.
+   prec = KDMG_MIXED: complex64 vectors, FP16-stored links, FP32 arithmetic.
+   in and out must not overlap. */
+kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const void* in,
+                         void* out, int nrhs, kdmg_prec prec, void* stream);
+
+/* out = A in with A = D B^-1 (Sec. 2.1 eq. "defA"), or out = A^dag in when
+   dagger != 0, using A^dag = eps B^-1 D eps (eq. "gamma5L").  complex128, FP64.
+   B^-1 is the exact inverse of each 2^d Kahler-Dirac block (mass included). */
+kdmg_status kdmg_apply_A(const kdmg_lattice* lat, double mass, const void* in,
+                         void* out, int nrhs, int dagger, void* stream);
+
+/* out = B^-1 in (block-local inverse of the Kahler-Dirac blocks), complex128. */
+kdmg_status kdmg_apply_Binv(const kdmg_lattice* lat, double mass, const void* in,
+                            void* out, int nrhs, void* stream);
+
+/* out_e = (1 - A_eo A_oe) in_e on even-block vectors (Table 1 level-1 operator),
+   complex128, FP64. */
+kdmg_status kdmg_apply_schur(const kdmg_lattice* lat, double mass,
+                             const void* in_even, void* out_even, int nrhs,
+                             void* stream);
+
+/* Builds the KD-MG hierarchy (Sec. 4 setup):
+   for coarsening k = 0..nlevels-2, relax n_vec Gaussian starts with CG on
+   A_k A_k^dag (tolerance setup_tol, setup_maxit iterations), orthonormalise
+   them globally (modified Gram-Schmidt in vector order), chirally double and
+   block-orthonormalise (thin QR, positive real diagonal) into P_k, and form
+   A_{k+1} = P_k^dag A_k P_k.
+   psi0_host[k]: complex128 [nvec_k][ndof_k] host starting vectors of coarsening
+   k in that level's layout (fine: natural [site][colour]; coarse: see top).
+   relaxed != 0: the vectors are taken as already-relaxed near-null vectors
+   (no CG), which makes the hierarchy a pure function of them.
+   Synchronises `stream` before returning.  The lattice must outlive the
+   hierarchy. */
+kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass,
+                                 const kdmg_mg_params* params,
+                                 const double* const* psi0_host, int relaxed,
+                                 void* stream, kdmg_hierarchy** out);
+void kdmg_hierarchy_destroy(kdmg_hierarchy* h);
+
+/* Geometry of coarse level k (1 .. nlevels-1): dims[0..nd-1], dofs per site. */
+kdmg_status kdmg_hierarchy_level_info(const kdmg_hierarchy* h, int level,
+                                      int* dims_out, int* ndof_site_out);
+/* Copies to host: the relaxed null vectors of coarsening k (before any
+   orthonormalisation), complex128 [nvec][ndof_k]. */
+kdmg_status kdmg_hierarchy_get_nullvecs(const kdmg_hierarchy* h, int k, double* host_out);
+/* Copies to host the prolongator of coarsening k as its nonzero values:
+   complex128 [ndof_k][nvec], row x holding P[x, (Z(x), c(x), i)] for i < nvec,
+   where Z(x), c(x) are the aggregate and chirality of dof x. */
+kdmg_status kdmg_hierarchy_get_prolongator(const kdmg_hierarchy* h, int k, double* host_out);
+/* Copies to host the coarse operator of level k >= 1 as its stencil blocks:
+   complex128 [ndir][nsites][ndof][ndof], ndir = 2*nd + 1, direction 0 the
+   site itself, 1 + 2*mu the neighbour Z + mu, 2 + 2*mu the neighbour Z - mu;
+   block [dir][Z][i][j] couples dof i of Z to dof j of that neighbour. */
+kdmg_status kdmg_hierarchy_get_coarse_op(const kdmg_hierarchy* h, int level, double* host_out);
+
+/* out = A_level in (dagger = 0) or A_level^dag in on coarse level >= 1.
+   prec KDMG_FP64: complex128 and FP64 operator; KDMG_MIXED: complex64 and the
+   FP32 operator. */
+kdmg_status kdmg_coarse_apply(const kdmg_hierarchy* h, int level, int dagger,
+                              const void* in, void* out, int nrhs, kdmg_prec prec,
+                              void* stream);
+/* Restriction R_k = P_k^dag from level k to k+1 and prolongation P_k, complex128. */
+kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void* in, void* out,
+                          int nrhs, void* stream);
+kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* out,
+                         int nrhs, void* stream);
+
+/* Solves D x = b for nrhs right-hand sides sharing the hierarchy (Sec. 4):
+   FGCR on the Schur system until ||b - D x|| <= tol ||b|| per rhs, then
+   reconstruction and an FP64 true-residual check.  b, x: complex128 device
+   vectors (x is overwritten; its input value is ignored).  info_host: nrhs
+   records (may be NULL).  Synchronises `stream`.  Returns KDMG_ENOCONV if any
+   rhs missed tol within outer_maxit iterations. */
+kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int nrhs, double tol,
+                       kdmg_prec prec, kdmg_solve_info* info_host, void* stream);
+
+/* Device bytes held by the hierarchy including its solve workspace for
+   `nrhs` right-hand sides (admission control). */
+kdmg_status kdmg_hierarchy_footprint(const kdmg_hierarchy* h, int nrhs, size_t* bytes);
+
+const char* kdmg_status_string(kdmg_status s);
+const char* kdmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KDMG_H */

@@ -1,0 +1,141 @@
+// Host drivers of the batched Krylov methods (Sec. 4, Table 1).  Operators are
+// callables  op(out, in, resid, act)  computing out = op(in), or
+// out = resid - op(in) when `resid` is non-null, for the rhs whose flag in
+// `act` is set.
+#pragma once
+#include "krylov.h"
+
+namespace kdmg {
+
+// Device allocations for one Krylov state of `nrhs` right-hand sides.
+struct KrylovAlloc {
+  DevBuf sc, ints;
+  KrylovState k;
+  void init(int nrhs) {
+    sc.alloc(sizeof(double) * S_COUNT * nrhs);
+    ints.alloc(sizeof(int) * 4 * nrhs);
+    KDMG_HIP(hipMemset(sc.p, 0, sc.bytes));
+    KDMG_HIP(hipMemset(ints.p, 0, ints.bytes));
+    k.sc = sc.as<double>();
+    k.act = ints.as<int>();
+    k.its = k.act + nrhs;
+    k.calls = k.its + nrhs;
+    k.tot = k.calls + nrhs;
+  }
+  // a state sharing another's flags (smoothers run under their caller's mask)
+  KrylovState under(const int* act) const {
+    KrylovState s = k;
+    s.act = const_cast<int*>(act);
+    return s;
+  }
+};
+
+struct CtxAlloc {
+  DevBuf partials, counters;
+  int* h_poll = nullptr;
+  Ctx c;
+  void init(hipStream_t st, int slots, int nrhs_max) {
+    partials.alloc(sizeof(double) * (size_t)slots * 3 * RED_MAX_BLOCKS);
+    counters.alloc(sizeof(unsigned) * slots);
+    KDMG_HIP(hipMemset(counters.p, 0, counters.bytes));
+    KDMG_HIP(hipHostMalloc((void**)&h_poll, sizeof(int) * (nrhs_max + 8), hipHostMallocDefault));
+    c.st = st;
+    c.rs.partials = partials.as<double>();
+    c.rs.counters = counters.as<unsigned>();
+    c.rs.slots = slots;
+    c.h_poll = h_poll;
+  }
+  ~CtxAlloc() {
+    if (h_poll) (void)hipHostFree(h_poll);
+  }
+};
+
+inline void start_solve(const Ctx& c, const KrylovState& k, const int* parent, int nrhs) {
+  launch_map(OpStart{k, parent}, 1, nrhs, c.st);
+}
+
+// CG on a Hermitian positive operator (null-vector relaxation).
+template <class T, class NormalF>
+int cg_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* p, Cx<T>* q,
+             double tol, int maxit, const KrylovState& k, NormalF normal, int poll) {
+  start_solve(c, k, nullptr, nrhs);
+  launch_map_reduce<1>(OpInit<T>{x, r, p, b, n, k, tol * tol, nullptr}, n, nrhs, 1, c.rs, c.st);
+  int it = 0;
+  for (; it < maxit; ++it) {
+    normal(q, p, k.act);
+    launch_map_reduce<1>(OpCGpq<T>{p, q, n, k}, n, nrhs, 1, c.rs, c.st);
+    launch_map_reduce<1>(OpCGupd<T>{x, r, p, q, n, k}, n, nrhs, 1, c.rs, c.st);
+    launch_map(OpCGp<T>{p, r, n, k}, n, nrhs, c.st);
+    if ((it + 1) % poll == 0 && !any_active(c, k.act, nrhs)) { ++it; break; }
+  }
+  return it;
+}
+
+// Global MR with zero start folded into x: x += sum omega a_k r_k (Sec. 4, Table 1).
+template <class T, class OpF>
+void mr_smooth(const Ctx& c, int nrhs, long n, Cx<T>* x, Cx<T>* r, Cx<T>* q, int its, double omega,
+               const KrylovState& k, OpF op) {
+  for (int it = 0; it < its; ++it) {
+    op(q, r, (const Cx<T>*)nullptr, k.act);
+    launch_map_reduce<3>(OpMRred<T>{q, r, n, k, omega}, n, nrhs, 1, c.rs, c.st);
+    launch_map(OpMRupd<T>{x, r, q, n, k}, n, nrhs, c.st);
+  }
+}
+
+// Flexible restarted GCR with classical Gram-Schmidt applied twice.
+// Stops a rhs when ||r||^2 <= tol^2 * (ext ? ext[r] : ||b||^2).
+template <class T, class OpF, class PrecF>
+int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* Zb,
+              Cx<T>* Wb, int restart, int maxit, double tol, const double* ext,
+              const KrylovState& k, const int* parent, OpF op, PrecF prec) {
+  start_solve(c, k, parent, nrhs);
+  launch_map_reduce<1>(OpInit<T>{x, r, nullptr, b, n, k, tol * tol, ext}, n, nrhs, 1, c.rs, c.st);
+  const long vs = (long)nrhs * n;
+  int its = 0;
+  if (!any_active(c, k.act, nrhs)) return 0;
+  while (its < maxit) {
+    for (int kk = 0; kk < restart && its < maxit; ++kk) {
+      Cx<T>* z = Zb + kk * vs;
+      Cx<T>* w = Wb + kk * vs;
+      prec(z, r, k.act);
+      op(w, z, (const Cx<T>*)nullptr, k.act);
+      if (kk > 0)
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_map_reduce<2>(OpMultiDot<T>{Wb, vs, w, n, k}, n, nrhs, kk, c.rs, c.st);
+          launch_map(OpMultiAxpy<T>{w, z, Wb, Zb, vs, kk, n, k}, n, nrhs, c.st);
+        }
+      launch_map_reduce<3>(OpGCRred<T>{w, r, n, k}, n, nrhs, 1, c.rs, c.st);
+      launch_map_reduce<1>(OpGCRupd<T>{x, r, w, z, n, k}, n, nrhs, 1, c.rs, c.st);
+      ++its;
+      if (!any_active(c, k.act, nrhs)) return its;
+    }
+    if (its >= maxit) break;
+    op(r, x, b, k.act);  // r = b - op x (true residual at restart)
+    launch_map_reduce<1>(OpResNorm<T>{r, n, k}, n, nrhs, 1, c.rs, c.st);
+    if (!any_active(c, k.act, nrhs)) break;
+  }
+  return its;
+}
+
+// CGNE on the coarsest level: CG on op op^dag y = b, x = op^dag y; stops a rhs
+// when ||b - op x|| <= tol ||b||.
+template <class T, class OpF, class OpDF>
+int cgne_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* p,
+               Cx<T>* q, double tol, int maxit, const KrylovState& k, const int* parent, OpF op,
+               OpDF opdag, int poll) {
+  start_solve(c, k, parent, nrhs);
+  launch_map_reduce<1>(OpInit<T>{x, r, nullptr, b, n, k, tol * tol, nullptr}, n, nrhs, 1, c.rs, c.st);
+  opdag(p, r, k.act);
+  launch_map_reduce<1>(OpAlphaFromNorm<T>{p, n, k}, n, nrhs, 1, c.rs, c.st);
+  int it = 0;
+  for (; it < maxit; ++it) {
+    op(q, p, k.act);
+    launch_map_reduce<1>(OpCGupd<T>{x, r, p, q, n, k}, n, nrhs, 1, c.rs, c.st);
+    opdag(q, r, k.act);
+    launch_map_reduce<1>(OpCGp<T>{p, q, n, k}, n, nrhs, 1, c.rs, c.st);
+    if ((it + 1) % poll == 0 && !any_active(c, k.act, nrhs)) { ++it; break; }
+  }
+  return it;
+}
+
+}  // namespace kdmg

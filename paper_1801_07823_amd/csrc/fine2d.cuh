@@ -1,0 +1,400 @@
+// Fine-level kernels for the 2D U(1) staggered operator in Kahler-Dirac block
+// layout.
+//
+// Layout.  The L_x x L_t lattice is cut into 2x2 Kahler-Dirac blocks anchored
+// at even coordinates (Sec. 2.1).  Block X = (X0, X1) has parity
+// p = (X0 + X1) & 1 and index b = X1 * (B_x/2) + X0/2 within its parity, so a
+// vector is [rhs][p][b][s] with s = (x0 & 1) + 2 (x1 & 1) the site inside the
+// block; each block's four complex values are contiguous (64 B in FP64, 32 B
+// in FP32) and consecutive threads read consecutive blocks.  The Schur space
+// of the solver is the p = 0 half.
+//
+// Links.  Per block 8 complex values with the staggered phase eta_mu(x), the
+// factor 1/2 of eq. "staggeredD" and the antiperiodic sign folded in
+// (U~_mu(x) = 1/2 eta_mu(x) bc_mu(x) U_mu(x)); eta_mu(x - mu) = eta_mu(x)
+// makes the backward hop -U~_mu(x - mu)^* psi(x - mu).  Entries 0..3 are the
+// intra-block links U~_0(s0), U~_1(s0), U~_1(s1), U~_0(s2) (the part of B);
+// entries 4..7 the forward inter-block links U~_0(s1), U~_0(s3), U~_1(s2),
+// U~_1(s3) (the part of C).
+//
+// Operators.  D = B + C with B = m + intra-block hops (Sec. 2.1).  In block
+// site order the even sites (eps = +1) are s0, s3 and the odd s1, s2, so
+// B = [[m, K], [-K^dag, m]] with K = [[a, c], [-d^*, -f^*]] in the links
+// (a, c, d, f) = entries 0..3, and
+//   B^-1 b = ( S_e^-1 (m b_e - K b_o),  S_o^-1 (m b_o + K^dag b_e) ),
+//   S_e = m^2 + K K^dag,  S_o = m^2 + K^dag K  (2x2 Hermitian positive).
+// B^-1 is recomputed from the four intra-block links in every kernel that
+// needs it instead of being stored.
+#pragma once
+#include "common.h"
+#include "blas.cuh"
+
+namespace kdmg {
+
+struct Geo2 {
+  int Lx, Lt;   // sites
+  int Bx, Bt;   // KD blocks
+  int hBx;      // Bx / 2
+  int Nb2;      // blocks per parity
+  long half;    // complex entries in one parity half (= 4 * Nb2)
+};
+
+__host__ __device__ __forceinline__ void blk_coords(const Geo2& g, int p, int b, int& X0, int& X1) {
+  X1 = b / g.hBx;
+  X0 = 2 * (b % g.hBx) + ((p + X1) & 1);
+}
+__host__ __device__ __forceinline__ int blk_index(const Geo2& g, int X0, int X1) {
+  return X1 * g.hBx + (X0 >> 1);
+}
+// chirality of site s in a block: 0 for eps=+1 (s0, s3), 1 for eps=-1 (s1, s2)
+__host__ __device__ __forceinline__ int chir2(int s) { return (s == 1 || s == 2) ? 1 : 0; }
+
+template <class R, class LT>
+__device__ __forceinline__ void load_intra(const Cx<LT>* L, Cx<R> k[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) k[i] = ld<R>(L[i]);
+}
+
+// out = B^-1 in for one block (links a, c, d, f = L[0..3])
+template <class R>
+__device__ __forceinline__ void binv_block(const Cx<R> L[4], R m, const Cx<R> in[4], Cx<R> out[4]) {
+  const Cx<R> K00 = L[0], K01 = L[1], K10 = -conj(L[2]), K11 = -conj(L[3]);
+  const R m2 = m * m;
+  const R se00 = m2 + norm2(K00) + norm2(K01);
+  const R se11 = m2 + norm2(K10) + norm2(K11);
+  const Cx<R> se01 = K00 * conj(K10) + K01 * conj(K11);
+  const R so00 = m2 + norm2(K00) + norm2(K10);
+  const R so11 = m2 + norm2(K01) + norm2(K11);
+  const Cx<R> so01 = conj(K00) * K01 + conj(K10) * K11;
+  const Cx<R> ye0 = m * in[0] - (K00 * in[1] + K01 * in[2]);
+  const Cx<R> ye1 = m * in[3] - (K10 * in[1] + K11 * in[2]);
+  const Cx<R> yo0 = m * in[1] + (conj(K00) * in[0] + conj(K10) * in[3]);
+  const Cx<R> yo1 = m * in[2] + (conj(K01) * in[0] + conj(K11) * in[3]);
+  const R de = R(1) / (se00 * se11 - norm2(se01));
+  const R dd = R(1) / (so00 * so11 - norm2(so01));
+  out[0] = de * (se11 * ye0 - se01 * ye1);
+  out[3] = de * (se00 * ye1 - conj(se01) * ye0);
+  out[1] = dd * (so11 * yo0 - so01 * yo1);
+  out[2] = dd * (so00 * yo1 - conj(so01) * yo0);
+}
+
+// out = B in for one block
+template <class R>
+__device__ __forceinline__ void b_block(const Cx<R> L[4], R m, const Cx<R> in[4], Cx<R> out[4]) {
+  out[0] = m * in[0] + L[0] * in[1] + L[1] * in[2];
+  out[1] = m * in[1] - conj(L[0]) * in[0] + L[2] * in[3];
+  out[2] = m * in[2] - conj(L[1]) * in[0] + L[3] * in[3];
+  out[3] = m * in[3] - conj(L[2]) * in[1] - conj(L[3]) * in[2];
+}
+
+// Neighbour blocks of (p, b): indices within parity 1-p.
+struct Nbr2 {
+  int xp, xm, tp, tm;  // X+0, X-0, X+1, X-1
+  int X0, X1;
+};
+__device__ __forceinline__ Nbr2 nbr2(const Geo2& g, int p, int b) {
+  Nbr2 n;
+  blk_coords(g, p, b, n.X0, n.X1);
+  const int x0p = n.X0 + 1 == g.Bx ? 0 : n.X0 + 1, x0m = n.X0 == 0 ? g.Bx - 1 : n.X0 - 1;
+  const int x1p = n.X1 + 1 == g.Bt ? 0 : n.X1 + 1, x1m = n.X1 == 0 ? g.Bt - 1 : n.X1 - 1;
+  n.xp = blk_index(g, x0p, n.X1);
+  n.xm = blk_index(g, x0m, n.X1);
+  n.tp = blk_index(g, n.X0, x1p);
+  n.tm = blk_index(g, n.X0, x1m);
+  return n;
+}
+
+// out = C in on block (p, b); `in` is the parity-(1-p) half of the source
+// (already offset to this rhs).  eps_in multiplies the source by eps(s).
+template <class R, class LT, class VT>
+__device__ __forceinline__ void hop_block(const Geo2& g, int p, int b, const Nbr2& n,
+                                          const Cx<LT>* links, const Cx<VT>* in, bool eps_in,
+                                          Cx<R> out[4]) {
+  const int q = 1 - p;
+  const Cx<LT>* Lo = links + ((size_t)p * g.Nb2 + b) * 8;
+  const Cx<LT>* Lxm = links + ((size_t)q * g.Nb2 + n.xm) * 8;
+  const Cx<LT>* Ltm = links + ((size_t)q * g.Nb2 + n.tm) * 8;
+  Cx<R> xp0 = ld<R>(in[4 * n.xp + 0]), xp2 = ld<R>(in[4 * n.xp + 2]);
+  Cx<R> xm1 = ld<R>(in[4 * n.xm + 1]), xm3 = ld<R>(in[4 * n.xm + 3]);
+  Cx<R> tp0 = ld<R>(in[4 * n.tp + 0]), tp1 = ld<R>(in[4 * n.tp + 1]);
+  Cx<R> tm2 = ld<R>(in[4 * n.tm + 2]), tm3 = ld<R>(in[4 * n.tm + 3]);
+  if (eps_in) { xp2 = -xp2; xm1 = -xm1; tp1 = -tp1; tm2 = -tm2; }
+  out[0] = -(cmul_conj(ld<R>(Lxm[4]), xm1) + cmul_conj(ld<R>(Ltm[6]), tm2));
+  out[1] = ld<R>(Lo[4]) * xp0 - cmul_conj(ld<R>(Ltm[7]), tm3);
+  out[2] = ld<R>(Lo[6]) * tp0 - cmul_conj(ld<R>(Lxm[5]), xm3);
+  out[3] = ld<R>(Lo[5]) * xp2 + ld<R>(Lo[7]) * tp1;
+}
+
+__device__ __forceinline__ float eps2(int s) { return (s == 1 || s == 2) ? -1.f : 1.f; }
+
+// ------------------------------------------------------------------ kernels
+// Grid: x over blocks of one parity, y = rhs, z = parity offset (p = p0 + z).
+// Every vector argument is the base of a [p][b][s] layout (parity-0 half
+// first); `s*` is its per-rhs stride in complex entries.  A vector that only
+// holds the even half (the Schur space) has stride `half` and is only ever
+// addressed at p = 0.
+
+// out = [add +] [eps] B^-1 in ; optionally out2 = B^-1 out
+template <class R, class LT, class VT>
+__global__ __launch_bounds__(256) void k_binv(Cx<VT>* out, long so, Cx<VT>* out2, long so2,
+                                               const Cx<VT>* in, long si, const Cx<VT>* add, long sa,
+                                               const Cx<LT>* links, Geo2 g, int p0, R m, int eps_out,
+                                               const int* act) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y, p = p0 + blockIdx.z;
+  if (b >= g.Nb2 || !is_active(act, r)) return;
+  Cx<R> L[4], v[4], w[4];
+  load_intra<R, LT>(links + ((size_t)p * g.Nb2 + b) * 8, L);
+  const long o = (long)p * g.half + 4L * b;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) v[s] = ld<R>(in[r * si + o + s]);
+  binv_block<R>(L, m, v, w);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (eps_out && (s == 1 || s == 2)) w[s] = -w[s];
+    if (add) w[s] += ld<R>(add[r * sa + o + s]);
+    out[r * so + o + s] = st<VT>(w[s]);
+  }
+  if (out2) {
+    binv_block<R>(L, m, w, v);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out2[r * so2 + o + s] = st<VT>(v[s]);
+  }
+}
+
+// mode 0: out = [add +] [c2 add2 +] sgn C in ;  mode 1: out = B^-1 (C in)
+template <class R, class LT, class VT>
+__global__ __launch_bounds__(256) void k_hop(Cx<VT>* out, long so, const Cx<VT>* in, long si,
+                                              const Cx<VT>* add, long sa, const Cx<VT>* add2,
+                                              long sa2, R c2, R sgn, const Cx<LT>* links, Geo2 g,
+                                              int p0, R m, int mode, int eps_in, const int* act) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y, p = p0 + blockIdx.z;
+  if (b >= g.Nb2 || !is_active(act, r)) return;
+  const Nbr2 n = nbr2(g, p, b);
+  const Cx<VT>* src = in + r * si + (long)(1 - p) * g.half;
+  Cx<R> h[4];
+  hop_block<R, LT, VT>(g, p, b, n, links, src, eps_in != 0, h);
+  const long o = (long)p * g.half + 4L * b;
+  if (mode == 1) {
+    Cx<R> L[4], w[4];
+    load_intra<R, LT>(links + ((size_t)p * g.Nb2 + b) * 8, L);
+    binv_block<R>(L, m, h, w);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[r * so + o + s] = st<VT>(w[s]);
+    return;
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    Cx<R> v = sgn * h[s];
+    if (add) v += ld<R>(add[r * sa + o + s]);
+    if (add2) v += c2 * ld<R>(add2[r * sa2 + o + s]);
+    out[r * so + o + s] = st<VT>(v);
+  }
+}
+
+// out = D in on full block-layout vectors; with `sub`, out = sub - D in.
+template <class R, class LT, class VT>
+__global__ __launch_bounds__(256) void k_dslash_blk(Cx<VT>* out, long so, const Cx<VT>* in, long si,
+                                                    const Cx<VT>* sub, long ss, const Cx<LT>* links,
+                                                    Geo2 g, R m, const int* act) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y, p = blockIdx.z;
+  if (b >= g.Nb2 || !is_active(act, r)) return;
+  const Nbr2 n = nbr2(g, p, b);
+  const Cx<VT>* src = in + r * si;
+  Cx<R> h[4], L[4], v[4], w[4];
+  hop_block<R, LT, VT>(g, p, b, n, links, src + (long)(1 - p) * g.half, false, h);
+  load_intra<R, LT>(links + ((size_t)p * g.Nb2 + b) * 8, L);
+  const long o = (long)p * g.half + 4L * b;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) v[s] = ld<R>(src[o + s]);
+  b_block<R>(L, m, v, w);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    Cx<R> d = w[s] + h[s];
+    if (sub) d = ld<R>(sub[r * ss + o + s]) - d;
+    out[r * so + o + s] = st<VT>(d);
+  }
+}
+
+// D in natural site order (one thread per site); links_nat[mu][site] folded.
+template <class R, class LT, class VT>
+__global__ __launch_bounds__(256) void k_dslash_nat(Cx<VT>* __restrict__ out, const Cx<VT>* __restrict__ in,
+                                                    const Cx<LT>* __restrict__ Ux,
+                                                    const Cx<LT>* __restrict__ Ut, int Lx, int Lt,
+                                                    long vol, R m) {
+  const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (x >= vol) return;
+  const int x0 = (int)(x % Lx), x1 = (int)(x / Lx);
+  const int x0p = x0 + 1 == Lx ? 0 : x0 + 1, x0m = x0 == 0 ? Lx - 1 : x0 - 1;
+  const int x1p = x1 + 1 == Lt ? 0 : x1 + 1, x1m = x1 == 0 ? Lt - 1 : x1 - 1;
+  const Cx<VT>* v = in + r * vol;
+  const long ixp = (long)x1 * Lx + x0p, ixm = (long)x1 * Lx + x0m;
+  const long itp = (long)x1p * Lx + x0, itm = (long)x1m * Lx + x0;
+  Cx<R> acc = m * ld<R>(v[x]);
+  acc += ld<R>(Ux[x]) * ld<R>(v[ixp]);
+  acc -= cmul_conj(ld<R>(Ux[ixm]), ld<R>(v[ixm]));
+  acc += ld<R>(Ut[x]) * ld<R>(v[itp]);
+  acc -= cmul_conj(ld<R>(Ut[itm]), ld<R>(v[itm]));
+  out[r * vol + x] = st<VT>(acc);
+}
+
+// gather / scatter between an external ordering and the block layout:
+// dst[r][i] = src[r][idx[i]]  (gather)   or  dst[r][idx[i]] = src[r][i]  (scatter)
+template <class TO, class TI>
+__global__ __launch_bounds__(256) void k_permute(Cx<TO>* dst, long sd, const Cx<TI>* src, long ss,
+                                                 const int* idx, long n, int scatter) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  if (scatter) dst[r * sd + idx[i]] = st<TO>(ld<double>(src[r * ss + i]));
+  else dst[r * sd + i] = st<TO>(ld<double>(src[r * ss + idx[i]]));
+}
+
+// --------------------------------------------------- level-1 transfer (2D)
+
+struct Agg2 {
+  int a0, a1;     // aggregate extent in KD blocks
+  int Ncx, Nct;   // coarse lattice
+  int nv;         // null vectors (coarse dofs = 2 nv)
+};
+
+// out[r][Z][c*nv+i] = sum_{x in Z, chir(x)=c} conj(P[x][i]) in[r][x]
+// in: full block-layout vector (even_only: parity-0 half only contributes).
+// Block of 2*nv*NPART threads; grid (nZ, nrhs).
+template <class R, class PT, class VI, class VO>
+__global__ __launch_bounds__(256) void k_restrict1(Cx<VO>* out, const Cx<VI>* in, long si,
+                                                   const Cx<PT>* P, Geo2 g, Agg2 a, int even_only,
+                                                   const int* act) {
+  const int Z = blockIdx.x, r = blockIdx.y;
+  if (!is_active(act, r)) return;
+  const int ndc = 2 * a.nv;
+  const int col = threadIdx.x % ndc, part = threadIdx.x / ndc, nparts = blockDim.x / ndc;
+  const int c = col / a.nv, i = col % a.nv;
+  const int Z0 = Z % a.Ncx, Z1 = Z / a.Ncx;
+  Cx<R> acc{0, 0};
+  const int nblk = a.a0 * a.a1;
+  for (int k = part; k < nblk; k += nparts) {
+    const int X0 = Z0 * a.a0 + k % a.a0, X1 = Z1 * a.a1 + k / a.a0;
+    const int p = (X0 + X1) & 1;
+    if (even_only && p) continue;
+    const int b = blk_index(g, X0, X1);
+    const long base = (long)p * g.half + 4L * b;
+    const int s0 = c ? 1 : 0, s1 = c ? 2 : 3;
+    cfma_conj(acc, ld<R>(P[(base + s0) * a.nv + i]), ld<R>(in[r * si + base + s0]));
+    cfma_conj(acc, ld<R>(P[(base + s1) * a.nv + i]), ld<R>(in[r * si + base + s1]));
+  }
+  __shared__ Cx<R> sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (part == 0) {
+    for (int q = 1; q < nparts; ++q) acc += sh[q * ndc + col];
+    out[((long)r * a.Ncx * a.Nct + Z) * ndc + col] = st<VO>(acc);
+  }
+}
+
+// out[r][x] = [add[r][x] +] sum_i P[x][i] in[r][Z(x)][c(x)*nv+i]
+// grid: (blocks of parity, nrhs, nparity); out/add full or half (single parity)
+template <class R, class PT, class VI, class VO>
+__global__ __launch_bounds__(256) void k_prolong1(Cx<VO>* out, long so, const Cx<VO>* add, long sa,
+                                                  const Cx<VI>* in, const Cx<PT>* P, Geo2 g, Agg2 a,
+                                                  const int* act) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y, p = blockIdx.z;
+  if (b >= g.Nb2 || !is_active(act, r)) return;
+  int X0, X1;
+  blk_coords(g, p, b, X0, X1);
+  const int Z = (X0 / a.a0) + a.Ncx * (X1 / a.a1);
+  const int ndc = 2 * a.nv;
+  const Cx<VI>* e = in + ((long)r * a.Ncx * a.Nct + Z) * ndc;
+  const long base = (long)p * g.half + 4L * b;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int c = chir2(s);
+    Cx<R> acc{0, 0};
+    const Cx<PT>* Px = P + (base + s) * a.nv;
+    for (int i = 0; i < a.nv; ++i) cfma(acc, ld<R>(Px[i]), ld<R>(e[c * a.nv + i]));
+    if (add) acc += ld<R>(add[r * sa + base + s]);
+    out[r * so + base + s] = st<VO>(acc);
+  }
+}
+
+// W[x][c'][j] = sum_{s' in block(x), chir(s')=c'} B^-1[x][s'] P[s'][j]   (FP64)
+// grid: (blocks, nv, 2 parities)
+template <class LT>
+__global__ __launch_bounds__(256) void k_galerkin_w1(c64* W, const c64* P, const Cx<LT>* links,
+                                                     Geo2 g, int nv, double m) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, p = blockIdx.z;
+  if (b >= g.Nb2) return;
+  c64 L[4], v[4], w[4];
+  load_intra<double, LT>(links + ((size_t)p * g.Nb2 + b) * 8, L);
+  const long base = (long)p * g.half + 4L * b;
+  for (int cp = 0; cp < 2; ++cp) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = chir2(s) == cp ? P[(base + s) * nv + j] : c64{0, 0};
+    binv_block<double>(L, m, v, w);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) W[((base + s) * 2 + cp) * nv + j] = w[s];
+  }
+}
+
+// A_hat = 1 + P^dag C W, level 1.  One workgroup per coarse site Z.
+// Output Yt[dir][Z][col][row] (column-major blocks), dir 0 self, 1/2 = +-x,
+// 3/4 = +-t.
+template <class LT>
+__global__ __launch_bounds__(1024) void k_galerkin1(c64* Yt, const c64* P, const c64* W,
+                                                    const Cx<LT>* links, Geo2 g, Agg2 a) {
+  const int Z = blockIdx.x;
+  const int nv = a.nv, ndc = 2 * nv;
+  const long nZ = (long)a.Ncx * a.Nct;
+  const int Z0 = Z % a.Ncx, Z1 = Z / a.Ncx;
+  for (int pair = threadIdx.x; pair < ndc * ndc; pair += blockDim.x) {
+    const int row = pair / ndc, col = pair % ndc;
+    const int c = row / nv, i = row % nv, cp = col / nv, j = col % nv;
+    c64 acc[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) acc[d] = c64{0, 0};
+    for (int k = 0; k < a.a0 * a.a1; ++k) {
+      const int X0 = Z0 * a.a0 + k % a.a0, X1 = Z1 * a.a1 + k / a.a0;
+      const int p = (X0 + X1) & 1, q = 1 - p;
+      const int b = blk_index(g, X0, X1);
+      const Nbr2 n = nbr2(g, p, b);
+      const Cx<LT>* Lb = links + ((size_t)p * g.Nb2 + b) * 8;
+      const Cx<LT>* Lxm = links + ((size_t)q * g.Nb2 + n.xm) * 8;
+      const Cx<LT>* Ltm = links + ((size_t)q * g.Nb2 + n.tm) * 8;
+      const long base = (long)p * g.half + 4L * b;
+      const int dxp = ((X0 + 1) % a.a0 == 0) ? 1 : 0, dxm = (X0 % a.a0 == 0) ? 2 : 0;
+      const int dtp = ((X1 + 1) % a.a1 == 0) ? 3 : 0, dtm = (X1 % a.a1 == 0) ? 4 : 0;
+      auto Wat = [&](int nb, int s) -> c64 {
+        return W[(((long)q * g.half + 4L * nb + s) * 2 + cp) * nv + j];
+      };
+      if (c == 0) {
+        // s0: bwd x -> (X-0, s1), bwd t -> (X-1, s2)
+        const c64 P0 = P[(base + 0) * nv + i];
+        cfma_conj(acc[dxm], P0, -(conj(ld<double>(Lxm[4])) * Wat(n.xm, 1)));
+        cfma_conj(acc[dtm], P0, -(conj(ld<double>(Ltm[6])) * Wat(n.tm, 2)));
+        // s3: fwd x -> (X+0, s2), fwd t -> (X+1, s1)
+        const c64 P3 = P[(base + 3) * nv + i];
+        cfma_conj(acc[dxp], P3, ld<double>(Lb[5]) * Wat(n.xp, 2));
+        cfma_conj(acc[dtp], P3, ld<double>(Lb[7]) * Wat(n.tp, 1));
+      } else {
+        // s1: fwd x -> (X+0, s0), bwd t -> (X-1, s3)
+        const c64 P1 = P[(base + 1) * nv + i];
+        cfma_conj(acc[dxp], P1, ld<double>(Lb[4]) * Wat(n.xp, 0));
+        cfma_conj(acc[dtm], P1, -(conj(ld<double>(Ltm[7])) * Wat(n.tm, 3)));
+        // s2: fwd t -> (X+1, s0), bwd x -> (X-0, s3)
+        const c64 P2 = P[(base + 2) * nv + i];
+        cfma_conj(acc[dtp], P2, ld<double>(Lb[6]) * Wat(n.tp, 0));
+        cfma_conj(acc[dxm], P2, -(conj(ld<double>(Lxm[5])) * Wat(n.xm, 3)));
+      }
+    }
+    if (row == col) acc[0].re += 1.0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) Yt[(((long)d * nZ + Z) * ndc + col) * ndc + row] = acc[d];
+  }
+}
+
+}  // namespace kdmg

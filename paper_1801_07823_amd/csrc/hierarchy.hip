@@ -1,0 +1,451 @@
+// Multigrid setup (Sec. 4 and Table 1, "setup" rows): near-null vectors by CG
+// on A A^dag, global modified Gram-Schmidt, chiral doubling with
+// block-orthonormalisation into P, Galerkin coarse operators A_hat = P^dag A P.
+#include <cstring>
+
+#include "algos.h"
+#include "api_guard.h"
+
+using namespace kdmg;
+
+namespace {
+
+struct Scalars1 {  // one device complex scalar for the global Gram-Schmidt
+  DevBuf d;
+  Scalars1() : d(sizeof(double) * 4) {}
+};
+
+// y *= 1/sqrt(s[0])
+struct OpScaleInvSqrt {
+  c64* y; long n; const double* s;
+  __device__ bool active(int) const { return true; }
+  __device__ void elem(int, long i) const { y[i] = (1.0 / sqrt(s[0])) * y[i]; }
+};
+
+// y = -y
+struct OpNeg {
+  c64* y; long n;
+  __device__ bool active(int) const { return true; }
+  __device__ void elem(int r, long i) const { y[r * n + i] = -y[r * n + i]; }
+};
+
+// x += e
+struct OpAdd {
+  c64* x; const c64* e; long n;
+  __device__ bool active(int) const { return true; }
+  __device__ void elem(int r, long i) const { x[r * n + i] += e[r * n + i]; }
+};
+
+// Modified Gram-Schmidt over whole vectors, in vector order (FP64).
+void global_mgs(const Ctx& c, c64* V, long n, int nv) {
+  Scalars1 s;
+  double* d = s.d.as<double>();
+  for (int i = 0; i < nv; ++i) {
+    c64* vi = V + (long)i * n;
+    for (int j = 0; j < i; ++j) {
+      const c64* vj = V + (long)j * n;
+      launch_map_reduce<2>(OpDot<double>{vj, vi, n, d, nullptr}, n, 1, 1, c.rs, c.st);
+      launch_map(OpAxpyDev<double>{vi, vj, n, d, 2, -1.0, nullptr}, n, 1, c.st);
+    }
+    launch_map_reduce<1>(OpNorm2<double>{vi, n, d + 2, nullptr}, n, 1, 1, c.rs, c.st);
+    launch_map(OpScaleInvSqrt{vi, n, d + 2}, n, 1, c.st);
+  }
+}
+
+void run_blockqr(const Ctx& c, c64* P, const c64* V, long n, const std::vector<int>& rows, int ngroups,
+                 int nrows, int nv) {
+  DevBuf drows(sizeof(int) * rows.size());
+  KDMG_HIP(hipMemcpyAsync(drows.p, rows.data(), drows.bytes, hipMemcpyHostToDevice, c.st));
+  const size_t smem = sizeof(c64) * (size_t)nrows * nv;
+  KDMG_CHECK(smem <= 65536, KDMG_EUNSUPPORTED, "aggregate too large for the block QR kernel");
+  int threads = ((nrows + 63) / 64) * 64;
+  if (threads > 256) threads = 256;
+  hipLaunchKernelGGL(k_blockqr, dim3(ngroups), dim3(threads), smem, c.st, P, V, n, drows.as<int>(),
+                     nrows, nv);
+  KDMG_LAUNCH_CHECK();
+  KDMG_HIP(hipStreamSynchronize(c.st));
+}
+
+void finish_coarse_level(const Ctx& c, CoarseLevel& L) {
+  const long nbytes = (long)L.ndir * L.nsites * L.ndc * L.ndc;
+  L.Yd64.alloc(sizeof(c64) * nbytes);
+  L.Yt32.alloc(sizeof(c32) * nbytes);
+  L.Yd32.alloc(sizeof(c32) * nbytes);
+  hipLaunchKernelGGL(k_dagger_build<double>, dim3(cdiv(nbytes, 256)), dim3(256), 0, c.st,
+                     L.Yd64.as<c64>(), L.Yt64.as<c64>(), L.nbr.as<int>(), L.nsites, L.ndc, L.ndir);
+  KDMG_LAUNCH_CHECK();
+  convert<float, double>(L.Yt32.as<c32>(), L.Yt64.as<c64>(), nbytes, 1, nullptr, c.st);
+  convert<float, double>(L.Yd32.as<c32>(), L.Yd64.as<c64>(), nbytes, 1, nullptr, c.st);
+}
+
+void make_nbr(CoarseLevel& L) {
+  const int nd = L.nd;
+  L.ndir = 2 * nd + 1;
+  L.nsites = 1;
+  for (int mu = 0; mu < nd; ++mu) L.nsites *= L.dims[mu];
+  L.h_nbr.assign((size_t)L.ndir * L.nsites, 0);
+  for (int X = 0; X < L.nsites; ++X) {
+    int co[4], rem = X;
+    for (int mu = 0; mu < nd; ++mu) { co[mu] = rem % L.dims[mu]; rem /= L.dims[mu]; }
+    L.h_nbr[X] = X;
+    for (int mu = 0; mu < nd; ++mu)
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        int cc[4];
+        std::memcpy(cc, co, sizeof(cc));
+        cc[mu] = (co[mu] + (sgn == 0 ? 1 : L.dims[mu] - 1)) % L.dims[mu];
+        int idx = 0, str = 1;
+        for (int nu = 0; nu < nd; ++nu) { idx += cc[nu] * str; str *= L.dims[nu]; }
+        L.h_nbr[(size_t)(1 + 2 * mu + sgn) * L.nsites + X] = idx;
+      }
+  }
+  L.nbr.alloc(sizeof(int) * L.h_nbr.size());
+  KDMG_HIP(hipMemcpy(L.nbr.p, L.h_nbr.data(), L.nbr.bytes, hipMemcpyHostToDevice));
+}
+
+// Relax the columns of V (nv vectors of length n) with CG on `normal`:
+// solve normal e = -normal V to tol (relative) or maxit iterations, V += e.
+template <class NormalF>
+void relax(const Ctx& c, c64* V, long n, int nv, double tol, int maxit, NormalF normal) {
+  DevBuf b(sizeof(c64) * n * nv), x(sizeof(c64) * n * nv), r(sizeof(c64) * n * nv),
+      p(sizeof(c64) * n * nv), q(sizeof(c64) * n * nv);
+  KrylovAlloc ka;
+  ka.init(nv);
+  normal(b.as<c64>(), V, (const int*)nullptr);
+  launch_map(OpNeg{b.as<c64>(), n}, n, nv, c.st);
+  cg_solve<double>(c, nv, n, b.as<c64>(), x.as<c64>(), r.as<c64>(), p.as<c64>(), q.as<c64>(), tol,
+                   maxit, ka.k, normal, 10);
+  launch_map(OpAdd{V, x.as<c64>(), n}, n, nv, c.st);
+  KDMG_HIP(hipStreamSynchronize(c.st));
+}
+
+void upload(const Ctx& c, DevBuf& dst, const double* host, size_t bytes) {
+  dst.alloc(bytes);
+  KDMG_HIP(hipMemcpyAsync(dst.p, host, bytes, hipMemcpyHostToDevice, c.st));
+}
+
+// fine lattice -> first coarse lattice (2D U(1))
+void build_level1(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int relaxed) {
+  const kdmg_lattice& lat = *h.lat;
+  const Geo2& g = lat.g;
+  const kdmg_level_params& lp = h.params.lvl[0];
+  const int nv = lp.nvec, a0 = lp.agg[0], a1 = lp.agg[1];
+  KDMG_CHECK(a0 >= 1 && a1 >= 1 && g.Bx % a0 == 0 && g.Bt % a1 == 0, KDMG_EINVAL,
+             "first aggregate must divide the KD-block lattice");
+  KDMG_CHECK(nv >= 1 && nv <= 2 * a0 * a1 && 2 * nv <= 64, KDMG_EINVAL,
+             "n_vec must not exceed the sites of one aggregate chirality (and 2 n_vec <= 64)");
+  Transfer& T = h.T[0];
+  T.k = 0;
+  T.nv = nv;
+  T.a2 = Agg2{a0, a1, g.Bx / a0, g.Bt / a1, nv};
+  const long f = 2 * g.half, V = lat.volume;
+  T.nfine = f;
+  const double m = h.mass;
+  // starting vectors: natural order -> block layout
+  DevBuf nat;
+  upload(c, nat, psi0, sizeof(c64) * V * nv);
+  DevBuf Vb(sizeof(c64) * f * nv);
+  launch_permute<double, double>(Vb.as<c64>(), f, nat.as<c64>(), V, lat.perm_full.as<int>(), V, 1, nv,
+                                 c.st);
+  const c64* L = lat.links64.as<c64>();
+  if (!relaxed) {
+    DevBuf u(sizeof(c64) * f * nv), t(sizeof(c64) * f * nv), t2(sizeof(c64) * f * nv);
+    auto normal = [&](c64* out, const c64* in, const int* act) {
+      fullAdag_apply<double>(u.as<c64>(), t2.as<c64>(), in, t.as<c64>(), L, g, m, act, nv, c.st);
+      launch_hop<double, double, double>(out, f, t2.as<c64>(), f, u.as<c64>(), f, nullptr, 0, 0.0, 1.0,
+                                         L, g, 0, 2, m, 0, 0, act, nv, c.st);
+    };
+    relax(c, Vb.as<c64>(), f, nv, h.params.setup_tol, h.params.setup_maxit, normal);
+  }
+  T.relaxed.alloc(Vb.bytes);
+  KDMG_HIP(hipMemcpyAsync(T.relaxed.p, Vb.p, Vb.bytes, hipMemcpyDeviceToDevice, c.st));
+  global_mgs(c, Vb.as<c64>(), f, nv);
+  // block QR per (aggregate, chirality)
+  const int nZ = T.a2.Ncx * T.a2.Nct, nrows = 2 * a0 * a1;
+  std::vector<int> rows((size_t)nZ * 2 * nrows);
+  for (int Z = 0; Z < nZ; ++Z) {
+    const int Z0 = Z % T.a2.Ncx, Z1 = Z / T.a2.Ncx;
+    for (int cc = 0; cc < 2; ++cc) {
+      int k = 0;
+      for (int kb = 0; kb < a0 * a1; ++kb) {
+        const int X0 = Z0 * a0 + kb % a0, X1 = Z1 * a1 + kb / a0;
+        const int p = (X0 + X1) & 1, b = blk_index(g, X0, X1);
+        for (int s = 0; s < 4; ++s)
+          if (chir2(s) == cc) rows[((size_t)Z * 2 + cc) * nrows + k++] = (int)(((long)p * g.Nb2 + b) * 4 + s);
+      }
+    }
+  }
+  T.P64.alloc(sizeof(c64) * f * nv);
+  run_blockqr(c, T.P64.as<c64>(), Vb.as<c64>(), f, rows, nZ * 2, nrows, nv);
+  // Galerkin: W = B^-1 P, then A_hat = 1 + P^dag C W
+  DevBuf W(sizeof(c64) * f * 2 * nv);
+  hipLaunchKernelGGL((k_galerkin_w1<double>), dim3(cdiv(g.Nb2, 256), nv, 2), dim3(256), 0, c.st,
+                     W.as<c64>(), T.P64.as<c64>(), L, g, nv, m);
+  KDMG_LAUNCH_CHECK();
+  CoarseLevel& C1 = h.L[1];
+  C1.nd = 2;
+  C1.dims[0] = T.a2.Ncx;
+  C1.dims[1] = T.a2.Nct;
+  C1.ndc = 2 * nv;
+  make_nbr(C1);
+  C1.Yt64.alloc(sizeof(c64) * (size_t)C1.ndir * C1.nsites * C1.ndc * C1.ndc);
+  const int thr = C1.ndc * C1.ndc > 1024 ? 1024 : C1.ndc * C1.ndc;
+  hipLaunchKernelGGL((k_galerkin1<double>), dim3(nZ), dim3(thr), 0, c.st, C1.Yt64.as<c64>(),
+                     T.P64.as<c64>(), W.as<c64>(), L, g, T.a2);
+  KDMG_LAUNCH_CHECK();
+  finish_coarse_level(c, C1);
+  T.P16.alloc(sizeof(c16) * f * nv);
+  convert<_Float16, double>(T.P16.as<c16>(), T.P64.as<c64>(), f * nv, 1, nullptr, c.st);
+  KDMG_HIP(hipStreamSynchronize(c.st));
+}
+
+// coarse level k -> k+1
+void build_coarse(kdmg_hierarchy& h, int k, const Ctx& c, const double* psi0, int relaxed) {
+  CoarseLevel& Lf = h.L[k];
+  const kdmg_level_params& lp = h.params.lvl[k];
+  const int nv = lp.nvec, nd = Lf.nd;
+  int nchild = 1;
+  CoarseLevel& Lc = h.L[k + 1];
+  Lc.nd = nd;
+  for (int mu = 0; mu < nd; ++mu) {
+    KDMG_CHECK(lp.agg[mu] >= 1 && Lf.dims[mu] % lp.agg[mu] == 0, KDMG_EINVAL,
+               "coarse aggregate must divide the coarse lattice");
+    Lc.dims[mu] = Lf.dims[mu] / lp.agg[mu];
+    nchild *= lp.agg[mu];
+  }
+  const int ndf = Lf.ndc, nvp = ndf / 2;
+  KDMG_CHECK(nv >= 1 && nv <= nchild * nvp && 2 * nv <= 32, KDMG_EINVAL,
+             "coarse n_vec must fit the aggregate and 2 n_vec <= 32");
+  Lc.ndc = 2 * nv;
+  make_nbr(Lc);
+  Transfer& T = h.T[k];
+  T.k = k;
+  T.nv = nv;
+  T.nchild = nchild;
+  T.nZ = Lc.nsites;
+  T.nsf = Lf.nsites;
+  T.ndf = ndf;
+  const long n = Lf.n();
+  T.nfine = n;
+  // children / parent / coarse direction of each hop
+  std::vector<int> children((size_t)T.nZ * nchild), parent(T.nsf), gdir((size_t)Lf.ndir * T.nsf);
+  std::vector<int> fill(T.nZ, 0);
+  for (int X = 0; X < T.nsf; ++X) {
+    int co[4], rem = X;
+    for (int mu = 0; mu < nd; ++mu) { co[mu] = rem % Lf.dims[mu]; rem /= Lf.dims[mu]; }
+    int Z = 0, str = 1;
+    for (int mu = 0; mu < nd; ++mu) { Z += (co[mu] / lp.agg[mu]) * str; str *= Lc.dims[mu]; }
+    parent[X] = Z;
+    // children in local lexicographic order (x fastest)
+    int loc = 0, lstr = 1;
+    for (int mu = 0; mu < nd; ++mu) { loc += (co[mu] % lp.agg[mu]) * lstr; lstr *= lp.agg[mu]; }
+    children[(size_t)Z * nchild + loc] = X;
+    fill[Z]++;
+    gdir[X] = 0;
+    for (int mu = 0; mu < nd; ++mu) {
+      gdir[(size_t)(1 + 2 * mu) * T.nsf + X] = ((co[mu] + 1) % lp.agg[mu] == 0) ? 1 + 2 * mu : 0;
+      gdir[(size_t)(2 + 2 * mu) * T.nsf + X] = (co[mu] % lp.agg[mu] == 0) ? 2 + 2 * mu : 0;
+    }
+  }
+  T.children.alloc(sizeof(int) * children.size());
+  T.parent.alloc(sizeof(int) * parent.size());
+  DevBuf dgdir(sizeof(int) * gdir.size());
+  KDMG_HIP(hipMemcpy(T.children.p, children.data(), T.children.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(T.parent.p, parent.data(), T.parent.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(dgdir.p, gdir.data(), dgdir.bytes, hipMemcpyHostToDevice));
+  DevBuf Vb;
+  upload(c, Vb, psi0, sizeof(c64) * n * nv);
+  if (!relaxed) {
+    DevBuf u(sizeof(c64) * n * nv);
+    auto normal = [&](c64* out, const c64* in, const int* act) {
+      coarse_apply<double, double>(Lf, true, u.as<c64>(), in, nullptr, 1.0, act, nv, c.st);
+      coarse_apply<double, double>(Lf, false, out, u.as<c64>(), nullptr, 1.0, act, nv, c.st);
+    };
+    relax(c, Vb.as<c64>(), n, nv, h.params.setup_tol, h.params.setup_maxit, normal);
+  }
+  T.relaxed.alloc(Vb.bytes);
+  KDMG_HIP(hipMemcpyAsync(T.relaxed.p, Vb.p, Vb.bytes, hipMemcpyDeviceToDevice, c.st));
+  global_mgs(c, Vb.as<c64>(), n, nv);
+  const int nrows = nchild * nvp;
+  std::vector<int> rows((size_t)T.nZ * 2 * nrows);
+  for (int Z = 0; Z < T.nZ; ++Z)
+    for (int cc = 0; cc < 2; ++cc) {
+      int kk = 0;
+      for (int ch = 0; ch < nchild; ++ch)
+        for (int ia = 0; ia < nvp; ++ia)
+          rows[((size_t)Z * 2 + cc) * nrows + kk++] = children[(size_t)Z * nchild + ch] * ndf + cc * nvp + ia;
+    }
+  T.P64.alloc(sizeof(c64) * n * nv);
+  run_blockqr(c, T.P64.as<c64>(), Vb.as<c64>(), n, rows, T.nZ * 2, nrows, nv);
+  Lc.Yt64.alloc(sizeof(c64) * (size_t)Lc.ndir * Lc.nsites * Lc.ndc * Lc.ndc);
+  const size_t smem = sizeof(c64) * (size_t)ndf * Lc.ndc;
+  KDMG_CHECK(smem <= 65536 && Lc.ndc * Lc.ndc <= 1024 && Lf.ndir <= 9, KDMG_EUNSUPPORTED,
+             "coarse Galerkin shape not supported");
+  hipLaunchKernelGGL(k_galerkin_c, dim3(T.nZ), dim3(Lc.ndc * Lc.ndc), smem, c.st, Lc.Yt64.as<c64>(),
+                     Lf.Yt64.as<c64>(), T.P64.as<c64>(), Lf.nbr.as<int>(), dgdir.as<int>(),
+                     T.children.as<int>(), nchild, T.nsf, ndf, T.nZ, nv, Lf.ndir);
+  KDMG_LAUNCH_CHECK();
+  finish_coarse_level(c, Lc);
+  T.P16.alloc(sizeof(c16) * n * nv);
+  convert<_Float16, double>(T.P16.as<c16>(), T.P64.as<c64>(), n * nv, 1, nullptr, c.st);
+  KDMG_HIP(hipStreamSynchronize(c.st));
+}
+
+}  // namespace
+
+kdmg_hierarchy::~kdmg_hierarchy() {
+  if (ws) kdmg::destroy_ws(ws);
+}
+
+extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass,
+                                            const kdmg_mg_params* params,
+                                            const double* const* psi0_host, int relaxed,
+                                            void* stream, kdmg_hierarchy** out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(lat && params && psi0_host && out, KDMG_EINVAL, "kdmg_hierarchy_build: null argument");
+  *out = nullptr;
+  KDMG_CHECK(params->nlevels >= 2 && params->nlevels <= 4, KDMG_EINVAL, "nlevels must be 2..4");
+  KDMG_CHECK(mass > 0.0, KDMG_EINVAL, "mass must be positive");
+  KDMG_CHECK(params->setup_maxit >= 0 && params->outer_restart >= 1 && params->outer_restart <= 64 &&
+                 params->inter_restart >= 1 && params->inter_restart <= 64,
+             KDMG_EINVAL, "bad solver parameters");
+  for (int k = 0; k < params->nlevels - 1; ++k)
+    KDMG_CHECK(psi0_host[k] != nullptr, KDMG_EINVAL, "missing starting vectors");
+  auto h = std::make_unique<kdmg_hierarchy>();
+  h->lat = lat;
+  h->mass = mass;
+  h->params = *params;
+  h->nlevels = params->nlevels;
+  h->L.resize(h->nlevels);
+  h->T.resize(h->nlevels - 1);
+  int nvmax = 1;
+  for (int k = 0; k < h->nlevels - 1; ++k) nvmax = std::max(nvmax, params->lvl[k].nvec);
+  CtxAlloc ca;
+  ca.init((hipStream_t)stream, nvmax * 2 + 8, nvmax);
+  build_level1(*h, ca.c, psi0_host[0], relaxed);
+  for (int k = 1; k < h->nlevels - 1; ++k) build_coarse(*h, k, ca.c, psi0_host[k], relaxed);
+  KDMG_HIP(hipStreamSynchronize((hipStream_t)stream));
+  *out = h.release();
+  KDMG_API_END
+}
+
+extern "C" void kdmg_hierarchy_destroy(kdmg_hierarchy* h) { delete h; }
+
+extern "C" kdmg_status kdmg_hierarchy_level_info(const kdmg_hierarchy* h, int level, int* dims_out,
+                                                 int* ndof_out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && level >= 1 && level < h->nlevels, KDMG_EINVAL, "bad level");
+  const CoarseLevel& L = h->L[level];
+  if (dims_out)
+    for (int mu = 0; mu < L.nd; ++mu) dims_out[mu] = L.dims[mu];
+  if (ndof_out) *ndof_out = L.ndc;
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_get_nullvecs(const kdmg_hierarchy* h, int k, double* host_out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && host_out && k >= 0 && k < h->nlevels - 1, KDMG_EINVAL, "bad level");
+  const Transfer& T = h->T[k];
+  const long n = T.nfine;
+  if (k == 0) {
+    const kdmg_lattice& lat = *h->lat;
+    const long V = lat.volume;
+    DevBuf nat(sizeof(c64) * V * T.nv);
+    launch_permute<double, double>(nat.as<c64>(), V, T.relaxed.as<c64>(), n, lat.perm_full.as<int>(), V,
+                                   0, T.nv, 0);
+    KDMG_HIP(hipMemcpy(host_out, nat.p, nat.bytes, hipMemcpyDeviceToHost));
+  } else {
+    KDMG_HIP(hipMemcpy(host_out, T.relaxed.p, T.relaxed.bytes, hipMemcpyDeviceToHost));
+  }
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_get_prolongator(const kdmg_hierarchy* h, int k, double* host_out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && host_out && k >= 0 && k < h->nlevels - 1, KDMG_EINVAL, "bad level");
+  const Transfer& T = h->T[k];
+  std::vector<c64> buf(T.P64.bytes / sizeof(c64));
+  KDMG_HIP(hipMemcpy(buf.data(), T.P64.p, T.P64.bytes, hipMemcpyDeviceToHost));
+  c64* o = reinterpret_cast<c64*>(host_out);
+  if (k == 0) {
+    const kdmg_lattice& lat = *h->lat;
+    for (long x = 0; x < lat.volume; ++x)
+      for (int i = 0; i < T.nv; ++i) o[x * T.nv + i] = buf[(size_t)lat.h_perm_full[x] * T.nv + i];
+  } else {
+    std::memcpy(o, buf.data(), T.P64.bytes);
+  }
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_get_coarse_op(const kdmg_hierarchy* h, int level, double* host_out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && host_out && level >= 1 && level < h->nlevels, KDMG_EINVAL, "bad level");
+  const CoarseLevel& L = h->L[level];
+  std::vector<c64> buf(L.Yt64.bytes / sizeof(c64));
+  KDMG_HIP(hipMemcpy(buf.data(), L.Yt64.p, L.Yt64.bytes, hipMemcpyDeviceToHost));
+  c64* o = reinterpret_cast<c64*>(host_out);
+  const long nd2 = (long)L.ndc * L.ndc;
+  for (long db = 0; db < (long)L.ndir * L.nsites; ++db)
+    for (int i = 0; i < L.ndc; ++i)
+      for (int j = 0; j < L.ndc; ++j) o[db * nd2 + (long)i * L.ndc + j] = buf[db * nd2 + (long)j * L.ndc + i];
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_coarse_apply(const kdmg_hierarchy* h, int level, int dagger, const void* in,
+                                         void* out, int nrhs, kdmg_prec prec, void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && in && out && in != out, KDMG_EINVAL, "kdmg_coarse_apply: bad pointers");
+  KDMG_CHECK(level >= 1 && level < h->nlevels && nrhs >= 1 && nrhs <= 65535, KDMG_EINVAL,
+             "kdmg_coarse_apply: bad level or nrhs");
+  const CoarseLevel& L = h->L[level];
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == KDMG_FP64)
+    coarse_apply<double, double>(L, dagger != 0, (c64*)out, (const c64*)in, nullptr, 1.0, nullptr, nrhs, st);
+  else
+    coarse_apply<float, float>(L, dagger != 0, (c32*)out, (const c32*)in, nullptr, 1.0, nullptr, nrhs, st);
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void* in, void* out, int nrhs,
+                                     void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && in && out && k >= 0 && k < h->nlevels - 1 && nrhs >= 1, KDMG_EINVAL,
+             "kdmg_restrict: bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  const Transfer& T = h->T[k];
+  if (k == 0) {
+    const kdmg_lattice& lat = *h->lat;
+    const long f = 2 * lat.g.half, V = lat.volume;
+    DevBuf a(sizeof(c64) * f * nrhs);
+    launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, V, lat.perm_full.as<int>(), V, 1,
+                                   nrhs, st);
+    transfer_restrict<double, double, double, double>(T, lat, nullptr, (c64*)out, a.as<c64>(), f, 0,
+                                                      nullptr, nrhs, st);
+    KDMG_HIP(hipStreamSynchronize(st));
+  } else {
+    transfer_restrict<double, double, double, double>(T, *h->lat, &h->L[k], (c64*)out, (const c64*)in,
+                                                      T.nfine, 0, nullptr, nrhs, st);
+  }
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* out, int nrhs,
+                                    void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && in && out && k >= 0 && k < h->nlevels - 1 && nrhs >= 1, KDMG_EINVAL,
+             "kdmg_prolong: bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  const Transfer& T = h->T[k];
+  if (k == 0) {
+    const kdmg_lattice& lat = *h->lat;
+    const long f = 2 * lat.g.half, V = lat.volume;
+    DevBuf a(sizeof(c64) * f * nrhs);
+    transfer_prolong<double, double, double, double>(T, lat, a.as<c64>(), f, nullptr, 0, (const c64*)in,
+                                                     2, nullptr, nrhs, st);
+    launch_permute<double, double>((c64*)out, V, a.as<c64>(), f, lat.perm_full.as<int>(), V, 0, nrhs, st);
+    KDMG_HIP(hipStreamSynchronize(st));
+  } else {
+    transfer_prolong<double, double, double, double>(T, *h->lat, (c64*)out, 0, nullptr, 0,
+                                                     (const c64*)in, 1, nullptr, nrhs, st);
+  }
+  KDMG_API_END
+}

@@ -1,0 +1,249 @@
+// Internal C++ objects behind the C-ABI handles, and the launchers shared by
+// the lattice, setup and solver translation units.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "blas.cuh"
+#include "fine2d.cuh"
+#include "coarse.cuh"
+
+namespace kdmg {
+
+enum class Prec { F64 = 0, F32 = 1 };
+
+}  // namespace kdmg
+
+// ------------------------------------------------------------------ lattice
+struct kdmg_lattice {
+  int nd = 0, nc = 0;
+  int dims[4] = {1, 1, 1, 1};
+  long volume = 0;
+  int antiperiodic = 1;
+  kdmg::Geo2 g{};
+  // folded links (1/2 eta bc U), block layout [2][Nb2][8]
+  kdmg::DevBuf links64, links16, links32;
+  // folded links in natural order, per direction [mu][site]
+  kdmg::DevBuf nat64, nat16;
+  // natural site -> block-layout index; even-block rank -> index in the even half
+  kdmg::DevBuf perm_full, perm_even;
+  std::vector<int> h_perm_full, h_perm_even;
+  size_t footprint() const {
+    return links64.bytes + links16.bytes + links32.bytes + nat64.bytes + nat16.bytes +
+           perm_full.bytes + perm_even.bytes;
+  }
+};
+
+namespace kdmg {
+
+// ------------------------------------------------------------------ launch helpers
+
+inline dim3 fine_grid(const Geo2& g, int nrhs, int npar) { return dim3(cdiv(g.Nb2, 256), nrhs, npar); }
+
+template <class R, class LT, class VT>
+void launch_binv(Cx<VT>* out, long so, Cx<VT>* out2, long so2, const Cx<VT>* in, long si,
+                 const Cx<VT>* add, long sa, const Cx<LT>* links, const Geo2& g, int p0, int npar,
+                 double m, int eps_out, const int* act, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_binv<R, LT, VT>), fine_grid(g, nrhs, npar), dim3(256), 0, st, out, so, out2,
+                     so2, in, si, add, sa, links, g, p0, (R)m, eps_out, act);
+  KDMG_LAUNCH_CHECK();
+}
+
+template <class R, class LT, class VT>
+void launch_hop(Cx<VT>* out, long so, const Cx<VT>* in, long si, const Cx<VT>* add, long sa,
+                const Cx<VT>* add2, long sa2, double c2, double sgn, const Cx<LT>* links,
+                const Geo2& g, int p0, int npar, double m, int mode, int eps_in, const int* act,
+                int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_hop<R, LT, VT>), fine_grid(g, nrhs, npar), dim3(256), 0, st, out, so, in, si,
+                     add, sa, add2, sa2, (R)c2, (R)sgn, links, g, p0, (R)m, mode, eps_in, act);
+  KDMG_LAUNCH_CHECK();
+}
+
+template <class R, class LT, class VT>
+void launch_dslash_blk(Cx<VT>* out, long so, const Cx<VT>* in, long si, const Cx<VT>* sub, long ss,
+                       const Cx<LT>* links, const Geo2& g, double m, const int* act, int nrhs,
+                       hipStream_t st) {
+  hipLaunchKernelGGL((k_dslash_blk<R, LT, VT>), fine_grid(g, nrhs, 2), dim3(256), 0, st, out, so, in,
+                     si, sub, ss, links, g, (R)m, act);
+  KDMG_LAUNCH_CHECK();
+}
+
+template <class TO, class TI>
+void launch_permute(Cx<TO>* dst, long sd, const Cx<TI>* src, long ss, const int* idx, long n,
+                    int scatter, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_permute<TO, TI>), dim3(cdiv(n, 256), nrhs), dim3(256), 0, st, dst, sd, src, ss,
+                     idx, n, scatter);
+  KDMG_LAUNCH_CHECK();
+}
+
+// Schur operator S = 1 - A_eo A_oe on even-half vectors:
+//   t = B_e^-1 v ; w = B_o^-1 C_oe t ; out = v - C_eo w            (resid == null)
+//                                       out = resid - v + C_eo w   (= resid - S v)
+// t and w are full-layout temporaries (>= nrhs * 2 * half entries).
+template <class R, class LT>
+void schur_apply(Cx<R>* out, const Cx<R>* v, const Cx<R>* resid, Cx<R>* t, Cx<R>* w,
+                 const Cx<LT>* links, const Geo2& g, double m, const int* act, int nrhs,
+                 hipStream_t st) {
+  const long h = g.half, f = 2 * g.half;
+  launch_binv<R, LT, R>(t, f, nullptr, 0, v, h, nullptr, 0, links, g, 0, 1, m, 0, act, nrhs, st);
+  launch_hop<R, LT, R>(w, f, t, f, nullptr, 0, nullptr, 0, 0.0, 1.0, links, g, 1, 1, m, 1, 0, act,
+                       nrhs, st);
+  if (!resid)
+    launch_hop<R, LT, R>(out, h, w, f, v, h, nullptr, 0, 0.0, -1.0, links, g, 0, 1, m, 0, 0, act,
+                         nrhs, st);
+  else
+    launch_hop<R, LT, R>(out, h, w, f, resid, h, v, h, -1.0, 1.0, links, g, 0, 1, m, 0, 0, act,
+                         nrhs, st);
+}
+
+// Full-lattice A = 1 + C B^-1:  t = B^-1 v ; out = v + C t
+template <class LT>
+void fullA_apply(c64* out, const c64* v, c64* t, const Cx<LT>* links, const Geo2& g, double m,
+                 const int* act, int nrhs, hipStream_t st) {
+  const long f = 2 * g.half;
+  launch_binv<double, LT, double>(t, f, nullptr, 0, v, f, nullptr, 0, links, g, 0, 2, m, 0, act,
+                                  nrhs, st);
+  launch_hop<double, LT, double>(out, f, t, f, v, f, nullptr, 0, 0.0, 1.0, links, g, 0, 2, m, 0, 0,
+                                 act, nrhs, st);
+}
+
+// Full-lattice A^dag = 1 + eps B^-1 C eps:  t = C (eps v) ; out = v + eps B^-1 t
+// (optionally out2 = B^-1 out, the first half of the next A apply)
+template <class LT>
+void fullAdag_apply(c64* out, c64* out2, const c64* v, c64* t, const Cx<LT>* links, const Geo2& g,
+                    double m, const int* act, int nrhs, hipStream_t st) {
+  const long f = 2 * g.half;
+  launch_hop<double, LT, double>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, links, g, 0, 2, m, 0,
+                                 1, act, nrhs, st);
+  launch_binv<double, LT, double>(out, f, out2, f, t, f, v, f, links, g, 0, 2, m, 1, act, nrhs, st);
+}
+
+}  // namespace kdmg
+
+namespace kdmg {
+
+// One coarse lattice (level >= 1): geometry and its block-stencil operator.
+struct CoarseLevel {
+  int nd = 0;
+  int dims[4] = {1, 1, 1, 1};
+  int nsites = 0, ndc = 0, ndir = 0;
+  DevBuf nbr;                    // int [ndir][nsites]
+  DevBuf Yt64, Yd64, Yt32, Yd32; // operator and adjoint, FP64 and FP32 copies
+  std::vector<int> h_nbr;
+  long n() const { return (long)nsites * ndc; }
+  size_t bytes() const { return nbr.bytes + Yt64.bytes + Yd64.bytes + Yt32.bytes + Yd32.bytes; }
+};
+
+// Transfer from level k to level k+1.
+struct Transfer {
+  int k = 0, nv = 0;
+  Agg2 a2{};                     // k == 0 (fine -> first coarse)
+  int nchild = 0, nZ = 0, nsf = 0, ndf = 0;  // k >= 1
+  DevBuf P64, P16;               // prolongator values [ndof_k][nv]
+  DevBuf children, parent;       // k >= 1: int [nZ][nchild], int [nsf]
+  DevBuf relaxed;                // relaxed null vectors, FP64, internal layout [nv][n_k]
+  long nfine = 0;                // entries per null vector (internal layout)
+  size_t bytes() const {
+    return P64.bytes + P16.bytes + children.bytes + parent.bytes + relaxed.bytes;
+  }
+};
+
+struct SolveWS;  // solver workspace (solver.hip)
+void destroy_ws(SolveWS*);
+
+}  // namespace kdmg
+
+struct kdmg_hierarchy {
+  const kdmg_lattice* lat = nullptr;
+  double mass = 0.0;
+  kdmg_mg_params params{};
+  int nlevels = 0;
+  std::vector<kdmg::Transfer> T;
+  std::vector<kdmg::CoarseLevel> L;   // index by level; L[0] unused
+  kdmg::SolveWS* ws = nullptr;
+  ~kdmg_hierarchy();
+  size_t bytes() const {
+    size_t b = 0;
+    for (auto& t : T) b += t.bytes();
+    for (auto& l : L) b += l.bytes();
+    return b;
+  }
+};
+
+namespace kdmg {
+
+// ------------------------------------------------------------ coarse launchers
+
+inline void capply_shape(int ndc, int nrhs, int& js, int& rpb) {
+  rpb = nrhs >= 8 ? 8 : nrhs;
+  if (ndc * rpb > 1024) rpb = 1024 / ndc;
+  if (rpb < 1) rpb = 1;
+  js = 256 / (ndc * rpb);
+  if (js < 1) js = 1;
+}
+
+template <class R, class OT>
+void coarse_apply(const CoarseLevel& L, bool dag, Cx<R>* out, const Cx<R>* in, const Cx<R>* add,
+                  double sgn, const int* act, int nrhs, hipStream_t st) {
+  const Cx<OT>* Y;
+  if (sizeof(OT) == 8) Y = (const Cx<OT>*)(dag ? L.Yd64.p : L.Yt64.p);
+  else Y = (const Cx<OT>*)(dag ? L.Yd32.p : L.Yt32.p);
+  int js, rpb;
+  capply_shape(L.ndc, nrhs, js, rpb);
+  const int threads = L.ndc * js * rpb;
+  dim3 grid(L.nsites, cdiv(nrhs, rpb));
+  hipLaunchKernelGGL((k_capply<R, OT, R, R>), grid, dim3(threads), threads * sizeof(Cx<R>), st, out,
+                     in, add, (R)sgn, Y, L.nbr.as<int>(), L.nsites, L.ndc, L.ndir, js, rpb, nrhs, act);
+  KDMG_LAUNCH_CHECK();
+}
+
+// restriction level k -> k+1 ; in: level-k vector (fine: block layout with
+// stride `si`, even_only selects the Schur half), out: level-(k+1) vector
+template <class R, class PT, class VI, class VO>
+void transfer_restrict(const Transfer& T, const kdmg_lattice& lat, const CoarseLevel* Lk,
+                       Cx<VO>* out, const Cx<VI>* in, long si, int even_only, const int* act,
+                       int nrhs, hipStream_t st) {
+  const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
+  if (T.k == 0) {
+    const int ndc = 2 * T.nv;
+    int parts = 256 / ndc;
+    if (parts < 1) parts = 1;
+    dim3 grid(T.a2.Ncx * T.a2.Nct, nrhs);
+    hipLaunchKernelGGL((k_restrict1<R, PT, VI, VO>), grid, dim3(ndc * parts), 0, st, out, in, si, P,
+                       lat.g, T.a2, even_only, act);
+  } else {
+    const int ndn = 2 * T.nv;
+    int parts = 256 / ndn;
+    if (parts < 1) parts = 1;
+    dim3 grid(T.nZ, nrhs);
+    hipLaunchKernelGGL((k_restrict_c<R, PT, VI, VO>), grid, dim3(ndn * parts), 0, st, out, in, P,
+                       T.children.as<int>(), T.nchild, T.nsf, T.ndf, T.nZ, T.nv, act);
+  }
+  KDMG_LAUNCH_CHECK();
+}
+
+// prolongation level k+1 -> k: out = [add +] P in (fine: npar parities from p=0)
+template <class R, class PT, class VI, class VO>
+void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, long so,
+                      const Cx<VO>* add, long sa, const Cx<VI>* in, int npar, const int* act,
+                      int nrhs, hipStream_t st) {
+  const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
+  if (T.k == 0) {
+    dim3 grid(cdiv(lat.g.Nb2, 256), nrhs, npar);
+    hipLaunchKernelGGL((k_prolong1<R, PT, VI, VO>), grid, dim3(256), 0, st, out, so, add, sa, in, P,
+                       lat.g, T.a2, act);
+  } else {
+    dim3 grid(cdiv((long)T.nsf * T.ndf, 256), nrhs);
+    hipLaunchKernelGGL((k_prolong_c<R, PT, VI, VO>), grid, dim3(256), 0, st, out, add, in, P,
+                       T.parent.as<int>(), T.nsf, T.ndf, T.nZ, T.nv, act);
+  }
+  KDMG_LAUNCH_CHECK();
+}
+
+template <class TO, class TI>
+void convert(Cx<TO>* y, const Cx<TI>* x, long n, int nrhs, const int* act, hipStream_t st) {
+  launch_map(OpCopy<TO, TI>{y, x, n, act}, n, nrhs, st);
+}
+
+}  // namespace kdmg

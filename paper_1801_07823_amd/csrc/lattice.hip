@@ -1,0 +1,257 @@
+// Lattice handle (gauge field upload, layouts) and the fine-level operator
+// entry points: D, A, A^dag, B^-1 and the Schur operator.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+#include "api_guard.h"
+
+using namespace kdmg;
+
+namespace kdmg {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+}  // namespace kdmg
+
+namespace {
+
+// Fold 1/2 eta_mu(x) bc_mu(x) into the links (2D, U(1)).
+void fold_links_2d(const kdmg_lattice& lat, const double* links, std::vector<c64>& nat) {
+  const int Lx = lat.dims[0], Lt = lat.dims[1];
+  const long V = lat.volume;
+  nat.assign(2 * V, c64{0, 0});
+  for (long x = 0; x < V; ++x) {
+    const int x0 = (int)(x % Lx), x1 = (int)(x / Lx);
+    const double eta1 = (x0 & 1) ? -1.0 : 1.0;
+    const double bc = (lat.antiperiodic && x1 == Lt - 1) ? -1.0 : 1.0;
+    const double* u0 = links + 2 * (0 * V + x);
+    const double* u1 = links + 2 * (1 * V + x);
+    nat[x] = c64{0.5 * u0[0], 0.5 * u0[1]};
+    nat[V + x] = c64{0.5 * eta1 * bc * u1[0], 0.5 * eta1 * bc * u1[1]};
+  }
+}
+
+}  // namespace
+
+extern "C" kdmg_status kdmg_init(int device) {
+  KDMG_API_BEGIN
+  int n = 0;
+  KDMG_HIP(hipGetDeviceCount(&n));
+  KDMG_CHECK(device >= 0 && device < n, KDMG_EINVAL, "kdmg_init: no such device");
+  KDMG_HIP(hipSetDevice(device));
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
+                                           const double* links_host, int antiperiodic_time,
+                                           kdmg_lattice** out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(out && dims && links_host, KDMG_EINVAL, "kdmg_lattice_create: null argument");
+  *out = nullptr;
+  if (!(nd == 2 && ncolor == 1))
+    throw Error(KDMG_EUNSUPPORTED, "kdmg_lattice_create: only nd=2 with ncolor=1 is built");
+  for (int mu = 0; mu < nd; ++mu)
+    KDMG_CHECK(dims[mu] >= 4 && dims[mu] % 4 == 0, KDMG_EINVAL,
+               "kdmg_lattice_create: extents must be positive multiples of 4");
+  auto lat = std::make_unique<kdmg_lattice>();
+  lat->nd = nd;
+  lat->nc = ncolor;
+  lat->volume = 1;
+  for (int mu = 0; mu < nd; ++mu) {
+    lat->dims[mu] = dims[mu];
+    lat->volume *= dims[mu];
+  }
+  lat->antiperiodic = antiperiodic_time ? 1 : 0;
+  Geo2& g = lat->g;
+  g.Lx = dims[0];
+  g.Lt = dims[1];
+  g.Bx = g.Lx / 2;
+  g.Bt = g.Lt / 2;
+  g.hBx = g.Bx / 2;
+  g.Nb2 = g.Bx * g.Bt / 2;
+  g.half = 4L * g.Nb2;
+  const long V = lat->volume;
+
+  std::vector<c64> nat;
+  fold_links_2d(*lat, links_host, nat);
+  std::vector<c64> blk(2L * g.Nb2 * 8);
+  lat->h_perm_full.assign(V, 0);
+  lat->h_perm_even.assign(V / 2, 0);
+  auto site = [&](int x0, int x1) { return (long)x1 * g.Lx + x0; };
+  for (int p = 0; p < 2; ++p)
+    for (int b = 0; b < g.Nb2; ++b) {
+      int X0, X1;
+      blk_coords(g, p, b, X0, X1);
+      const long s0 = site(2 * X0, 2 * X1), s1 = site(2 * X0 + 1, 2 * X1);
+      const long s2 = site(2 * X0, 2 * X1 + 1), s3 = site(2 * X0 + 1, 2 * X1 + 1);
+      c64* L = &blk[((long)p * g.Nb2 + b) * 8];
+      L[0] = nat[s0];          // U~_0(s0)
+      L[1] = nat[V + s0];      // U~_1(s0)
+      L[2] = nat[V + s1];      // U~_1(s1)
+      L[3] = nat[s2];          // U~_0(s2)
+      L[4] = nat[s1];          // U~_0(s1)  -> X+0
+      L[5] = nat[s3];          // U~_0(s3)  -> X+0
+      L[6] = nat[V + s2];      // U~_1(s2)  -> X+1
+      L[7] = nat[V + s3];      // U~_1(s3)  -> X+1
+      const long sites[4] = {s0, s1, s2, s3};
+      for (int s = 0; s < 4; ++s) lat->h_perm_full[sites[s]] = (int)(((long)p * g.Nb2 + b) * 4 + s);
+    }
+  long rank = 0;
+  for (long x = 0; x < V; ++x) {
+    const int x0 = (int)(x % g.Lx), x1 = (int)(x / g.Lx);
+    if ((((x0 >> 1) + (x1 >> 1)) & 1) == 0) lat->h_perm_even[rank++] = lat->h_perm_full[x];
+  }
+  KDMG_CHECK(rank == V / 2, KDMG_EINVAL, "even-block count mismatch");
+
+  lat->links64.alloc(blk.size() * sizeof(c64));
+  lat->links32.alloc(blk.size() * sizeof(c32));
+  lat->links16.alloc(blk.size() * sizeof(c16));
+  lat->nat64.alloc(nat.size() * sizeof(c64));
+  lat->nat16.alloc(nat.size() * sizeof(c16));
+  lat->perm_full.alloc(V * sizeof(int));
+  lat->perm_even.alloc(V / 2 * sizeof(int));
+  KDMG_HIP(hipMemcpy(lat->links64.p, blk.data(), lat->links64.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(lat->nat64.p, nat.data(), lat->nat64.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(lat->perm_full.p, lat->h_perm_full.data(), lat->perm_full.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(lat->perm_even.p, lat->h_perm_even.data(), lat->perm_even.bytes, hipMemcpyHostToDevice));
+  convert<_Float16, double>(lat->links16.as<c16>(), lat->links64.as<c64>(), (long)blk.size(), 1, nullptr, 0);
+  convert<float, double>(lat->links32.as<c32>(), lat->links64.as<c64>(), (long)blk.size(), 1, nullptr, 0);
+  convert<_Float16, double>(lat->nat16.as<c16>(), lat->nat64.as<c64>(), (long)nat.size(), 1, nullptr, 0);
+  KDMG_HIP(hipStreamSynchronize(0));
+  *out = lat.release();
+  KDMG_API_END
+}
+
+extern "C" void kdmg_lattice_destroy(kdmg_lattice* lat) { delete lat; }
+
+extern "C" kdmg_status kdmg_lattice_footprint(const kdmg_lattice* lat, size_t* bytes) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(lat && bytes, KDMG_EINVAL, "null argument");
+  *bytes = lat->footprint();
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const void* in, void* out,
+                                    int nrhs, kdmg_prec prec, void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(lat && in && out, KDMG_EINVAL, "kdmg_apply_D: null argument");
+  KDMG_CHECK(nrhs >= 1 && nrhs <= 65535, KDMG_EINVAL, "kdmg_apply_D: bad nrhs");
+  KDMG_CHECK(in != out, KDMG_EINVAL, "kdmg_apply_D: in and out must not alias");
+  hipStream_t st = (hipStream_t)stream;
+  const long V = lat->volume;
+  dim3 grid(cdiv(V, 256), nrhs);
+  if (prec == KDMG_FP64) {
+    const c64* U = lat->nat64.as<c64>();
+    hipLaunchKernelGGL((k_dslash_nat<double, double, double>), grid, dim3(256), 0, st, (c64*)out,
+                       (const c64*)in, U, U + V, lat->dims[0], lat->dims[1], V, mass);
+  } else if (prec == KDMG_MIXED) {
+    const c16* U = lat->nat16.as<c16>();
+    hipLaunchKernelGGL((k_dslash_nat<float, _Float16, float>), grid, dim3(256), 0, st, (c32*)out,
+                       (const c32*)in, U, U + V, lat->dims[0], lat->dims[1], V, (float)mass);
+  } else {
+    throw Error(KDMG_EINVAL, "kdmg_apply_D: bad precision");
+  }
+  KDMG_LAUNCH_CHECK();
+  KDMG_API_END
+}
+
+namespace {
+
+enum FineOp { OP_A, OP_ADAG, OP_BINV, OP_SCHUR };
+
+void fine_op_natural(const kdmg_lattice* lat, double mass, const void* in, void* out, int nrhs,
+                     FineOp op, hipStream_t st) {
+  KDMG_CHECK(lat && in && out, KDMG_EINVAL, "null argument");
+  KDMG_CHECK(nrhs >= 1 && nrhs <= 65535, KDMG_EINVAL, "bad nrhs");
+  const Geo2& g = lat->g;
+  const long f = 2 * g.half, V = lat->volume;
+  DevBuf a(sizeof(c64) * f * nrhs), b(sizeof(c64) * f * nrhs), t(sizeof(c64) * f * nrhs),
+      w(sizeof(c64) * f * nrhs);
+  const c64* L = lat->links64.as<c64>();
+  if (op == OP_SCHUR) {
+    launch_permute<double, double>(a.as<c64>(), g.half, (const c64*)in, V / 2,
+                                   lat->perm_even.as<int>(), V / 2, 1, nrhs, st);
+    schur_apply<double, double>(b.as<c64>(), a.as<c64>(), nullptr, t.as<c64>(), w.as<c64>(), L, g,
+                                mass, nullptr, nrhs, st);
+    launch_permute<double, double>((c64*)out, V / 2, b.as<c64>(), g.half, lat->perm_even.as<int>(),
+                                   V / 2, 0, nrhs, st);
+  } else {
+    launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, V, lat->perm_full.as<int>(), V, 1,
+                                   nrhs, st);
+    if (op == OP_A)
+      fullA_apply<double>(b.as<c64>(), a.as<c64>(), t.as<c64>(), L, g, mass, nullptr, nrhs, st);
+    else if (op == OP_ADAG)
+      fullAdag_apply<double>(b.as<c64>(), nullptr, a.as<c64>(), t.as<c64>(), L, g, mass, nullptr,
+                             nrhs, st);
+    else
+      launch_binv<double, double, double>(b.as<c64>(), f, nullptr, 0, a.as<c64>(), f, nullptr, 0, L,
+                                          g, 0, 2, mass, 0, nullptr, nrhs, st);
+    launch_permute<double, double>((c64*)out, V, b.as<c64>(), f, lat->perm_full.as<int>(), V, 0, nrhs,
+                                   st);
+  }
+  KDMG_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+extern "C" kdmg_status kdmg_apply_A(const kdmg_lattice* lat, double mass, const void* in, void* out,
+                                    int nrhs, int dagger, void* stream) {
+  KDMG_API_BEGIN
+  fine_op_natural(lat, mass, in, out, nrhs, dagger ? OP_ADAG : OP_A, (hipStream_t)stream);
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_apply_Binv(const kdmg_lattice* lat, double mass, const void* in,
+                                       void* out, int nrhs, void* stream) {
+  KDMG_API_BEGIN
+  fine_op_natural(lat, mass, in, out, nrhs, OP_BINV, (hipStream_t)stream);
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_apply_schur(const kdmg_lattice* lat, double mass, const void* in_even,
+                                        void* out_even, int nrhs, void* stream) {
+  KDMG_API_BEGIN
+  fine_op_natural(lat, mass, in_even, out_even, nrhs, OP_SCHUR, (hipStream_t)stream);
+  KDMG_API_END
+}
+
+extern "C" const char* kdmg_status_string(kdmg_status s) {
+  switch (s) {
+    case KDMG_OK: return "ok";
+    case KDMG_EINVAL: return "invalid argument";
+    case KDMG_ENOMEM: return "out of device memory";
+    case KDMG_EHIP: return "HIP runtime error";
+    case KDMG_ENOCONV: return "solver did not converge";
+    case KDMG_EBUSY: return "busy";
+    case KDMG_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* kdmg_last_error(void) { return kdmg::last_error(); }
+
+extern "C" void kdmg_default_params(kdmg_mg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nlevels = 3;
+  p->lvl[0].agg[0] = p->lvl[0].agg[1] = p->lvl[0].agg[2] = p->lvl[0].agg[3] = 4;
+  p->lvl[0].nvec = 8;
+  p->lvl[1].agg[0] = p->lvl[1].agg[1] = p->lvl[1].agg[2] = p->lvl[1].agg[3] = 2;
+  p->lvl[1].nvec = 12;
+  p->lvl[2] = p->lvl[1];
+  p->setup_tol = 1e-4;
+  p->setup_maxit = 250;
+  p->outer_restart = 32;
+  p->outer_maxit = 2000;
+  p->mr_its = 2;
+  p->mr_omega = 0.85;
+  p->inter_restart = 8;
+  p->inter_maxit = 16;
+  p->inter_tol = 0.2;
+  p->coarse_tol = 0.2;
+  p->coarse_maxit = 256;
+}

@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libkdmg (the C ABI declared in include/kdmg.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device vectors are torch tensors (complex128 or complex64, on the
+current HIP device); their data pointers and the current stream are passed
+through unchanged.  If the library is missing this module raises at import:
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("KDMG_LIB", os.path.join(HERE, "libkdmg.so"))
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libkdmg.so not built: run __graft_entry__.build() (or "
+                      "python paper_1801_07823_amd/build_lib.py) first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+KDMG_OK, KDMG_EINVAL, KDMG_ENOMEM, KDMG_EHIP, KDMG_ENOCONV, KDMG_EBUSY, KDMG_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+KDMG_FP64, KDMG_MIXED = 0, 1
+
+
+class kdmg_level_params(ctypes.Structure):
+    _fields_ = [("agg", ctypes.c_int * 4), ("nvec", ctypes.c_int)]
+
+
+class kdmg_mg_params(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int), ("lvl", kdmg_level_params * 3),
+                ("setup_tol", ctypes.c_double), ("setup_maxit", ctypes.c_int),
+                ("outer_restart", ctypes.c_int), ("outer_maxit", ctypes.c_int),
+                ("mr_its", ctypes.c_int), ("mr_omega", ctypes.c_double),
+                ("inter_restart", ctypes.c_int), ("inter_maxit", ctypes.c_int),
+                ("inter_tol", ctypes.c_double), ("coarse_tol", ctypes.c_double),
+                ("coarse_maxit", ctypes.c_int)]
+
+
+class kdmg_solve_info(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int), ("outer_its", ctypes.c_int),
+                ("fine_applies", ctypes.c_int), ("level_avg_its", ctypes.c_double * 3),
+                ("true_rel_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"converged": bool(self.converged), "outer_its": self.outer_its,
+                "fine_applies": self.fine_applies,
+                "level_avg_its": list(self.level_avg_its),
+                "true_rel_resid": self.true_rel_resid, "seconds": self.seconds}
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_S = ctypes.c_size_t
+
+_SIGS = {
+    "kdmg_default_params": (None, [ctypes.POINTER(kdmg_mg_params)]),
+    "kdmg_init": (_I, [_I]),
+    "kdmg_lattice_create": (_I, [_I, ctypes.POINTER(_I), _I, _P, _I, ctypes.POINTER(_P)]),
+    "kdmg_lattice_destroy": (None, [_P]),
+    "kdmg_lattice_footprint": (_I, [_P, ctypes.POINTER(_S)]),
+    "kdmg_apply_D": (_I, [_P, _D, _P, _P, _I, _I, _P]),
+    "kdmg_apply_A": (_I, [_P, _D, _P, _P, _I, _I, _P]),
+    "kdmg_apply_Binv": (_I, [_P, _D, _P, _P, _I, _P]),
+    "kdmg_apply_schur": (_I, [_P, _D, _P, _P, _I, _P]),
+    "kdmg_hierarchy_build": (_I, [_P, _D, ctypes.POINTER(kdmg_mg_params),
+                                  ctypes.POINTER(_P), _I, _P, ctypes.POINTER(_P)]),
+    "kdmg_hierarchy_destroy": (None, [_P]),
+    "kdmg_hierarchy_level_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "kdmg_hierarchy_get_nullvecs": (_I, [_P, _I, _P]),
+    "kdmg_hierarchy_get_prolongator": (_I, [_P, _I, _P]),
+    "kdmg_hierarchy_get_coarse_op": (_I, [_P, _I, _P]),
+    "kdmg_coarse_apply": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
+    "kdmg_restrict": (_I, [_P, _I, _P, _P, _I, _P]),
+    "kdmg_prolong": (_I, [_P, _I, _P, _P, _I, _P]),
+    "kdmg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(kdmg_solve_info), _P]),
+    "kdmg_hierarchy_footprint": (_I, [_P, _I, ctypes.POINTER(_S)]),
+    "kdmg_status_string": (ctypes.c_char_p, [_I]),
+    "kdmg_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = sorted(_SIGS)
+
+
+class KdmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (_lib.kdmg_status_string(status).decode(), status, msg))
+        self.status = status
+
+
+def _check(st):
+    if st != KDMG_OK:
+        raise KdmgError(st, (_lib.kdmg_last_error() or b"").decode())
+    return st
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_params():
+    p = kdmg_mg_params()
+    _lib.kdmg_default_params(ctypes.byref(p))
+    return p
+
+
+def make_params(levels, **kw):
+    """levels: [(agg_tuple, nvec), ...] per coarsening; kw overrides Table 1 values."""
+    p = default_params()
+    p.nlevels = len(levels) + 1
+    for k, (agg, nv) in enumerate(levels):
+        a = list(agg) + [1] * (4 - len(agg))
+        p.lvl[k].agg[:] = a
+        p.lvl[k].nvec = nv
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def kdmg_init(device=0):
+    _check(_lib.kdmg_init(device))
+
+
+class Lattice:
+    def __init__(self, dims, links, antiperiodic_time=True):
+        links = np.ascontiguousarray(links, dtype=np.complex128)
+        nd = len(dims)
+        nc = links.shape[-1]
+        self.dims = tuple(int(d) for d in dims)
+        self.ncolor = nc
+        self.volume = int(np.prod(dims))
+        arr = (_I * nd)(*self.dims)
+        h = _P()
+        _check(_lib.kdmg_lattice_create(nd, arr, nc, links.ctypes.data_as(_P),
+                                        1 if antiperiodic_time else 0, ctypes.byref(h)))
+        self.handle = h
+
+    def footprint(self):
+        b = _S()
+        _check(_lib.kdmg_lattice_footprint(self.handle, ctypes.byref(b)))
+        return b.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.kdmg_lattice_destroy(self.handle)
+            self.handle = None
+
+
+def kdmg_apply_D(lat, mass, inp, out, nrhs, prec=KDMG_FP64, stream=None):
+    _check(_lib.kdmg_apply_D(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, prec, _stream(stream)))
+
+
+def kdmg_apply_A(lat, mass, inp, out, nrhs, dagger=False, stream=None):
+    _check(_lib.kdmg_apply_A(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, 1 if dagger else 0,
+                             _stream(stream)))
+
+
+def kdmg_apply_Binv(lat, mass, inp, out, nrhs, stream=None):
+    _check(_lib.kdmg_apply_Binv(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+
+
+def kdmg_apply_schur(lat, mass, inp, out, nrhs, stream=None):
+    _check(_lib.kdmg_apply_schur(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+
+
+class Hierarchy:
+    def __init__(self, lat, mass, params, psi0, relaxed=False, stream=None):
+        """psi0: list of complex128 numpy arrays [nvec, ndof_k] per coarsening."""
+        self.lat = lat
+        self.params = params
+        self._psi0 = [np.ascontiguousarray(v, dtype=np.complex128) for v in psi0]
+        ptrs = (_P * len(self._psi0))(*[v.ctypes.data_as(_P) for v in self._psi0])
+        h = _P()
+        _check(_lib.kdmg_hierarchy_build(lat.handle, mass, ctypes.byref(params), ptrs,
+                                         1 if relaxed else 0, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.nlevels = params.nlevels
+
+    def level_info(self, level):
+        dims = (_I * 4)()
+        nd = _I()
+        _check(_lib.kdmg_hierarchy_level_info(self.handle, level, dims, ctypes.byref(nd)))
+        return tuple(dims[:len(self.lat.dims)]), nd.value
+
+    def ndof(self, level):
+        if level == 0:
+            return self.lat.volume * self.lat.ncolor
+        dims, nd = self.level_info(level)
+        return int(np.prod(dims)) * nd
+
+    def nullvecs(self, k):
+        nv = self.params.lvl[k].nvec
+        out = np.zeros((nv, self.ndof(k)), dtype=np.complex128)
+        _check(_lib.kdmg_hierarchy_get_nullvecs(self.handle, k, out.ctypes.data_as(_P)))
+        return out
+
+    def prolongator_values(self, k):
+        nv = self.params.lvl[k].nvec
+        out = np.zeros((self.ndof(k), nv), dtype=np.complex128)
+        _check(_lib.kdmg_hierarchy_get_prolongator(self.handle, k, out.ctypes.data_as(_P)))
+        return out
+
+    def coarse_op(self, level):
+        dims, nd = self.level_info(level)
+        ndir = 2 * len(dims) + 1
+        out = np.zeros((ndir, int(np.prod(dims)), nd, nd), dtype=np.complex128)
+        _check(_lib.kdmg_hierarchy_get_coarse_op(self.handle, level, out.ctypes.data_as(_P)))
+        return out
+
+    def footprint(self, nrhs=1):
+        b = _S()
+        _check(_lib.kdmg_hierarchy_footprint(self.handle, nrhs, ctypes.byref(b)))
+        return b.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.kdmg_hierarchy_destroy(self.handle)
+            self.handle = None
+
+
+def kdmg_coarse_apply(h, level, inp, out, nrhs, dagger=False, prec=KDMG_FP64, stream=None):
+    _check(_lib.kdmg_coarse_apply(h.handle, level, 1 if dagger else 0, _ptr(inp), _ptr(out), nrhs,
+                                  prec, _stream(stream)))
+
+
+def kdmg_restrict(h, k, inp, out, nrhs, stream=None):
+    _check(_lib.kdmg_restrict(h.handle, k, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+
+
+def kdmg_prolong(h, k, inp, out, nrhs, stream=None):
+    _check(_lib.kdmg_prolong(h.handle, k, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+
+
+def kdmg_solve(h, b, x, nrhs, tol=1e-10, prec=KDMG_FP64, stream=None, raise_on_noconv=True):
+    info = (kdmg_solve_info * nrhs)()
+    st = _lib.kdmg_solve(h.handle, _ptr(b), _ptr(x), nrhs, tol, prec, info, _stream(stream))
+    if st != KDMG_OK and (st != KDMG_ENOCONV or raise_on_noconv):
+        _check(st)
+    return [i.as_dict() for i in info], st

@@ -1,0 +1,317 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+identical seeded inputs.  Tolerances:
+  * FP64 kernels: relative max-norm error <= 1e-12 (rounding order only);
+  * FP16-link / FP32 kernels: ||err|| / ||in|| <= 3e-3 (an FP16 link carries a
+    relative rounding error <= 2^-11 ~ 4.9e-4 per component; an output site sums
+    up to 2d + 1 = 5 terms of magnitude <= |psi|/2, giving ~2e-3 worst case);
+  * solves: true residual <= 1e-10 and ||x - x_oracle|| / ||x_oracle|| <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+from oracle.staggered import Lattice as OLattice, dirac_matrix
+from oracle.kd import KDOperator
+from oracle.mg import MGParams, LevelParams, Hierarchy as OHierarchy, Solver as OSolver
+from oracle.exact import dense_solve
+from synth import u1_heatbath, gaussian_vectors, unit_gauge
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1801_07823_amd import kdmg
+    kdmg.kdmg_init(0)
+    return kdmg
+
+
+def dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+CASES = [((16, 16), 3.0, 0.1), ((24, 20), 6.0, 0.01), ((8, 12), 3.0, 0.5)]
+
+
+def field(dims, beta, seed=7, sweeps=30):
+    U, _ = u1_heatbath(dims, beta, sweeps, seed)
+    return U
+
+
+@pytest.mark.parametrize("dims,beta,m", CASES)
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_apply_D_fp64(K, dims, beta, m, nrhs):
+    U = field(dims, beta)
+    lat = K.Lattice(dims, U)
+    V = lat.volume
+    v = gaussian_vectors(nrhs, V, 11)
+    out = torch.empty((nrhs, V), dtype=torch.complex128, device="cuda")
+    K.kdmg_apply_D(lat, m, dev(v), out, nrhs)
+    torch.cuda.synchronize()
+    D = dirac_matrix(OLattice(dims), U, m)
+    ref = (D @ v.T).T
+    assert relerr(out.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("dims,beta,m", CASES[:2])
+def test_apply_D_mixed(K, dims, beta, m):
+    U = field(dims, beta)
+    lat = K.Lattice(dims, U)
+    V = lat.volume
+    nrhs = 4
+    v = gaussian_vectors(nrhs, V, 12)
+    out = torch.empty((nrhs, V), dtype=torch.complex64, device="cuda")
+    K.kdmg_apply_D(lat, m, dev(v, torch.complex64), out, nrhs, prec=K.KDMG_MIXED)
+    torch.cuda.synchronize()
+    ref = (dirac_matrix(OLattice(dims), U, m) @ v.T).T
+    err = np.linalg.norm(out.cpu().numpy().astype(np.complex128) - ref, axis=1)
+    assert np.all(err / np.linalg.norm(v, axis=1) < 3e-3)
+
+
+@pytest.mark.parametrize("dims,beta,m", CASES)
+def test_fine_operators_fp64(K, dims, beta, m):
+    U = field(dims, beta)
+    lat = K.Lattice(dims, U)
+    kd = KDOperator(OLattice(dims), U, m)
+    V = lat.volume
+    nrhs = 2
+    v = gaussian_vectors(nrhs, V, 13)
+    for fn, ref in ((lambda i, o: K.kdmg_apply_A(lat, m, i, o, nrhs), kd.A),
+                    (lambda i, o: K.kdmg_apply_A(lat, m, i, o, nrhs, dagger=True), kd.Adag),
+                    (lambda i, o: K.kdmg_apply_Binv(lat, m, i, o, nrhs), kd.Binv)):
+        out = torch.empty((nrhs, V), dtype=torch.complex128, device="cuda")
+        fn(dev(v), out)
+        torch.cuda.synchronize()
+        assert relerr(out.cpu().numpy(), (ref @ v.T).T) < 1e-12
+    ve = gaussian_vectors(nrhs, V // 2, 14)
+    out = torch.empty((nrhs, V // 2), dtype=torch.complex128, device="cuda")
+    K.kdmg_apply_schur(lat, m, dev(ve), out, nrhs)
+    torch.cuda.synchronize()
+    assert relerr(out.cpu().numpy(), (kd.S @ ve.T).T) < 1e-12
+
+
+def oracle_setup(dims, U, m, levels, seed):
+    olat = OLattice(dims)
+    params = MGParams(levels=[LevelParams(a, nv) for a, nv in levels])
+    psi0 = []
+    n = olat.ndof
+    ncs = None
+    for k, (agg, nv) in enumerate(levels):
+        psi0.append(gaussian_vectors(nv, n, seed, tag=1 + k))
+        if k == 0:
+            ncs = olat.volume // int(np.prod([2 * a for a in agg]))
+        else:
+            ncs = ncs // int(np.prod(agg))
+        n = ncs * 2 * nv
+    return OHierarchy(olat, U, m, params, psi0), psi0
+
+
+def gpu_params(K, levels):
+    return K.make_params(levels)
+
+
+def assemble(op, dims):
+    """GPU stencil blocks [dir][Z][i][j] -> dense matrix (coinciding neighbours add)."""
+    ndir, ns, nd, _ = op.shape
+    M = np.zeros((ns * nd, ns * nd), dtype=np.complex128)
+    L0, L1 = dims
+    for Z in range(ns):
+        z0, z1 = Z % L0, Z // L0
+        nbrs = [Z, (z0 + 1) % L0 + L0 * z1, (z0 - 1) % L0 + L0 * z1,
+                z0 + L0 * ((z1 + 1) % L1), z0 + L0 * ((z1 - 1) % L1)]
+        for d in range(ndir):
+            M[Z * nd:(Z + 1) * nd, nbrs[d] * nd:(nbrs[d] + 1) * nd] += op[d, Z]
+    return M
+
+
+def oracle_P_values(h, k):
+    P = h.P[k].tocsr()
+    ag = h.aggr[k]
+    nv = h.params.levels[k].nvec
+    rows = np.arange(P.shape[0])
+    out = np.zeros((P.shape[0], nv), dtype=np.complex128)
+    for i in range(nv):
+        cols = ag.agg_of_dof * 2 * nv + ag.chir_of_dof * nv + i
+        out[:, i] = np.asarray(P[rows, cols]).ravel()
+    return out
+
+
+H_CASES = [((16, 16), 3.0, 0.1, [((4, 4), 8)]),
+           ((32, 32), 6.0, 0.02, [((2, 2), 8), ((2, 2), 8)]),
+           ((24, 40), 3.0, 0.05, [((3, 5), 8)])]
+
+
+@pytest.mark.parametrize("dims,beta,m,levels", H_CASES)
+def test_hierarchy_from_relaxed_vectors(K, dims, beta, m, levels):
+    """Given the oracle's relaxed null vectors, the GPU's P and coarse operators
+    match the oracle's to rounding."""
+    U = field(dims, beta)
+    oh, _ = oracle_setup(dims, U, m, levels, 21)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), oh.nullvecs, relaxed=True)
+    for k in range(len(levels)):
+        Pg = gh.prolongator_values(k)
+        assert relerr(Pg, oracle_P_values(oh, k)) < 1e-11
+        dims_c, _ = gh.level_info(k + 1)
+        Ag = assemble(gh.coarse_op(k + 1), dims_c)
+        Ao = oh.ops[k + 1].toarray()
+        assert relerr(Ag, Ao) < 1e-11
+
+
+RELAX_CASES = [((16, 16), 3.0, 0.5, [((4, 4), 8)], 1e-9),
+               ((16, 16), 3.0, 0.1, [((4, 4), 8)], 1e-2),
+               ((32, 32), 6.0, 0.02, [((2, 2), 8), ((2, 2), 8)], 1e-2)]
+
+
+@pytest.mark.parametrize("dims,beta,m,levels,bound", RELAX_CASES)
+def test_hierarchy_relaxation_matches_oracle(K, dims, beta, m, levels, bound):
+    """GPU CG relaxation from the same Gaussian starts.  Both sides stop CG at
+    ||A A^dag psi|| <= 1e-4 ||A A^dag psi0|| (or 250 iterations); rounding-order
+    differences change the iterate by up to the tolerance-sized remainder, so
+    the vectors agree to 1e-9 where CG converges in few iterations (m = 0.5)
+    and to 1e-2 otherwise, and every GPU vector meets the stopping rule."""
+    U = field(dims, beta)
+    oh, psi0 = oracle_setup(dims, U, m, levels, 22)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), psi0)
+    v0 = gh.nullvecs(0)
+    assert np.linalg.norm(v0 - oh.nullvecs[0]) / np.linalg.norm(oh.nullvecs[0]) < bound
+    A = oh.kd.A
+    for v, s, its in zip(v0, psi0[0], oh.setup_its[0]):
+        nrm = lambda u: np.linalg.norm(A @ (A.conj().T @ u))
+        if its < 250:
+            assert nrm(v) <= 1.0001e-4 * nrm(s)
+
+
+@pytest.mark.parametrize("dims,beta,m,levels", H_CASES[1:2])
+def test_transfer_and_coarse_apply(K, dims, beta, m, levels):
+    U = field(dims, beta)
+    oh, _ = oracle_setup(dims, U, m, levels, 23)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), oh.nullvecs, relaxed=True)
+    nrhs = 3
+    for k in range(len(levels)):
+        nf = gh.ndof(k)
+        nc = gh.ndof(k + 1)
+        v = gaussian_vectors(nrhs, nf, 30 + k)
+        out = torch.empty((nrhs, nc), dtype=torch.complex128, device="cuda")
+        K.kdmg_restrict(gh, k, dev(v), out, nrhs)
+        torch.cuda.synchronize()
+        P = oh.P[k]
+        assert relerr(out.cpu().numpy(), (P.conj().T @ v.T).T) < 1e-12
+        e = gaussian_vectors(nrhs, nc, 40 + k)
+        outp = torch.empty((nrhs, nf), dtype=torch.complex128, device="cuda")
+        K.kdmg_prolong(gh, k, dev(e), outp, nrhs)
+        torch.cuda.synchronize()
+        assert relerr(outp.cpu().numpy(), (P @ e.T).T) < 1e-12
+    for level in (1, 2):
+        n = gh.ndof(level)
+        v = gaussian_vectors(nrhs, n, 50 + level)
+        A = oh.ops[level]
+        for dag, ref in ((False, A), (True, A.conj().T)):
+            out = torch.empty((nrhs, n), dtype=torch.complex128, device="cuda")
+            K.kdmg_coarse_apply(gh, level, dev(v), out, nrhs, dagger=dag)
+            torch.cuda.synchronize()
+            assert relerr(out.cpu().numpy(), (ref @ v.T).T) < 1e-12
+            out32 = torch.empty((nrhs, n), dtype=torch.complex64, device="cuda")
+            K.kdmg_coarse_apply(gh, level, dev(v, torch.complex64), out32, nrhs, dagger=dag,
+                                prec=K.KDMG_MIXED)
+            torch.cuda.synchronize()
+            r = (ref @ v.T).T
+            assert np.linalg.norm(out32.cpu().numpy() - r) / np.linalg.norm(r) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_two_level_solve_c1(K, prec):
+    """16^2, beta=3, m=0.1, 2 levels (4x4 KD-block aggregates, n_vec 8): the
+    small workload; dense LU is the exact answer."""
+    dims, beta, m = (16, 16), 3.0, 0.1
+    U = field(dims, beta, seed=101, sweeps=200)
+    levels = [((4, 4), 8)]
+    oh, psi0 = oracle_setup(dims, U, m, levels, 7)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), psi0)
+    b = gaussian_vectors(1, lat.volume, 55)
+    x = torch.empty((1, lat.volume), dtype=torch.complex128, device="cuda")
+    p = K.KDMG_FP64 if prec == "fp64" else K.KDMG_MIXED
+    info, _ = K.kdmg_solve(gh, dev(b), x, 1, 1e-10, prec=p)
+    xg = x.cpu().numpy()[0]
+    xd = dense_solve(OLattice(dims), U, m, b[0])
+    assert info[0]["converged"] and info[0]["true_rel_resid"] <= 1e-10
+    D = dirac_matrix(OLattice(dims), U, m)
+    assert np.linalg.norm(b[0] - D @ xg) / np.linalg.norm(b[0]) <= 1e-10
+    assert np.linalg.norm(xg - xd) / np.linalg.norm(xd) < 1e-8
+    xo, oinfo = OSolver(oh).solve(b[0], 1e-10)
+    if prec == "fp64":
+        assert abs(info[0]["outer_its"] - oinfo["outer_its"]) <= 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_three_level_multi_rhs_solve(K, prec):
+    dims, beta, m = (32, 32), 6.0, 0.02
+    U = field(dims, beta, seed=102, sweeps=100)
+    levels = [((2, 2), 8), ((2, 2), 8)]
+    oh, psi0 = oracle_setup(dims, U, m, levels, 8)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), psi0)
+    nrhs = 4
+    b = gaussian_vectors(nrhs, lat.volume, 56)
+    x = torch.empty((nrhs, lat.volume), dtype=torch.complex128, device="cuda")
+    p = K.KDMG_FP64 if prec == "fp64" else K.KDMG_MIXED
+    info, _ = K.kdmg_solve(gh, dev(b), x, nrhs, 1e-10, prec=p)
+    D = dirac_matrix(OLattice(dims), U, m)
+    xs = x.cpu().numpy()
+    for r in range(nrhs):
+        assert info[r]["converged"]
+        assert np.linalg.norm(b[r] - D @ xs[r]) / np.linalg.norm(b[r]) <= 1e-10
+        xd = dense_solve(OLattice(dims), U, m, b[r])
+        assert np.linalg.norm(xs[r] - xd) / np.linalg.norm(xd) < 1e-8
+    # each rhs alone gives the same answer as in the batch
+    x1 = torch.empty((1, lat.volume), dtype=torch.complex128, device="cuda")
+    info1, _ = K.kdmg_solve(gh, dev(b[2:3]), x1, 1, 1e-10, prec=p)
+    assert info1[0]["outer_its"] == info[2]["outer_its"]
+    assert np.linalg.norm(x1.cpu().numpy()[0] - xs[2]) / np.linalg.norm(xs[2]) < 1e-12
+
+
+def test_free_field_solve_matches_fft(K):
+    from oracle.exact import free_fft_solve
+    dims, m = (32, 32), 0.01
+    U = unit_gauge(dims)
+    levels = [((4, 4), 8)]
+    oh, psi0 = oracle_setup(dims, U, m, levels, 9)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), psi0)
+    b = gaussian_vectors(1, lat.volume, 57)
+    x = torch.empty((1, lat.volume), dtype=torch.complex128, device="cuda")
+    info, _ = K.kdmg_solve(gh, dev(b), x, 1, 1e-10)
+    xf = free_fft_solve(OLattice(dims), m, b[0])
+    assert np.linalg.norm(x.cpu().numpy()[0] - xf) / np.linalg.norm(xf) < 1e-8
+
+
+def test_errors_are_reported(K):
+    dims = (16, 16)
+    U = field(dims, 3.0)
+    with pytest.raises(K.KdmgError) as e:
+        K.Lattice((10, 16), unit_gauge((10, 16)))
+    assert e.value.status == K.KDMG_EINVAL
+    lat = K.Lattice(dims, U)
+    bad = K.make_params([((3, 3), 8)])  # 3 does not divide the 8x8 block lattice
+    with pytest.raises(K.KdmgError) as e:
+        K.Hierarchy(lat, 0.1, bad, [gaussian_vectors(8, 256, 1)])
+    assert e.value.status == K.KDMG_EINVAL
+    # iteration cap forced from the host: ENOCONV with the best iterate returned
+    levels = [((4, 4), 8)]
+    p = K.make_params(levels, outer_maxit=1)
+    h = K.Hierarchy(lat, 0.1, p, [gaussian_vectors(8, 256, 2, tag=1)])
+    b = gaussian_vectors(1, 256, 3)
+    x = torch.empty((1, 256), dtype=torch.complex128, device="cuda")
+    info, st = K.kdmg_solve(h, dev(b), x, 1, 1e-10, raise_on_noconv=False)
+    assert st == K.KDMG_ENOCONV and not info[0]["converged"]
+    assert info[0]["true_rel_resid"] < 1.0
