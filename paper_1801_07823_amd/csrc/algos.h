@@ -3,9 +3,33 @@
 // out = resid - op(in) when `resid` is non-null, for the rhs whose flag in
 // `act` is set.
 #pragma once
+#include <cstdlib>
+#include <vector>
+
 #include "krylov.h"
 
 namespace kdmg {
+
+// KDMG_TRACE=1 prints the outer solver's per-rhs relative residual after every
+// iteration (diagnostics; one extra device-to-host copy per iteration).
+inline bool trace_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("KDMG_TRACE");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+inline void trace_residuals(const Ctx& c, const KrylovState& k, int nrhs, int its, double tol) {
+  std::vector<double> sc((size_t)nrhs * S_COUNT);
+  KDMG_HIP(hipMemcpyAsync(sc.data(), k.sc, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c.st));
+  KDMG_HIP(hipStreamSynchronize(c.st));
+  std::fprintf(stderr, "[kdmg] it %3d rel.res:", its);
+  for (int r = 0; r < nrhs; ++r)
+    std::fprintf(stderr, " %.2e", tol * std::sqrt(sc[(size_t)r * S_COUNT + S_RR] /
+                                                  sc[(size_t)r * S_COUNT + S_TARGET]));
+  std::fprintf(stderr, "\n");
+}
 
 // Device allocations for one Krylov state of `nrhs` right-hand sides.
 struct KrylovAlloc {
@@ -87,7 +111,7 @@ void mr_smooth(const Ctx& c, int nrhs, long n, Cx<T>* x, Cx<T>* r, Cx<T>* q, int
 template <class T, class OpF, class PrecF>
 int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* Zb,
               Cx<T>* Wb, int restart, int maxit, double tol, const double* ext,
-              const KrylovState& k, const int* parent, OpF op, PrecF prec) {
+              const KrylovState& k, const int* parent, OpF op, PrecF prec, bool trace = false) {
   start_solve(c, k, parent, nrhs);
   launch_map_reduce<1>(OpInit<T>{x, r, nullptr, b, n, k, tol * tol, ext}, n, nrhs, 1, c.rs, c.st);
   const long vs = (long)nrhs * n;
@@ -107,6 +131,7 @@ int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r
       launch_map_reduce<3>(OpGCRred<T>{w, r, n, k}, n, nrhs, 1, c.rs, c.st);
       launch_map_reduce<1>(OpGCRupd<T>{x, r, w, z, n, k}, n, nrhs, 1, c.rs, c.st);
       ++its;
+      if (trace) trace_residuals(c, k, nrhs, its, tol);
       if (!any_active(c, k.act, nrhs)) return its;
     }
     if (its >= maxit) break;

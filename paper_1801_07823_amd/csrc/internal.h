@@ -1,6 +1,7 @@
 // Internal C++ objects behind the C-ABI handles, and the launchers shared by
 // the lattice, setup and solver translation units.
 #pragma once
+#include <cstdlib>
 #include <memory>
 #include <vector>
 
@@ -176,6 +177,16 @@ namespace kdmg {
 // ------------------------------------------------------------ coarse launchers
 
 inline void capply_shape(int ndc, int nrhs, int& js, int& rpb) {
+  static const int force = [] {
+    const char* e = std::getenv("KDMG_CAPPLY_JS1");
+    return e ? std::atoi(e) : 0;
+  }();
+  if (force) {
+    rpb = nrhs >= 8 ? 8 : nrhs;
+    if (ndc * rpb > 1024) rpb = 1024 / ndc;
+    js = 1;
+    return;
+  }
   rpb = nrhs >= 8 ? 8 : nrhs;
   if (ndc * rpb > 1024) rpb = 1024 / ndc;
   if (rpb < 1) rpb = 1;
