@@ -197,6 +197,12 @@ kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* o
 kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int nrhs, double tol,
                        kdmg_prec prec, kdmg_solve_info* info_host, void* stream);
 
+/* Times every candidate launch shape of the coarse stencil kernels on this
+   hierarchy's operators for `nrhs` right-hand sides at precision `prec` and
+   keeps the fastest per level (kdmg_solve does this on its first call for a
+   given nrhs unless KDMG_AUTOTUNE=0).  Synchronises `stream`. */
+kdmg_status kdmg_hierarchy_autotune(kdmg_hierarchy* h, int nrhs, kdmg_prec prec, void* stream);
+
 /* Device bytes held by the hierarchy including its solve workspace for
    `nrhs` right-hand sides (admission control). */
 kdmg_status kdmg_hierarchy_footprint(const kdmg_hierarchy* h, int nrhs, size_t* bytes);

@@ -1,0 +1,660 @@
+// Coarse stencil apply and the fused coarsest-level CGNE, LDS-staged, with
+// two compute cores:
+//   * MFMA core (>= 16 rhs): the per-site product out(X) = sum_dir Y_dir(X)
+//     V(nbr(X, dir)) is a complex (ndc x K) . (K x RT) GEMM, K = ndir*ndc.
+//     Complex arithmetic is split into four real products
+//       Re C += Yr Vr - Yi Vi,   Im C += Yr Vi + Yi Vr,
+//     each a v_mfma_{f32,f64}_16x16x4 on 16x16 output tiles; one wavefront
+//     owns one (16 dofs x 16 rhs) tile and runs two independent accumulator
+//     sets over even/odd k-chunks to keep the matrix pipe busy;
+//   * SIMT core (< 16 rhs): each thread accumulates a TI x TR register tile,
+//     with the (dir, j) loop split KS ways for few rhs.
+// Both read the site's stencil blocks and the neighbour panel from LDS: the
+// workgroup first copies Y_dir(X) (column-major, [dir][j][i]) and
+// v[r][nbr(X,dir)][j] for its rhs tile with coalesced loads.
+//
+// Fused CGNE (Sec. 4, Table 1: CG on A A^dag, x = A^dag y, on the coarsest
+// level).  One iteration is two kernels:
+//   A_k: alpha = rr_k / ||p||^2 ; q = A p ; x += alpha p ; r -= alpha q
+//   B_k: beta = ||r||^2 / rr_k (stop the rhs once ||r|| <= tol ||b||) ;
+//        p = A^dag r + beta p
+// Every workgroup writes one partial sum per (site, rhs); each workgroup of
+// the next kernel adds up all partials of its rhs in the same fixed order, so
+// all of them obtain bit-identical scalars with no atomics and no device-scope
+// fences.  Per-rhs state (rr, active flag) is double-buffered by iteration
+// parity because workgroup 0 updates it while other workgroups of the same
+// kernel still read the previous values.
+#pragma once
+#include "common.h"
+#include "blas.cuh"
+
+namespace kdmg {
+
+// ------------------------------------------------------------------ MFMA traits
+
+template <class R>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element v of lane l holds row (l / 16) + 4 v, column l % 16
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element v of lane l holds row 4 (l / 16) + v, column l % 16
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+// ------------------------------------------------------------------ launch shape
+
+struct TileShape {
+  int core = 0;  // 0 SIMT, 1 MFMA
+  int RT = 1;    // rhs per workgroup
+  int TI = 1;    // SIMT: dofs per thread
+  int TR = 1;    // SIMT: rhs per thread
+  int KS = 1;    // SIMT: split of the (dir, j) loop
+  int MT = 1;    // MFMA: 16-row tiles
+  int NT = 1;    // MFMA: 16-rhs tiles
+  int ylds = 1;  // MFMA: stencil blocks staged in LDS (1) or read from global with prefetch (0)
+  int threads = 0;
+  size_t smem = 0;
+  int nslots() const { return core ? MT * 4 : 0; }
+};
+
+struct LdsLayout {
+  size_t ys, vs, red, S, sc, live, O, total;
+};
+
+// panel row stride (complex entries): one pad entry keeps the rhs-strided LDS
+// stores of the dof-fastest gather off a single bank
+__host__ __device__ __forceinline__ int panel_stride(int RT) { return RT + 1; }
+
+inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz) {
+  LdsLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (bytes + 15) & ~size_t(15);
+    return at;
+  };
+  L.ys = take(s.core && s.ylds ? (size_t)ndir * ndc * ndc * esz : 0);  // else blocks read from global
+  L.vs = take((size_t)ndir * ndc * panel_stride(s.RT) * esz);
+  int nib = s.core ? 0 : ndc / s.TI, nrb = s.core ? 0 : s.RT / s.TR;
+  L.red = take(s.core ? 0 : (size_t)(s.KS - 1) * nib * nrb * s.TI * s.TR * esz);
+  const int nsl = s.core ? s.MT * 4 : nib;
+  L.S = take((size_t)nsl * s.RT * sizeof(double));
+  L.sc = take((size_t)(2 * s.RT + 1024) * sizeof(double));
+  L.live = take((size_t)s.RT * sizeof(int));
+  L.O = take((size_t)s.RT * ndc * esz);
+  L.total = o;
+  return L;
+}
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+inline TileShape choose_tile(int ndc, int nrhs, int ndir, size_t esz) {
+  TileShape s;
+  if (nrhs >= 16) {
+    s.core = 1;
+    s.MT = (ndc + 15) / 16;
+    s.NT = nrhs >= 32 ? 2 : 1;
+    s.RT = 16 * s.NT;
+    while (s.NT > 1 && lds_layout(s, ndc, ndir, esz).total > LDS_LIMIT) {
+      s.NT /= 2;
+      s.RT = 16 * s.NT;
+    }
+    s.threads = 64 * s.MT * s.NT;
+    if (s.threads < 512) s.threads = 512;
+    s.smem = lds_layout(s, ndc, ndir, esz).total;
+    if (s.smem <= LDS_LIMIT && s.threads <= 1024) return s;
+    s = TileShape();
+  }
+  s.core = 0;
+  if (nrhs >= 4) {
+    s.TI = (ndc % 2 == 0) ? 2 : 1;
+    s.TR = 1;
+    s.RT = nrhs >= 16 ? 16 : nrhs;
+  } else {
+    s.TI = 1;
+    s.TR = 1;
+    s.RT = nrhs;
+  }
+  auto tiles = [&] { return (ndc / s.TI) * (s.RT / s.TR); };
+  while (s.RT > 1 && (tiles() > 256 || lds_layout(s, ndc, ndir, esz).total > LDS_LIMIT)) s.RT /= 2;
+  s.KS = 256 / tiles();
+  if (s.KS < 1) s.KS = 1;
+  if (s.KS > 16) s.KS = 16;
+  while (s.KS > 1 && lds_layout(s, ndc, ndir, esz).total > LDS_LIMIT) --s.KS;
+  s.threads = tiles() * s.KS;
+  s.threads = ((s.threads + 63) / 64) * 64;
+  if (s.threads < 64) s.threads = 64;
+  s.smem = lds_layout(s, ndc, ndir, esz).total;
+  return s;
+}
+
+// ------------------------------------------------------------------ staging
+
+constexpr int STAGE_UNROLL = 16;
+
+// Ys[(d*ndc + j)*ndc + i] = Y_dir(X)[i][j]  (the column-major block, contiguous per dir).
+// Loads are batched STAGE_UNROLL deep so many are in flight per thread.
+template <class R, class OT>
+__device__ __forceinline__ void stage_blocks(Cx<R>* Ys, const Cx<OT>* __restrict__ Yt, int X, int nsites,
+                                             int ndc, int ndir) {
+  const int per = ndc * ndc, tot = ndir * per;
+  const int step = blockDim.x * STAGE_UNROLL;
+  for (int base = threadIdx.x; base < tot; base += step) {
+    Cx<R> tmp[STAGE_UNROLL];
+#pragma unroll
+    for (int u = 0; u < STAGE_UNROLL; ++u) {
+      const int e = base + u * blockDim.x;
+      tmp[u] = Cx<R>{0, 0};
+      if (e < tot) {
+        const int d = e / per, q = e - d * per;
+        tmp[u] = ld<R>(Yt[((long)d * nsites + X) * per + q]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_UNROLL; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < tot) Ys[e] = tmp[u];
+    }
+  }
+}
+
+// Vs[(d*ndc + j)*RTP + r] = v[r0 + r][nbr(X, d)][j] (RTP = RT + 1); rhs past
+// nrhs read as 0.  Threads walk j fastest so each (rhs, dir) row of ndc
+// entries is one contiguous global segment.
+template <class R, class VI>
+__device__ __forceinline__ void stage_panel(Cx<R>* Vs, const Cx<VI>* __restrict__ v, const int* nbr, int X,
+                                            int nsites, int ndc, int ndir, int r0, int RT, int nrhs) {
+  const int tot = ndir * ndc * RT, RTP = panel_stride(RT);
+  const int step = blockDim.x * STAGE_UNROLL;
+  for (int base = threadIdx.x; base < tot; base += step) {
+    Cx<R> tmp[STAGE_UNROLL];
+#pragma unroll
+    for (int u = 0; u < STAGE_UNROLL; ++u) {
+      const int e = base + u * blockDim.x;
+      tmp[u] = Cx<R>{0, 0};
+      if (e < tot) {
+        const int j = e % ndc, q = e / ndc;
+        const int d = q % ndir, r = q / ndir;
+        const int rr = r0 + r;
+        if (rr < nrhs) tmp[u] = ld<R>(v[((long)rr * nsites + nbr[(long)d * nsites + X]) * ndc + j]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_UNROLL; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < tot) {
+        const int j = e % ndc, q = e / ndc;
+        const int d = q % ndir, r = q / ndir;
+        Vs[(d * ndc + j) * RTP + r] = tmp[u];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ fragments
+
+// The outputs a thread owns after the compute core: N entries (dof i, tile
+// rhs t, value), and the partial-sum slot its entries belong to.
+template <class R, int N>
+struct Frag {
+  Cx<R> val[N];
+  int i[N];
+  int t[N];
+  bool ok[N];  // inside ndc x RT and owned (final) by this thread
+  int slot;    // row group for deterministic per-rhs partials (-1: none)
+};
+
+template <int CORE, int TI, int TR>
+struct FragN {
+  static constexpr int value = CORE ? 4 : TI * TR;
+};
+
+// SIMT core: acc[a][b] over (dir, j) in steps of KS (stencil blocks read from
+// global memory, k-loop unrolled so several loads are in flight), then the
+// k-split partial tiles are summed via LDS.
+template <class R, class OT, int TI, int TR>
+__device__ __forceinline__ void core_simt(Frag<R, TI * TR>& f, const Cx<OT>* __restrict__ Yt, int X, int nsites,
+                                          const Cx<R>* Vs, Cx<R>* red, int ndc, int ndir, int RT, int KS) {
+  const int nib = ndc / TI, nrb = RT / TR;
+  const int tid = threadIdx.x;
+  const int ib = tid % nib, rb = (tid / nib) % nrb, ks = tid / (nib * nrb);
+  const bool valid = ks < KS;
+  Cx<R> acc[TI][TR];
+#pragma unroll
+  for (int a = 0; a < TI; ++a)
+#pragma unroll
+    for (int b = 0; b < TR; ++b) acc[a][b] = Cx<R>{0, 0};
+  if (valid) {
+    const int nk = ndir * ndc;
+    const int i0 = ib * TI, r0l = rb * TR, RTP = panel_stride(RT);
+    const long per = (long)ndc * ndc;
+#pragma unroll 8
+    for (int k = ks; k < nk; k += KS) {
+      const int d = k / ndc, j = k - d * ndc;
+      const Cx<OT>* yp = Yt + ((long)d * nsites + X) * per + (long)j * ndc + i0;
+      Cx<R> y[TI], v[TR];
+#pragma unroll
+      for (int a = 0; a < TI; ++a) y[a] = ld<R>(yp[a]);
+#pragma unroll
+      for (int b = 0; b < TR; ++b) v[b] = Vs[k * RTP + r0l + b];
+#pragma unroll
+      for (int a = 0; a < TI; ++a)
+#pragma unroll
+        for (int b = 0; b < TR; ++b) cfma(acc[a][b], y[a], v[b]);
+    }
+  }
+  if (KS > 1) {
+    const int nslots = nib * nrb, sb = rb * nib + ib;
+    if (valid && ks > 0)
+#pragma unroll
+      for (int a = 0; a < TI; ++a)
+#pragma unroll
+        for (int b = 0; b < TR; ++b) red[((ks - 1) * nslots + sb) * TI * TR + a * TR + b] = acc[a][b];
+    __syncthreads();
+    if (valid && ks == 0)
+      for (int q = 1; q < KS; ++q)
+#pragma unroll
+        for (int a = 0; a < TI; ++a)
+#pragma unroll
+          for (int b = 0; b < TR; ++b) acc[a][b] += red[((q - 1) * nslots + sb) * TI * TR + a * TR + b];
+  }
+  const bool owner = valid && ks == 0;
+  f.slot = owner ? ib : -1;
+#pragma unroll
+  for (int a = 0; a < TI; ++a)
+#pragma unroll
+    for (int b = 0; b < TR; ++b) {
+      const int e = a * TR + b;
+      f.val[e] = acc[a][b];
+      f.i[e] = ib * TI + a;
+      f.t[e] = rb * TR + b;
+      f.ok[e] = owner;
+    }
+}
+
+// MFMA core: wave w owns the 16x16 tile (mt, nt) = (w % MT, w / MT).  The A
+// operand (stencil blocks) comes from LDS (YL = 1) or straight from global
+// memory with loads issued one chunk pair ahead (YL = 0).
+template <class R, class OT, int YL>
+__device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const Cx<OT>* __restrict__ Yt, int X,
+                                          int nsites, const Cx<R>* Vs, int ndc, int ndir, int RT, int MT, int NT) {
+  using M = Mfma<R>;
+  typedef typename M::v4 v4;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const bool on = w < MT * NT;
+  const int mt = on ? w % MT : 0, nt = on ? w / MT : 0;
+  const int K = ndir * ndc, nkc = (K + 3) / 4;
+  const int ia = mt * 16 + (l & 15);      // A-operand row held by this lane
+  const int cb = nt * 16 + (l & 15);      // B-operand column held by this lane
+  const int kk = l >> 4;
+  const bool arow = ia < ndc;
+  const long per = (long)ndc * ndc;
+  auto loadA = [&](int k) -> Cx<R> {
+    if (k >= K || !arow) return Cx<R>{0, 0};
+    if constexpr (YL == 1) {
+      return Ys[k * ndc + ia];
+    } else {
+      const int d = k / ndc, j = k - d * ndc;
+      return ld<R>(Yt[((long)d * nsites + X) * per + (long)j * ndc + ia]);
+    }
+  };
+  const int RTP = panel_stride(RT);
+  auto loadB = [&](int k) -> Cx<R> { return k < K ? Vs[k * RTP + cb] : Cx<R>{0, 0}; };
+  v4 cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
+  if (on) {
+    Cx<R> a0 = loadA(kk), a1 = loadA(kk + 4), b0 = loadB(kk), b1 = loadB(kk + 4);
+    for (int kc = 0; kc < nkc; kc += 2) {
+      const int k0 = 4 * kc + kk, k1 = k0 + 4;
+      // operands of the next chunk pair, fetched before this pair's MFMAs
+      const Cx<R> na0 = loadA(k0 + 8), na1 = loadA(k1 + 8);
+      const Cx<R> nb0 = loadB(k0 + 8), nb1 = loadB(k1 + 8);
+      cr0 = M::op(a0.re, b0.re, cr0);
+      ci0 = M::op(a0.re, b0.im, ci0);
+      cr1 = M::op(a1.re, b1.re, cr1);
+      ci1 = M::op(a1.re, b1.im, ci1);
+      cr0 = M::op(-a0.im, b0.im, cr0);
+      ci0 = M::op(a0.im, b0.re, ci0);
+      cr1 = M::op(-a1.im, b1.im, cr1);
+      ci1 = M::op(a1.im, b1.re, ci1);
+      a0 = na0;
+      a1 = na1;
+      b0 = nb0;
+      b1 = nb1;
+    }
+  }
+  f.slot = on ? mt * 4 + (l >> 4) : -1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = mt * 16 + M::row(l, v);
+    f.val[v] = Cx<R>{cr0[v] + cr1[v], ci0[v] + ci1[v]};
+    f.i[v] = i;
+    f.t[v] = cb;
+    f.ok[v] = on && i < ndc && cb < RT;
+  }
+}
+
+template <class R, class OT, int CORE, int TI, int TR, int YL>
+__device__ __forceinline__ void run_core(Frag<R, FragN<CORE, TI, TR>::value>& f, unsigned char* raw,
+                                         const LdsLayout& L, const Cx<OT>* Yt, int X, int nsites, int ndc,
+                                         int ndir, int RT, int KS, int MT, int NT) {
+  const Cx<R>* Ys = reinterpret_cast<const Cx<R>*>(raw + L.ys);
+  const Cx<R>* Vs = reinterpret_cast<const Cx<R>*>(raw + L.vs);
+  if constexpr (CORE == 1)
+    core_mfma<R, OT, YL>(f, Ys, Yt, X, nsites, Vs, ndc, ndir, RT, MT, NT);
+  else
+    core_simt<R, OT, TI, TR>(f, Yt, X, nsites, Vs, reinterpret_cast<Cx<R>*>(raw + L.red), ndc, ndir, RT, KS);
+}
+
+// Device-side recomputation of the LDS layout (same arithmetic as the host).
+__device__ __forceinline__ LdsLayout lds_layout_dev(int core, int ylds, int RT, int TI, int TR, int KS, int MT,
+                                                    int ndc, int ndir, int esz) {
+  LdsLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (bytes + 15) & ~size_t(15);
+    return at;
+  };
+  L.ys = take(core && ylds ? (size_t)ndir * ndc * ndc * esz : 0);
+  L.vs = take((size_t)ndir * ndc * panel_stride(RT) * esz);
+  const int nib = core ? 0 : ndc / TI, nrb = core ? 0 : RT / TR;
+  L.red = take(core ? 0 : (size_t)(KS - 1) * nib * nrb * TI * TR * esz);
+  const int nsl = core ? MT * 4 : nib;
+  L.S = take((size_t)nsl * RT * sizeof(double));
+  L.sc = take((size_t)(2 * RT + 1024) * sizeof(double));
+  L.live = take((size_t)RT * sizeof(int));
+  L.O = take((size_t)RT * ndc * esz);
+  L.total = o;
+  return L;
+}
+
+struct TileArgs {
+  int RT, TI, TR, KS, MT, NT;
+};
+
+// out[r][X][i] = [add +] sgn * (A v)[r][X][i]
+template <class R, class OT, class VI, class VO, int CORE, int TI, int TR, int YL>
+__global__ __launch_bounds__(1024) void k_capply_fast(Cx<VO>* __restrict__ out, const Cx<VI>* __restrict__ in,
+                                                      const Cx<VO>* add, R sgn, const Cx<OT>* __restrict__ Yt,
+                                                      const int* __restrict__ nbr, int nsites, int ndc, int ndir,
+                                                      TileArgs ta, int nrhs, const int* act) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>));
+  const int X = blockIdx.x, r0 = blockIdx.y * ta.RT;
+  if (CORE == 1 && YL == 1) stage_blocks<R, OT>(reinterpret_cast<Cx<R>*>(smem_raw + L.ys), Yt, X, nsites, ndc, ndir);
+  stage_panel<R, VI>(reinterpret_cast<Cx<R>*>(smem_raw + L.vs), in, nbr, X, nsites, ndc, ndir, r0, ta.RT, nrhs);
+  __syncthreads();
+  Frag<R, FragN<CORE, TI, TR>::value> f;
+  run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yt, X, nsites, ndc, ndir, ta.RT, ta.KS, ta.MT, ta.NT);
+  Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
+  frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  for (int e = threadIdx.x; e < ta.RT * ndc; e += blockDim.x) {
+    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    if (rr >= nrhs || !is_active(act, rr)) continue;
+    const long o = ((long)rr * nsites + X) * ndc + i;
+    Cx<R> res = sgn * O[e];
+    if (add) res += ld<R>(add[o]);
+    out[o] = st<VO>(res);
+  }
+}
+
+
+// ------------------------------------------------------------------ fused CGNE
+
+struct CgneState {
+  double* rr;         // [2][nrhs]  ||r||^2 at the start of iteration k (slot k & 1)
+  double* target;     // [nrhs]     (tol ||b||)^2
+  int* act;           // [2][nrhs]  active during iteration k (slot k & 1)
+  int* its;           // [nrhs]     iterations of the current call
+  int* tot;           // [nrhs]     iterations over all calls
+  int* calls;         // [nrhs]     calls while active
+  const int* parent;  // rhs the caller wants solved
+  double* PA;         // [nsites][nrhs] partial ||r||^2
+  double* PB;         // [nsites][nrhs] partial ||p||^2
+};
+
+// out[t] = sum_X P[X][r0 + t] for t < RT, summed in a fixed order: thread
+// (t, g) adds sites g, g + G, ... (G = blockDim / RT) in TS_UNROLL interleaved
+// running sums (all their loads in flight together), the running sums are
+// combined in order, then the G partial sums are added in g order.
+constexpr int TS_UNROLL = 16;
+__device__ __forceinline__ void tile_sums(const double* P, int nsites, int nrhs, int r0, int RT, double* out,
+                                          double* scratch) {
+  const int G = blockDim.x / RT;
+  const int t = threadIdx.x % RT, g = threadIdx.x / RT;
+  double acc = 0.0;
+  if (g < G && r0 + t < nrhs) {
+    const double* col = P + r0 + t;
+    for (int X0 = g; X0 < nsites; X0 += TS_UNROLL * G) {
+      double v[TS_UNROLL];
+#pragma unroll
+      for (int u = 0; u < TS_UNROLL; ++u) {
+        const int X = X0 + u * G;
+        v[u] = X < nsites ? col[(long)X * nrhs] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TS_UNROLL; ++u) acc += v[u];
+    }
+  }
+  if (g < G) scratch[g * RT + t] = acc;
+  __syncthreads();
+  if (threadIdx.x < RT) {
+    double a = 0.0;
+    for (int q = 0; q < G; ++q) a += scratch[q * RT + threadIdx.x];
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+// Scatter a thread's fragment into the workgroup's output tile O[t*ndc + i]
+// (every (t < RT, i < ndc) entry is owned by exactly one thread), so the
+// epilogue can walk the tile dof-fastest with coalesced global accesses.
+template <class R, int N>
+__device__ __forceinline__ void frag_to_tile(Cx<R>* O, const Frag<R, N>& f, int ndc) {
+#pragma unroll
+  for (int e = 0; e < N; ++e)
+    if (f.ok[e]) O[f.t[e] * ndc + f.i[e]] = f.val[e];
+  __syncthreads();
+}
+
+// P[X][r0 + t] = sum_i |O[t*ndc + i]|^2, dofs in order.
+template <class R>
+__device__ __forceinline__ void tile_partials(double* P, const Cx<R>* O, int X, int nrhs, int r0, int RT, int ndc) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
+    if (r0 + t >= nrhs) continue;
+    double s = 0.0;
+    for (int i = 0; i < ndc; ++i) s += (double)norm2(O[t * ndc + i]);
+    P[(long)X * nrhs + r0 + t] = s;
+  }
+}
+
+// init 1: x = 0, r = b, PA = partial ||b||^2 (one thread per rhs, dofs in order).
+template <class R>
+__global__ __launch_bounds__(256) void k_cgne_init1(Cx<R>* x, Cx<R>* r, const Cx<R>* b, int nsites, int ndc,
+                                                     int nrhs, CgneState s) {
+  const int X = blockIdx.x;
+  for (int rr = threadIdx.x; rr < nrhs; rr += blockDim.x) {
+    const bool on = s.parent == nullptr || s.parent[rr] != 0;
+    double acc = 0.0;
+    for (int i = 0; i < ndc; ++i) {
+      const long o = ((long)rr * nsites + X) * ndc + i;
+      const Cx<R> v = b[o];
+      if (on) {
+        x[o] = Cx<R>{0, 0};
+        r[o] = v;
+      }
+      acc += (double)norm2(v);
+    }
+    s.PA[(long)X * nrhs + rr] = acc;
+  }
+}
+
+// Common prologue pieces of the CGNE kernels.
+template <class R, class OT, int CORE, int YL>
+__device__ __forceinline__ void cgne_stage(unsigned char* raw, const LdsLayout& L, const Cx<OT>* Y, const Cx<R>* v,
+                                           const int* nbr, int X, int nsites, int ndc, int ndir, int r0, int RT,
+                                           int nrhs) {
+  if (CORE == 1 && YL == 1) stage_blocks<R, OT>(reinterpret_cast<Cx<R>*>(raw + L.ys), Y, X, nsites, ndc, ndir);
+  stage_panel<R, R>(reinterpret_cast<Cx<R>*>(raw + L.vs), v, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
+}
+
+// init 2: rr_0, target, act_0 ; p = A^dag r ; PB = partial ||p||^2
+template <class R, class OT, int CORE, int TI, int TR, int YL>
+__global__ __launch_bounds__(1024) void k_cgne_init2(Cx<R>* p, const Cx<R>* r, const Cx<OT>* Yd, const int* nbr,
+                                                      int nsites, int ndc, int ndir, TileArgs ta, int nrhs,
+                                                      CgneState s, double tol2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>));
+  double* sc = reinterpret_cast<double*>(smem_raw + L.sc);
+  int* live = reinterpret_cast<int*>(smem_raw + L.live);
+  const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT;
+  tile_sums(s.PA, nsites, nrhs, r0, RT, sc, sc + 2 * RT);
+  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
+    const int rr = r0 + t;
+    int lv = 0;
+    if (rr < nrhs) {
+      const double b2 = sc[t], tg = tol2 * b2;
+      const bool on = s.parent == nullptr || s.parent[rr] != 0;
+      lv = on && b2 > tg && b2 > 0.0;
+      if (X == 0) {
+        s.rr[rr] = b2;
+        s.target[rr] = tg;
+        s.act[rr] = lv;
+        s.its[rr] = 0;
+        if (on) s.calls[rr] += 1;
+      }
+    }
+    live[t] = lv;
+  }
+  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
+  __syncthreads();
+  Frag<R, FragN<CORE, TI, TR>::value> f;
+  run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yd, X, nsites, ndc, ndir, RT, ta.KS, ta.MT, ta.NT);
+  Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
+  frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  for (int e = threadIdx.x; e < RT * ndc; e += blockDim.x) {
+    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    if (rr >= nrhs || !live[t]) {
+      O[e] = Cx<R>{0, 0};
+      continue;
+    }
+    p[((long)rr * nsites + X) * ndc + i] = O[e];
+  }
+  tile_partials<R>(s.PB, O, X, nrhs, r0, RT, ndc);
+}
+
+
+// A_k: alpha = rr_k/||p||^2 ; q = A p ; x += alpha p ; r -= alpha q ; PA = partial ||r||^2
+template <class R, class OT, int CORE, int TI, int TR, int YL>
+__global__ __launch_bounds__(1024) void k_cgne_A(Cx<R>* x, Cx<R>* r, const Cx<R>* p, const Cx<OT>* Yt,
+                                                  const int* nbr, int nsites, int ndc, int ndir, TileArgs ta,
+                                                  int nrhs, CgneState s, int k) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>));
+  double* sc = reinterpret_cast<double*>(smem_raw + L.sc);
+  int* live = reinterpret_cast<int*>(smem_raw + L.live);
+  const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT, sl = (k & 1) * nrhs;
+  tile_sums(s.PB, nsites, nrhs, r0, RT, sc, sc + 2 * RT);
+  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
+    const int rr = r0 + t;
+    const int lv = rr < nrhs ? s.act[sl + rr] : 0;
+    live[t] = lv;
+    sc[RT + t] = lv ? s.rr[sl + rr] / sc[t] : 0.0;  // alpha
+  }
+  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yt, p, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
+  __syncthreads();
+  Frag<R, FragN<CORE, TI, TR>::value> f;
+  run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yt, X, nsites, ndc, ndir, RT, ta.KS, ta.MT, ta.NT);
+  const Cx<R>* Vs = reinterpret_cast<const Cx<R>*>(smem_raw + L.vs);
+  const int RTP = panel_stride(RT);
+  Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
+  frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  for (int e = threadIdx.x; e < RT * ndc; e += blockDim.x) {
+    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    if (rr >= nrhs || !live[t]) {
+      O[e] = Cx<R>{0, 0};
+      continue;
+    }
+    const R al = (R)sc[RT + t];
+    const long o = ((long)rr * nsites + X) * ndc + i;
+    const Cx<R> pv = Vs[i * RTP + t];  // direction 0 is the site itself
+    x[o] = x[o] + al * pv;
+    const Cx<R> rv = r[o] - al * O[e];
+    r[o] = rv;
+    O[e] = rv;
+  }
+  tile_partials<R>(s.PA, O, X, nrhs, r0, RT, ndc);
+}
+
+
+// B_k: ||r||^2 -> stop test, beta ; p = A^dag r + beta p ; PB = partial ||p||^2
+template <class R, class OT, int CORE, int TI, int TR, int YL>
+__global__ __launch_bounds__(1024) void k_cgne_B(Cx<R>* p, const Cx<R>* r, const Cx<OT>* Yd, const int* nbr,
+                                                  int nsites, int ndc, int ndir, TileArgs ta, int nrhs,
+                                                  CgneState s, int k) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>));
+  double* sc = reinterpret_cast<double*>(smem_raw + L.sc);
+  int* live = reinterpret_cast<int*>(smem_raw + L.live);
+  const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT;
+  const int sl = (k & 1) * nrhs, sn = ((k + 1) & 1) * nrhs;
+  tile_sums(s.PA, nsites, nrhs, r0, RT, sc, sc + 2 * RT);
+  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
+    const int rr = r0 + t;
+    int lv = 0;
+    double beta = 0.0;
+    if (rr < nrhs) {
+      const int was = s.act[sl + rr];
+      const double rn = sc[t], ro = s.rr[sl + rr];
+      lv = was && rn > s.target[rr];
+      beta = lv ? rn / ro : 0.0;
+      if (X == 0) {
+        s.rr[sn + rr] = was ? rn : ro;
+        s.act[sn + rr] = lv;
+        if (was) {
+          s.its[rr] += 1;
+          s.tot[rr] += 1;
+        }
+      }
+    }
+    live[t] = lv;
+    sc[RT + t] = beta;
+  }
+  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
+  __syncthreads();
+  Frag<R, FragN<CORE, TI, TR>::value> f;
+  run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yd, X, nsites, ndc, ndir, RT, ta.KS, ta.MT, ta.NT);
+  Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
+  frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  for (int e = threadIdx.x; e < RT * ndc; e += blockDim.x) {
+    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    if (rr >= nrhs || !live[t]) {
+      O[e] = Cx<R>{0, 0};
+      continue;
+    }
+    const R be = (R)sc[RT + t];
+    const long o = ((long)rr * nsites + X) * ndc + i;
+    const Cx<R> pv = O[e] + be * p[o];
+    p[o] = pv;
+    O[e] = pv;
+  }
+  tile_partials<R>(s.PB, O, X, nrhs, r0, RT, ndc);
+}
+
+
+}  // namespace kdmg

@@ -2,13 +2,16 @@
 // the lattice, setup and solver translation units.
 #pragma once
 #include <cstdlib>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
 #include "blas.cuh"
 #include "fine2d.cuh"
 #include "coarse.cuh"
+#include "coarse_fast.cuh"
 
 namespace kdmg {
 
@@ -132,6 +135,9 @@ struct CoarseLevel {
   DevBuf nbr;                    // int [ndir][nsites]
   DevBuf Yt64, Yd64, Yt32, Yd32; // operator and adjoint, FP64 and FP32 copies
   std::vector<int> h_nbr;
+  // autotuned launch shapes, keyed by nrhs * 64 + bytes per complex entry
+  mutable std::map<long, TileShape> tuned;
+  std::unique_ptr<std::mutex> tune_mu = std::make_unique<std::mutex>();
   long n() const { return (long)nsites * ndc; }
   size_t bytes() const { return nbr.bytes + Yt64.bytes + Yd64.bytes + Yt32.bytes + Yd32.bytes; }
 };
@@ -149,6 +155,9 @@ struct Transfer {
     return P64.bytes + P16.bytes + children.bytes + parent.bytes + relaxed.bytes;
   }
 };
+
+void autotune_level(const CoarseLevel& L, int nrhs, bool fp32, hipStream_t st);
+bool autotune_enabled();
 
 struct SolveWS;  // solver workspace (solver.hip)
 void destroy_ws(SolveWS*);
@@ -194,18 +203,71 @@ inline void capply_shape(int ndc, int nrhs, int& js, int& rpb) {
   if (js < 1) js = 1;
 }
 
+// Dispatch on the compute core of a TileShape: KERNEL(CORE, TI, TR).
+#define KDMG_TILE_DISPATCH(S, KERNEL)                      \
+  do {                                                     \
+    if ((S).core == 1 && (S).ylds) KERNEL(1, 1, 1, 1)      \
+    else if ((S).core == 1) KERNEL(1, 1, 1, 0)             \
+    else if ((S).TI == 2) KERNEL(0, 2, 1, 0)               \
+    else KERNEL(0, 1, 1, 0)                                \
+  } while (0)
+
+// Raise the dynamic-LDS limit of a kernel once (needed above 64 KB).
+inline void ensure_smem(const void* fn, size_t bytes) {
+  if (bytes > 65536) KDMG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+inline TileArgs tile_args(const TileShape& s) { return TileArgs{s.RT, s.TI, s.TR, s.KS, s.MT, s.NT}; }
+
+// The launch shape for a coarse level: the autotuned one if present, else the
+// default heuristic.
+inline TileShape level_shape(const CoarseLevel& L, int nrhs, size_t esz) {
+  {
+    std::lock_guard<std::mutex> g(*L.tune_mu);
+    auto it = L.tuned.find((long)nrhs * 64 + (long)esz);
+    if (it != L.tuned.end()) return it->second;
+  }
+  return choose_tile(L.ndc, nrhs, L.ndir, esz);
+}
+
+template <class R, class OT>
+void coarse_apply_shape(const CoarseLevel& L, bool dag, Cx<R>* out, const Cx<R>* in, const Cx<R>* add,
+                        double sgn, const int* act, int nrhs, hipStream_t st, const TileShape& s);
+
 template <class R, class OT>
 void coarse_apply(const CoarseLevel& L, bool dag, Cx<R>* out, const Cx<R>* in, const Cx<R>* add,
                   double sgn, const int* act, int nrhs, hipStream_t st) {
+  coarse_apply_shape<R, OT>(L, dag, out, in, add, sgn, act, nrhs, st, level_shape(L, nrhs, sizeof(Cx<R>)));
+}
+
+template <class R, class OT>
+void coarse_apply_shape(const CoarseLevel& L, bool dag, Cx<R>* out, const Cx<R>* in, const Cx<R>* add,
+                        double sgn, const int* act, int nrhs, hipStream_t st, const TileShape& s) {
   const Cx<OT>* Y;
   if (sizeof(OT) == 8) Y = (const Cx<OT>*)(dag ? L.Yd64.p : L.Yt64.p);
   else Y = (const Cx<OT>*)(dag ? L.Yd32.p : L.Yt32.p);
-  int js, rpb;
-  capply_shape(L.ndc, nrhs, js, rpb);
-  const int threads = L.ndc * js * rpb;
-  dim3 grid(L.nsites, cdiv(nrhs, rpb));
-  hipLaunchKernelGGL((k_capply<R, OT, R, R>), grid, dim3(threads), threads * sizeof(Cx<R>), st, out,
-                     in, add, (R)sgn, Y, L.nbr.as<int>(), L.nsites, L.ndc, L.ndir, js, rpb, nrhs, act);
+  if (s.smem > LDS_LIMIT) {
+    // stencil blocks too large for LDS: one thread per output, blocks from global memory
+    int js, rpb;
+    capply_shape(L.ndc, nrhs, js, rpb);
+    const int threads = L.ndc * js * rpb;
+    hipLaunchKernelGGL((k_capply<R, OT, R, R>), dim3(L.nsites, cdiv(nrhs, rpb)), dim3(threads),
+                       threads * sizeof(Cx<R>), st, out, in, add, (R)sgn, Y, L.nbr.as<int>(), L.nsites, L.ndc,
+                       L.ndir, js, rpb, nrhs, act);
+    KDMG_LAUNCH_CHECK();
+    return;
+  }
+  const dim3 grid(L.nsites, cdiv(nrhs, s.RT));
+  const TileArgs ta = tile_args(s);
+#define KDMG_LAUNCH_CAPPLY(C_, TI_, TR_, YL_)                                                              \
+  {                                                                                                        \
+    auto fn = k_capply_fast<R, OT, R, R, C_, TI_, TR_, YL_>;                                                    \
+    ensure_smem((const void*)fn, s.smem);                                                                  \
+    hipLaunchKernelGGL(fn, grid, dim3(s.threads), s.smem, st, out, in, add, (R)sgn, Y, L.nbr.as<int>(),    \
+                       L.nsites, L.ndc, L.ndir, ta, nrhs, act);                                            \
+  }
+  KDMG_TILE_DISPATCH(s, KDMG_LAUNCH_CAPPLY);
+#undef KDMG_LAUNCH_CAPPLY
   KDMG_LAUNCH_CHECK();
 }
 

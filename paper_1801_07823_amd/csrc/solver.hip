@@ -31,6 +31,7 @@ struct LevelWS {
   DevBuf r1, x, r2, q;        // K-cycle work (levels that have a coarser level)
   DevBuf t, w;                // level-0 Schur temporaries (full layout)
   DevBuf b, xs, rs, Z, W, p;  // coarse solve: input, solution, residual, GCR basis / CGNE p
+  DevBuf cg_rr, cg_target, cg_act, PA, PB;  // fused CGNE state (coarsest level)
   KrylovAlloc ks, kmr;
   template <class T> Cx<T>* v(DevBuf& d) const { return d.as<Cx<T>>(); }
 };
@@ -78,6 +79,64 @@ struct OpResidNorm {  // ||r||^2 -> out[r]
   __device__ void elem(int rr, int, long i, Acc<1>& a) const { a.v[0] += norm2(r[rr * stride + i]); }
   __device__ void finish(int rr, int, const double* s) const { out[rr] = s[0]; }
 };
+
+// Fused CGNE on the coarsest level: two kernels per iteration (see
+// coarse_fast.cuh), host reads the active flags every `poll` iterations.
+int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c64* b, c64* x, c64* r,
+               c64* p, double tol, int maxit, const int* parent, int poll) {
+  CgneState s;
+  s.rr = W.cg_rr.as<double>();
+  s.target = W.cg_target.as<double>();
+  s.act = W.cg_act.as<int>();
+  s.its = W.ks.k.its;
+  s.tot = W.ks.k.tot;
+  s.calls = W.ks.k.calls;
+  s.parent = parent;
+  s.PA = W.PA.as<double>();
+  s.PB = W.PB.as<double>();
+  const TileShape sh = level_shape(L, nrhs, sizeof(c64));
+  KDMG_CHECK(sh.smem <= LDS_LIMIT, KDMG_EUNSUPPORTED, "coarsest operator too large for the fused CGNE");
+  const dim3 grid(L.nsites, cdiv(nrhs, sh.RT));
+  const TileArgs ta = tile_args(sh);
+  const c64* Yt = L.Yt64.as<c64>();
+  const c64* Yd = L.Yd64.as<c64>();
+  const int* nbr = L.nbr.as<int>();
+  hipLaunchKernelGGL(k_cgne_init1<double>, dim3(L.nsites), dim3(64), 0, c.st, x, r, b, L.nsites, L.ndc, nrhs, s);
+#define KDMG_L_INIT2(C_, TI_, TR_, YL_)                                                                     \
+  {                                                                                                    \
+    auto fn = k_cgne_init2<double, double, C_, TI_, TR_, YL_>;                                              \
+    ensure_smem((const void*)fn, sh.smem);                                                             \
+    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, c.st, p, r, Yd, nbr, L.nsites, L.ndc, L.ndir, \
+                       ta, nrhs, s, tol * tol);                                                        \
+  }
+  KDMG_TILE_DISPATCH(sh, KDMG_L_INIT2);
+#undef KDMG_L_INIT2
+  KDMG_LAUNCH_CHECK();
+  int k = 0;
+  for (; k < maxit; ++k) {
+#define KDMG_L_A(C_, TI_, TR_, YL_)                                                                          \
+  {                                                                                                     \
+    auto fn = k_cgne_A<double, double, C_, TI_, TR_, YL_>;                                                   \
+    ensure_smem((const void*)fn, sh.smem);                                                              \
+    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, c.st, x, r, p, Yt, nbr, L.nsites, L.ndc,    \
+                       L.ndir, ta, nrhs, s, k);                                                         \
+  }
+#define KDMG_L_B(C_, TI_, TR_, YL_)                                                                          \
+  {                                                                                                     \
+    auto fn = k_cgne_B<double, double, C_, TI_, TR_, YL_>;                                                   \
+    ensure_smem((const void*)fn, sh.smem);                                                              \
+    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, c.st, p, r, Yd, nbr, L.nsites, L.ndc,       \
+                       L.ndir, ta, nrhs, s, k);                                                         \
+  }
+    KDMG_TILE_DISPATCH(sh, KDMG_L_A);
+    KDMG_TILE_DISPATCH(sh, KDMG_L_B);
+#undef KDMG_L_A
+#undef KDMG_L_B
+    KDMG_LAUNCH_CHECK();
+    if ((k + 1) % poll == 0 && !any_active(c, s.act + ((k + 1) & 1) * nrhs, nrhs)) { ++k; break; }
+  }
+  return k;
+}
 
 class Runner {
  public:
@@ -169,10 +228,15 @@ class Runner {
       Cx<T>* r = L.v<T>(L.rs);
       auto opf = [&](Cx<T>* o, const Cx<T>* i, const Cx<T>* res, const int* a) { op<T>(l, o, i, res, a); };
       if (l == h_.nlevels - 1) {
-        auto opd = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, true); };
-        auto opn = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, false); };
-        cgne_solve<T>(c_, nrhs_, n, b, x, r, L.v<T>(L.p), L.v<T>(L.q), P.coarse_tol, P.coarse_maxit,
-                      L.ks.k, parent, opn, opd, poll_);
+        if constexpr (sizeof(T) == 8) {
+          cgne_fused(c_, h_.L[l], L, nrhs_, b, x, r, L.v<T>(L.p), P.coarse_tol, P.coarse_maxit, parent,
+                     poll_);
+        } else {
+          auto opd = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, true); };
+          auto opn = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, false); };
+          cgne_solve<T>(c_, nrhs_, n, b, x, r, L.v<T>(L.p), L.v<T>(L.q), P.coarse_tol, P.coarse_maxit,
+                        L.ks.k, parent, opn, opd, poll_);
+        }
       } else {
         const KrylovState& ks = L.ks.k;
         auto prec = [&](Cx<T>* z, const Cx<T>* rr, const int* a) { kcycle<T>(l, z, rr, a); };
@@ -269,6 +333,11 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
       if (coarsest) {
         A(L.p, v);
         A(L.q, v);
+        A(L.cg_rr, sizeof(double) * 2 * nrhs);
+        A(L.cg_target, sizeof(double) * nrhs);
+        A(L.cg_act, sizeof(int) * 2 * nrhs);
+        A(L.PA, sizeof(double) * (size_t)nrhs * h.L[l].nsites);
+        A(L.PB, sizeof(double) * (size_t)nrhs * h.L[l].nsites);
       } else {
         A(L.Z, v * P.inter_restart);
         A(L.W, v * P.inter_restart);
@@ -324,6 +393,9 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
     h->ws = nullptr;
     h->ws = make_ws(*h, nrhs, prec, st);
   }
+  if (autotune_enabled())
+    for (int l = 1; l < h->nlevels; ++l)
+      autotune_level(h->L[l], nrhs, prec == KDMG_MIXED && l < h->nlevels - 1, st);
   SolveWS& ws = *h->ws;
   int expect = 0;
   KDMG_CHECK(ws.busy.compare_exchange_strong(expect, 1), KDMG_EBUSY, "hierarchy busy");

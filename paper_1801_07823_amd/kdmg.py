@@ -77,6 +77,7 @@ _SIGS = {
     "kdmg_prolong": (_I, [_P, _I, _P, _P, _I, _P]),
     "kdmg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(kdmg_solve_info), _P]),
     "kdmg_hierarchy_footprint": (_I, [_P, _I, ctypes.POINTER(_S)]),
+    "kdmg_hierarchy_autotune": (_I, [_P, _I, _I, _P]),
     "kdmg_status_string": (ctypes.c_char_p, [_I]),
     "kdmg_last_error": (ctypes.c_char_p, []),
 }
@@ -242,6 +243,10 @@ def kdmg_restrict(h, k, inp, out, nrhs, stream=None):
 
 def kdmg_prolong(h, k, inp, out, nrhs, stream=None):
     _check(_lib.kdmg_prolong(h.handle, k, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+
+
+def kdmg_hierarchy_autotune(h, nrhs, prec=KDMG_FP64, stream=None):
+    _check(_lib.kdmg_hierarchy_autotune(h.handle, nrhs, prec, _stream(stream)))
 
 
 def kdmg_solve(h, b, x, nrhs, tol=1e-10, prec=KDMG_FP64, stream=None, raise_on_noconv=True):
