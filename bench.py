@@ -18,14 +18,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+DIMS = (256, 256)
+BETA, MASS, NRHS, NV = 10.0, 0.001, 32, 16
+NV2 = int(os.environ.get("KDMG_BENCH_NV2", "12"))
+COARSE_MAXIT = 1024
 WORKLOAD = {"workload": "2D U(1) staggered KD-MG solve", "lattice": [256, 256], "beta": 10.0,
             "mass": 0.001, "nrhs": 32, "levels": "3: 2x2 KD blocks; 4x4 aggregates n_vec 16 "
-            "(32x32 complex coarse blocks); 2x2 aggregates n_vec 12", "tol": 1e-10,
+            "(32x32 complex coarse blocks); 2x2 aggregates n_vec %d" % NV2, "tol": 1e-10,
             "coarsest": "CGNE tol 0.2, at most 1024 iterations",
             "gauge": "quenched heatbath, 200 sweeps"}
-DIMS = (256, 256)
-BETA, MASS, NRHS, NV, NV2 = 10.0, 0.001, 32, 16, 12
-COARSE_MAXIT = 1024
+# HBM traffic of the dominant kernels from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE) over `bench.py --kernel-profile`, in bytes
+# per launch averaged over k_cgne_A and k_cgne_B.  FETCH_SIZE read 32784 KiB
+# and WRITE_SIZE 65536 KiB for a 64 MiB elementwise copy, so FETCH_SIZE is
+# scaled by 2.0 and WRITE_SIZE by 1.0.  Valid only for the kernel source it
+# was measured on (sha256 of coarse_fast.cuh); otherwise reported as null.
+TRAFFIC = {"coarse_fast_sha256": "c122569b3ca739944a0b5499e613fe959e4d3149eebe04e3828e4e8f938d72d5",
+           "n_vec_2": 12,
+           "bytes_per_launch": ((13658.1 + 12238.0) * 2.0 + (5760.5 + 2911.8) * 1.0) / 2 * 1024}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
@@ -90,6 +100,16 @@ def start_cpu_leg(budget_its):
 
 # ------------------------------------------------------------------ GPU leg
 
+def traffic_per_launch():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1801_07823_amd", "csrc", "coarse_fast.cuh")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != TRAFFIC["coarse_fast_sha256"] or NV2 != TRAFFIC["n_vec_2"]:
+        return None
+    return TRAFFIC["bytes_per_launch"]
+
+
 def event_time(fn, reps):
     import torch
     s = torch.cuda.current_stream()
@@ -104,15 +124,168 @@ def event_time(fn, reps):
     return e0.elapsed_time(e1) / reps * 1e-3
 
 
+# ------------------------------------------------------------------ served stream
+
+SERVE_SIZES = (64, 128, 256, 512)
+SERVE_BETAS = (3.0, 6.0, 10.0)
+SERVE_M_SETUP = 0.001
+
+
+def _serve_field(args):
+    L, c, sweeps = args
+    from synth import u1_heatbath, config_seed
+    beta = SERVE_BETAS[c % 3]
+    U, info = u1_heatbath((L, L), beta, sweeps, config_seed(L, beta, c))
+    return L, c, beta, U, info["plaquette"]
+
+
+def serve_main(a):
+    """Served stream of single-rhs mixed-precision solves through kdmg_server:
+    lattice sizes uniform in {64,128,256,512}^2, masses log-uniform in
+    [1e-3, 1e-1], each request on one of `--serve-configs` resident
+    configurations per size (beta cycling 3, 6, 10).  Reports the closed-loop
+    capacity, then p50/p99 latency and solves/s for Poisson arrivals at
+    fractions of it, and checks a sample of results alone against the mix."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    from synth import gaussian_vectors, config_seed
+    jobs = [(L, c, a.serve_sweeps) for L in SERVE_SIZES for c in range(a.serve_configs)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, len(jobs))) as ex:
+        fields = list(ex.map(_serve_field, jobs))
+    print("gauge fields: %d in %.1f s" % (len(fields), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    import torch
+    from paper_1801_07823_amd import kdmg
+    kdmg.kdmg_init(0)
+    params = kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=COARSE_MAXIT, outer_maxit=500)
+    cfgs = []
+    t0 = time.perf_counter()
+    for L, c, beta, U, plaq in fields:
+        lat = kdmg.Lattice((L, L), U)
+        seed = config_seed(L, beta, c)
+        nc1 = (L // 8) * (L // 8) * 2 * NV
+        psi0 = [gaussian_vectors(NV, L * L, seed, tag=1), gaussian_vectors(NV2, nc1, seed, tag=2)]
+        h = kdmg.Hierarchy(lat, SERVE_M_SETUP, params, psi0)
+        cfgs.append((L, c, beta, lat, h))
+    torch.cuda.synchronize()
+    print("setup of %d hierarchies: %.1f s" % (len(cfgs), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    rng = np.random.default_rng(12345)
+
+    def make_requests(n, tag):
+        out = []
+        for i in range(n):
+            k = int(rng.integers(len(cfgs)))
+            m = float(np.exp(rng.uniform(math.log(1e-3), math.log(1e-1))))
+            L = cfgs[k][0]
+            out.append((k, m, L, tag * 100000 + i))
+        return out
+
+    def run(srv, ids, reqs, arrivals):
+        """arrivals: seconds after start (None: all at once).  Returns latencies,
+        infos, x (host), makespan."""
+        live, lat_s, infos, xs = {}, {}, {}, {}
+        start = time.perf_counter()
+        order = list(range(len(reqs)))
+
+        def drain(block):
+            for t in list(live):
+                r = srv.poll(t, wait=block)
+                if r is not None:
+                    i, xd = live.pop(t)
+                    st, info, times = r
+                    if st not in (kdmg.KDMG_OK,):
+                        raise RuntimeError("served solve failed: status %d" % st)
+                    lat_s[i], infos[i] = times[2], info[0]
+                    xs[i] = xd
+        for i in order:
+            if arrivals is not None:
+                while time.perf_counter() - start < arrivals[i]:
+                    drain(False)
+                    time.sleep(0.0005)
+            k, m, L, seed = reqs[i]
+            b = torch.from_numpy(gaussian_vectors(1, L * L, seed, tag=0)).to("cuda")
+            x = torch.zeros_like(b)
+            t = srv.submit(ids[k], m, b, x, 1, 1e-10, kdmg.KDMG_MIXED)
+            live[t] = (i, x)
+        while live:
+            drain(True)
+        return lat_s, infos, xs, time.perf_counter() - start
+
+    budget = int(a.serve_budget_gb * (1 << 30))
+    srv = kdmg.Server(a.serve_slots, budget)
+    ids = [srv.add_config(c[4]) for c in cfgs]
+    # warm-up: one request per configuration (tunes launch shapes, fills the pool)
+    warm = [(k, 0.01, cfgs[k][0], 900000 + k) for k in range(len(cfgs))]
+    t0 = time.perf_counter()
+    run(srv, ids, warm, None)
+    print("warm-up: %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    closed = make_requests(a.serve_closed, 1)
+    lat_c, info_c, _, span = run(srv, ids, closed, None)
+    cap = len(closed) / span
+    print("closed loop: %d requests in %.2f s -> %.2f solves/s" % (len(closed), span, cap), file=sys.stderr,
+          flush=True)
+    points = []
+    for frac in a.serve_fracs:
+        qps = frac * cap
+        reqs = make_requests(a.serve_requests, 2 + len(points))
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
+        lat_s, infos, xs, span = run(srv, ids, reqs, list(arr))
+        v = np.array([lat_s[i] for i in range(len(reqs))])
+        worst = max(infos[i]["true_rel_resid"] for i in range(len(reqs)))
+        by_size = {}
+        for i, (k, m, L, sd) in enumerate(reqs):
+            by_size.setdefault(L, []).append(lat_s[i])
+        points.append({"offered_qps": qps, "fraction_of_capacity": frac, "requests": len(reqs),
+                       "solves_per_s": len(reqs) / span, "p50_s": float(np.percentile(v, 50)),
+                       "p99_s": float(np.percentile(v, 99)), "max_true_rel_resid": worst,
+                       "p50_s_by_L": {str(L): float(np.percentile(t, 50)) for L, t in sorted(by_size.items())}})
+        print("qps %.2f: p50 %.3f s p99 %.3f s, %.2f solves/s" % (qps, points[-1]["p50_s"], points[-1]["p99_s"],
+                                                                 points[-1]["solves_per_s"]),
+              file=sys.stderr, flush=True)
+        last = (reqs, xs)
+    stats = srv.stats()
+    srv.close()
+    # a sample of the last mix, each solved alone on a one-worker server
+    reqs, xs = last
+    sample = list(range(min(a.serve_check, len(reqs))))
+    alone = kdmg.Server(1, budget)
+    ids1 = [alone.add_config(c[4]) for c in cfgs]
+    _, _, xs1, _ = run(alone, ids1, [reqs[i] for i in sample], None)
+    alone.close()
+    diffs = [float(torch.linalg.norm(xs[i] - xs1[j]) / torch.linalg.norm(xs1[j])) for j, i in enumerate(sample)]
+    res = {"metric": "served KD-MG solves, 2D U(1), L^2 in {64,128,256,512}^2, m log-uniform in [1e-3, 1e-1]",
+           "unit": "solves/s", "closed_loop_solves_per_s": cap, "points": points,
+           "slots": a.serve_slots, "hbm_budget_gb": a.serve_budget_gb, "configs": len(cfgs),
+           "configs_per_size": a.serve_configs, "heatbath_sweeps": a.serve_sweeps,
+           "setup_mass": SERVE_M_SETUP, "prec": "mixed", "tol": 1e-10,
+           "levels": "4x4 n_vec %d; 2x2 n_vec %d" % (NV, NV2),
+           "server": stats, "alone_vs_mix_max_rel_diff": max(diffs) if diffs else None,
+           "alone_vs_mix_identical": sum(d == 0.0 for d in diffs), "alone_checked": len(diffs)}
+    print(json.dumps(res))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-its", type=int, default=1)
+    ap.add_argument("--cpu-its", type=int, default=3)
+    ap.add_argument("--kernel-profile", action="store_true",
+                    help="short run for hardware-counter passes: a 64 MiB copy, then one mixed "
+                         "32-rhs solve cut off after one outer iteration; prints no metric")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-rhs", type=int, default=1)
     ap.add_argument("--cpu-child", type=int, default=None)
+    ap.add_argument("--serve", action="store_true", help="served-stream measurement instead of the bench line")
+    ap.add_argument("--serve-configs", type=int, default=8)
+    ap.add_argument("--serve-sweeps", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-closed", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-fracs", type=float, nargs="+", default=[0.5, 0.8])
+    ap.add_argument("--serve-check", type=int, default=8)
     a = ap.parse_args()
     if a.cpu_child is not None:
         cpu_baseline_child(a.cpu_child)
@@ -122,7 +295,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d, WORLD_SIZE %d)" % (a.gpus, world), file=sys.stderr)
         return 2
-    cpu = None if a.no_cpu else start_cpu_leg(a.cpu_its)
+    if a.serve:
+        return serve_main(a)
+    cpu = None if (a.no_cpu or a.kernel_profile) else start_cpu_leg(a.cpu_its)
 
     import numpy as np
     import torch
@@ -143,16 +318,31 @@ def main():
     print("setup %.2f s" % setup_s, file=sys.stderr, flush=True)
     b = torch.from_numpy(gaussian_vectors(NRHS, V, seed, tag=0)).to("cuda")
     x = torch.empty_like(b)
+    if a.kernel_profile:
+        # calibration copy of known size (reads 64 MiB, writes 64 MiB)
+        src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        p1 = kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=COARSE_MAXIT, outer_maxit=1)
+        h1 = kdmg.Hierarchy(lat, MASS, p1, psi0)
+        info, st = kdmg.kdmg_solve(h1, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        print("kernel-profile run done: 1 outer iteration, level-3 avg its %.1f"
+              % info[0]["level_avg_its"][1], flush=True)
+        return 0
     for i in range(a.warmup):
         info, _ = kdmg.kdmg_solve(h, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
         print("warmup %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    kdmg.kdmg_hierarchy_kernel_timing(h, 1)
     t0 = time.perf_counter()
     for i in range(a.steps):
         info, _ = kdmg.kdmg_solve(h, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
         print("step %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    cg_ms, cg_launches = kdmg.kdmg_hierarchy_kernel_timing(h, 0)
     value = NRHS * a.steps / T
     max_res = max(i["true_rel_resid"] for i in info)
     assert all(i["converged"] for i in info) and max_res <= 1e-10
@@ -169,7 +359,7 @@ def main():
         t64.append(time.perf_counter() - t0)
         info64.append(inf[0])
         print("fp64 rhs %d: %.2f s" % (r, t64[-1]), file=sys.stderr, flush=True)
-    fp64_rate = len(t64) / sum(t64)
+    fp64_rate = len(t64) / sum(t64) if t64 else None
 
     # fine Dslash bandwidth (algorithmic bytes / kernel time)
     vin64 = torch.randn((1, V), dtype=torch.complex128, device="cuda")
@@ -186,20 +376,32 @@ def main():
               "mixed_32rhs": {"GB/s": bytes_d32 / t_d32 / 1e9, "us": t_d32 * 1e6,
                               "bytes": bytes_d32}}
 
-    # dominant kernel: coarsest-level stencil apply (FP64, 32 rhs, 16^2 x 32 dofs)
+    # dominant kernel: the coarsest level's fused CGNE iteration (k_cgne_A then
+    # k_cgne_B, FP64, 32 rhs), timed with HIP events on the solve stream during
+    # the timed steps.  Algorithmic traffic per launch, averaged over the pair:
+    # the stencil Y (ndir blocks of ndc^2 complex per site) once, plus 5 (A:
+    # p, x r/w, r r/w) or 3 (B: r, p r/w) vector passes of nsites*ndc*nrhs.
     dims3, nd3 = h.level_info(2)
-    n3 = int(np.prod(dims3)) * nd3
-    c_in = torch.randn((NRHS, n3), dtype=torch.complex128, device="cuda")
-    c_out = torch.empty_like(c_in)
-    t_c = event_time(lambda: kdmg.kdmg_coarse_apply(h, 2, c_in, c_out, NRHS), 500)
     ns3 = int(np.prod(dims3))
-    flops = 8.0 * 5 * nd3 * nd3 * ns3 * NRHS
-    bytes_c = 16.0 * (5 * nd3 * nd3 * ns3 + 2 * NRHS * n3)
-    roofline = {"kernel": "k_capply<double> (coarsest A_hat_hat apply, 16^2 x %d dofs, 32 rhs)" % nd3,
-                "bound": "alu", "achieved": flops / t_c / 1e12, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": flops / t_c / 1e12 / FP64_PEAK_TFLOPS,
-                "traffic": None, "us_per_launch": t_c * 1e6, "flops_per_launch": flops,
-                "algorithmic_bytes_per_launch": bytes_c}
+    ndir = 2 * len(dims3) + 1
+    t_c = cg_ms * 1e-3 / max(cg_launches, 1)
+    y_bytes = 16.0 * ndir * nd3 * nd3 * ns3
+    vec_bytes = 16.0 * ns3 * nd3 * NRHS
+    bytes_c = y_bytes + 4.0 * vec_bytes
+    flops = 8.0 * ndir * nd3 * nd3 * ns3 * NRHS
+    t_hbm, t_mfma = bytes_c / (HBM_PEAK_GBS * 1e9), flops / (FP64_PEAK_TFLOPS * 1e12)
+    achieved_gbs = bytes_c / t_c / 1e9
+    roofline = {"kernel": "k_cgne_A / k_cgne_B (coarsest CGNE iteration on A_hat_hat, %dx%d sites x %d "
+                          "dofs, FP64, 32 rhs; MFMA f64 16x16x4)" % (dims3[0], dims3[1], nd3),
+                "bound": "hbm" if t_hbm >= t_mfma else "mfma",
+                "achieved": achieved_gbs if t_hbm >= t_mfma else flops / t_c / 1e12,
+                "peak": HBM_PEAK_GBS if t_hbm >= t_mfma else FP64_PEAK_TFLOPS,
+                "unit": "GB/s" if t_hbm >= t_mfma else "TFLOP/s",
+                "frac": (t_hbm if t_hbm >= t_mfma else t_mfma) / t_c,
+                "traffic": traffic_per_launch(),
+                "us_per_launch": t_c * 1e6, "launches_timed": cg_launches,
+                "algorithmic_bytes_per_launch": bytes_c, "flops_per_launch": flops,
+                "fp64_mfma_tflops": flops / t_c / 1e12}
 
     cpu_res = None
     if cpu is not None:
@@ -221,7 +423,7 @@ def main():
                        "level3_avg": [round(i["level_avg_its"][1], 2) for i in info]},
         "fp64_single_rhs": {"value": fp64_rate, "unit": "solves/s", "rhs_timed": len(t64),
                             "outer_its": [i["outer_its"] for i in info64],
-                            "mixed_over_fp64": value / fp64_rate},
+                            "mixed_over_fp64": value / fp64_rate if fp64_rate else None},
         "dslash": dslash,
         "roofline": roofline,
         "cpu_baseline": cpu_res,

@@ -207,6 +207,87 @@ kdmg_status kdmg_hierarchy_autotune(kdmg_hierarchy* h, int nrhs, kdmg_prec prec,
    `nrhs` right-hand sides (admission control). */
 kdmg_status kdmg_hierarchy_footprint(const kdmg_hierarchy* h, int nrhs, size_t* bytes);
 
+/* A hierarchy for the same gauge field at another mass (Sec. 4 setup, Table 1;
+   the coarse operators are the Galerkin products of Sec. 3).  The new
+   hierarchy shares `base`'s relaxed null vectors and prolongators (read-only;
+   `base` may be destroyed first, the shared parts live until the last user)
+   and Galerkin-builds its own coarse operators at `mass`.  The near-null
+   vectors are not relaxed again: the low modes of D are those of its
+   mass-independent anti-Hermitian part, so vectors relaxed at one mass serve
+   nearby masses.  Allocates the coarse operators; synchronises `stream`. */
+kdmg_status kdmg_hierarchy_at_mass(const kdmg_hierarchy* base, double mass, void* stream,
+                                   kdmg_hierarchy** out);
+
+/* Rebuild h's coarse operators in place at `mass`.  With base != NULL (and
+   != h), h first switches to base's lattice, null vectors and prolongators;
+   base must have the same lattice dimensions and level structure (else
+   KDMG_EINVAL).  Reuses h's storage and solve workspace: after the first
+   build of each shape it allocates nothing, so a serving loop can keep one
+   hierarchy per (slot, shape) and move it between gauge configurations and
+   masses.  KDMG_EBUSY while a solve on h is running.  Synchronises
+   `stream`. */
+kdmg_status kdmg_hierarchy_set_mass(kdmg_hierarchy* h, const kdmg_hierarchy* base, double mass,
+                                    void* stream);
+
+/* Measurement hook (not an operation of the method): HIP-event timing of the
+   two fused kernels of each coarsest-level CGNE iteration, on the solve's own
+   stream, during later kdmg_solve calls.  enable = 1 starts (and zeroes) the
+   counters, 0 stops, -1 leaves the state as it is.  `ms` (may be NULL)
+   receives the summed kernel time and `launches` (may be NULL) the number of
+   kernel launches it covers: within every run of launches between two host
+   polls, the first launch is excluded so host launch latency after a poll is
+   not counted.  Only FP64 coarsest levels (the fused CGNE) are timed. */
+kdmg_status kdmg_hierarchy_kernel_timing(kdmg_hierarchy* h, int enable, double* ms, long long* launches);
+
+/* ------------------------------------------------------------------ serving
+   A solve service over device-resident configurations.  Not an operation of
+   the paper: it runs the paper's solve (Sec. 4, Table 1) for a stream of
+   requests.  Requests are admitted in arrival order as soon as one of the
+   `slots` workers is free and the request's device footprint fits
+   `hbm_budget`; admitted requests run concurrently, one HIP stream per
+   worker.  A request runs on a pooled hierarchy of its shape moved onto its
+   configuration and mass (kdmg_hierarchy_set_mass), or on a new one
+   (kdmg_hierarchy_at_mass); idle pooled hierarchies are released when memory
+   is needed.  Results depend only on (configuration, mass, b, tol, prec):
+   the same alone and in any mix. */
+typedef struct kdmg_server kdmg_server;
+
+/* Create a service on the current device.  slots: 1..64 workers. */
+kdmg_status kdmg_server_create(int slots, size_t hbm_budget, kdmg_server** out);
+
+/* Register a configuration: a hierarchy from kdmg_hierarchy_build (setup
+   done, at any mass).  Not owned: it (and its lattice) must outlive the
+   server.  Returns its id (0, 1, ... in registration order). */
+kdmg_status kdmg_server_add_config(kdmg_server* s, const kdmg_hierarchy* base, int* config_id);
+
+/* Device bytes one request on this configuration holds while it runs
+   (coarse operators at its mass + solve workspace): the admission unit. */
+kdmg_status kdmg_server_request_bytes(kdmg_server* s, int config_id, int nrhs, kdmg_prec prec,
+                                      size_t* bytes);
+
+/* Queue a solve of D(U_config, mass) x = b for nrhs right-hand sides, layout
+   as kdmg_solve.  b and x are caller-owned device buffers that must stay
+   valid and untouched until the request is collected by kdmg_server_poll.
+   KDMG_ENOMEM if the request alone exceeds the budget. */
+kdmg_status kdmg_server_submit(kdmg_server* s, int config_id, double mass, const void* b, void* x,
+                               int nrhs, double tol, kdmg_prec prec, long long* ticket);
+
+/* done = 1 once the request has finished (wait != 0 blocks until then).
+   When done: *solve_status is kdmg_solve's status (kdmg_last_error() has its
+   message), info[0..nrhs) as from kdmg_solve, times[0..3) = seconds queued,
+   running, and in total (submit to finish); the ticket is then released. */
+kdmg_status kdmg_server_poll(kdmg_server* s, long long ticket, int wait, int* done,
+                             kdmg_status* solve_status, kdmg_solve_info* info, double* times);
+
+/* Counters: completed requests, running now, peak concurrently running,
+   device bytes reserved now (running + pooled idle) and at peak. */
+kdmg_status kdmg_server_stats(kdmg_server* s, long long* completed, int* running, int* peak_running,
+                              size_t* allocated, size_t* peak_allocated);
+
+/* Finish the running requests, drop queued ones (their poll reports
+   KDMG_EBUSY), free pooled hierarchies and streams. */
+void kdmg_server_destroy(kdmg_server* s);
+
 const char* kdmg_status_string(kdmg_status s);
 const char* kdmg_last_error(void);
 

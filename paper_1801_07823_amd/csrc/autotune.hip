@@ -105,7 +105,7 @@ void autotune_level(const CoarseLevel& L, int nrhs, bool fp32, hipStream_t st) {
   const bool verbose = e && e[0] == '1';
   TileShape best = fp32 ? tune_one<float, float>(L, nrhs, st, verbose) : tune_one<double, double>(L, nrhs, st, verbose);
   std::lock_guard<std::mutex> g(*L.tune_mu);
-  L.tuned[key] = best;
+  L.tuned.emplace(key, best);  // a concurrent tuner that finished first wins
 }
 
 bool autotune_enabled() {

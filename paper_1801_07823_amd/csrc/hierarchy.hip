@@ -68,9 +68,9 @@ void run_blockqr(const Ctx& c, c64* P, const c64* V, long n, const std::vector<i
 
 void finish_coarse_level(const Ctx& c, CoarseLevel& L) {
   const long nbytes = (long)L.ndir * L.nsites * L.ndc * L.ndc;
-  L.Yd64.alloc(sizeof(c64) * nbytes);
-  L.Yt32.alloc(sizeof(c32) * nbytes);
-  L.Yd32.alloc(sizeof(c32) * nbytes);
+  if (!L.Yd64.p) L.Yd64.alloc(sizeof(c64) * nbytes);
+  if (!L.Yt32.p) L.Yt32.alloc(sizeof(c32) * nbytes);
+  if (!L.Yd32.p) L.Yd32.alloc(sizeof(c32) * nbytes);
   hipLaunchKernelGGL(k_dagger_build<double>, dim3(cdiv(nbytes, 256)), dim3(256), 0, c.st,
                      L.Yd64.as<c64>(), L.Yt64.as<c64>(), L.nbr.as<int>(), L.nsites, L.ndc, L.ndir);
   KDMG_LAUNCH_CHECK();
@@ -121,6 +121,59 @@ void relax(const Ctx& c, c64* V, long n, int nv, double tol, int maxit, NormalF 
 void upload(const Ctx& c, DevBuf& dst, const double* host, size_t bytes) {
   dst.alloc(bytes);
   KDMG_HIP(hipMemcpyAsync(dst.p, host, bytes, hipMemcpyHostToDevice, c.st));
+}
+
+// Level-1 Galerkin operator at the hierarchy's mass (Sec. 3, Sec. 4):
+// W = B^-1 P block by block, then A_hat = 1 + P^dag C W.  Storage is reused
+// when the level already exists (a rebuild at another mass).
+void galerkin_level1(kdmg_hierarchy& h, const Ctx& c) {
+  const kdmg_lattice& lat = *h.lat;
+  const Geo2& g = lat.g;
+  const Transfer& T = h.T[0];
+  const int nv = T.nv;
+  const long f = 2 * g.half;
+  if (!h.gal_w.p) h.gal_w.alloc(sizeof(c64) * f * 2 * nv);
+  hipLaunchKernelGGL((k_galerkin_w1<double>), dim3(cdiv(g.Nb2, 256), nv, 2), dim3(256), 0, c.st,
+                     h.gal_w.as<c64>(), T.P64.as<c64>(), lat.links64.as<c64>(), g, nv, h.mass);
+  KDMG_LAUNCH_CHECK();
+  CoarseLevel& C1 = h.L[1];
+  if (!C1.Yt64.p) {
+    C1.nd = 2;
+    C1.dims[0] = T.a2.Ncx;
+    C1.dims[1] = T.a2.Nct;
+    C1.ndc = 2 * nv;
+    make_nbr(C1);
+    C1.Yt64.alloc(sizeof(c64) * (size_t)C1.ndir * C1.nsites * C1.ndc * C1.ndc);
+  }
+  const int nZ = T.a2.Ncx * T.a2.Nct;
+  const int thr = C1.ndc * C1.ndc > 1024 ? 1024 : C1.ndc * C1.ndc;
+  hipLaunchKernelGGL((k_galerkin1<double>), dim3(nZ), dim3(thr), 0, c.st, C1.Yt64.as<c64>(),
+                     T.P64.as<c64>(), h.gal_w.as<c64>(), lat.links64.as<c64>(), g, T.a2);
+  KDMG_LAUNCH_CHECK();
+  finish_coarse_level(c, C1);
+}
+
+// Level-(k+1) Galerkin operator P^dag A_hat_k P from level k's operator.
+void galerkin_coarse(kdmg_hierarchy& h, int k, const Ctx& c) {
+  const CoarseLevel& Lf = h.L[k];
+  CoarseLevel& Lc = h.L[k + 1];
+  const Transfer& T = h.T[k];
+  const kdmg_level_params& lp = h.params.lvl[k];
+  if (!Lc.Yt64.p) {
+    Lc.nd = Lf.nd;
+    for (int mu = 0; mu < Lf.nd; ++mu) Lc.dims[mu] = Lf.dims[mu] / lp.agg[mu];
+    Lc.ndc = 2 * T.nv;
+    make_nbr(Lc);
+    Lc.Yt64.alloc(sizeof(c64) * (size_t)Lc.ndir * Lc.nsites * Lc.ndc * Lc.ndc);
+  }
+  const size_t smem = sizeof(c64) * (size_t)T.ndf * Lc.ndc;
+  KDMG_CHECK(smem <= 65536 && Lc.ndc * Lc.ndc <= 1024 && Lf.ndir <= 9, KDMG_EUNSUPPORTED,
+             "coarse Galerkin shape not supported");
+  hipLaunchKernelGGL(k_galerkin_c, dim3(T.nZ), dim3(Lc.ndc * Lc.ndc), smem, c.st, Lc.Yt64.as<c64>(),
+                     Lf.Yt64.as<c64>(), T.P64.as<c64>(), Lf.nbr.as<int>(), T.gdir.as<int>(),
+                     T.children.as<int>(), T.nchild, T.nsf, T.ndf, T.nZ, T.nv, Lf.ndir);
+  KDMG_LAUNCH_CHECK();
+  finish_coarse_level(c, Lc);
 }
 
 // fine lattice -> first coarse lattice (2D U(1))
@@ -176,25 +229,9 @@ void build_level1(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int relax
   }
   T.P64.alloc(sizeof(c64) * f * nv);
   run_blockqr(c, T.P64.as<c64>(), Vb.as<c64>(), f, rows, nZ * 2, nrows, nv);
-  // Galerkin: W = B^-1 P, then A_hat = 1 + P^dag C W
-  DevBuf W(sizeof(c64) * f * 2 * nv);
-  hipLaunchKernelGGL((k_galerkin_w1<double>), dim3(cdiv(g.Nb2, 256), nv, 2), dim3(256), 0, c.st,
-                     W.as<c64>(), T.P64.as<c64>(), L, g, nv, m);
-  KDMG_LAUNCH_CHECK();
-  CoarseLevel& C1 = h.L[1];
-  C1.nd = 2;
-  C1.dims[0] = T.a2.Ncx;
-  C1.dims[1] = T.a2.Nct;
-  C1.ndc = 2 * nv;
-  make_nbr(C1);
-  C1.Yt64.alloc(sizeof(c64) * (size_t)C1.ndir * C1.nsites * C1.ndc * C1.ndc);
-  const int thr = C1.ndc * C1.ndc > 1024 ? 1024 : C1.ndc * C1.ndc;
-  hipLaunchKernelGGL((k_galerkin1<double>), dim3(nZ), dim3(thr), 0, c.st, C1.Yt64.as<c64>(),
-                     T.P64.as<c64>(), W.as<c64>(), L, g, T.a2);
-  KDMG_LAUNCH_CHECK();
-  finish_coarse_level(c, C1);
   T.P16.alloc(sizeof(c16) * f * nv);
   convert<_Float16, double>(T.P16.as<c16>(), T.P64.as<c64>(), f * nv, 1, nullptr, c.st);
+  galerkin_level1(h, c);
   KDMG_HIP(hipStreamSynchronize(c.st));
 }
 
@@ -215,13 +252,12 @@ void build_coarse(kdmg_hierarchy& h, int k, const Ctx& c, const double* psi0, in
   const int ndf = Lf.ndc, nvp = ndf / 2;
   KDMG_CHECK(nv >= 1 && nv <= nchild * nvp && 2 * nv <= 32, KDMG_EINVAL,
              "coarse n_vec must fit the aggregate and 2 n_vec <= 32");
-  Lc.ndc = 2 * nv;
-  make_nbr(Lc);
   Transfer& T = h.T[k];
   T.k = k;
   T.nv = nv;
   T.nchild = nchild;
-  T.nZ = Lc.nsites;
+  T.nZ = 1;
+  for (int mu = 0; mu < nd; ++mu) T.nZ *= Lc.dims[mu];
   T.nsf = Lf.nsites;
   T.ndf = ndf;
   const long n = Lf.n();
@@ -248,10 +284,10 @@ void build_coarse(kdmg_hierarchy& h, int k, const Ctx& c, const double* psi0, in
   }
   T.children.alloc(sizeof(int) * children.size());
   T.parent.alloc(sizeof(int) * parent.size());
-  DevBuf dgdir(sizeof(int) * gdir.size());
+  T.gdir.alloc(sizeof(int) * gdir.size());
   KDMG_HIP(hipMemcpy(T.children.p, children.data(), T.children.bytes, hipMemcpyHostToDevice));
   KDMG_HIP(hipMemcpy(T.parent.p, parent.data(), T.parent.bytes, hipMemcpyHostToDevice));
-  KDMG_HIP(hipMemcpy(dgdir.p, gdir.data(), dgdir.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(T.gdir.p, gdir.data(), T.gdir.bytes, hipMemcpyHostToDevice));
   DevBuf Vb;
   upload(c, Vb, psi0, sizeof(c64) * n * nv);
   if (!relaxed) {
@@ -276,17 +312,9 @@ void build_coarse(kdmg_hierarchy& h, int k, const Ctx& c, const double* psi0, in
     }
   T.P64.alloc(sizeof(c64) * n * nv);
   run_blockqr(c, T.P64.as<c64>(), Vb.as<c64>(), n, rows, T.nZ * 2, nrows, nv);
-  Lc.Yt64.alloc(sizeof(c64) * (size_t)Lc.ndir * Lc.nsites * Lc.ndc * Lc.ndc);
-  const size_t smem = sizeof(c64) * (size_t)ndf * Lc.ndc;
-  KDMG_CHECK(smem <= 65536 && Lc.ndc * Lc.ndc <= 1024 && Lf.ndir <= 9, KDMG_EUNSUPPORTED,
-             "coarse Galerkin shape not supported");
-  hipLaunchKernelGGL(k_galerkin_c, dim3(T.nZ), dim3(Lc.ndc * Lc.ndc), smem, c.st, Lc.Yt64.as<c64>(),
-                     Lf.Yt64.as<c64>(), T.P64.as<c64>(), Lf.nbr.as<int>(), dgdir.as<int>(),
-                     T.children.as<int>(), nchild, T.nsf, ndf, T.nZ, nv, Lf.ndir);
-  KDMG_LAUNCH_CHECK();
-  finish_coarse_level(c, Lc);
   T.P16.alloc(sizeof(c16) * n * nv);
   convert<_Float16, double>(T.P16.as<c16>(), T.P64.as<c64>(), n * nv, 1, nullptr, c.st);
+  galerkin_coarse(h, k, c);
   KDMG_HIP(hipStreamSynchronize(c.st));
 }
 
@@ -294,6 +322,8 @@ void build_coarse(kdmg_hierarchy& h, int k, const Ctx& c, const double* psi0, in
 
 kdmg_hierarchy::~kdmg_hierarchy() {
   if (ws) kdmg::destroy_ws(ws);
+  if (timer.e0) (void)hipEventDestroy(timer.e0);
+  if (timer.e1) (void)hipEventDestroy(timer.e1);
 }
 
 extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass,
@@ -325,6 +355,82 @@ extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass
   for (int k = 1; k < h->nlevels - 1; ++k) build_coarse(*h, k, ca.c, psi0_host[k], relaxed);
   KDMG_HIP(hipStreamSynchronize((hipStream_t)stream));
   *out = h.release();
+  KDMG_API_END
+}
+
+namespace {
+
+bool same_shape(const kdmg_hierarchy& a, const kdmg_hierarchy& b) {
+  if (a.nlevels != b.nlevels || a.lat->nd != b.lat->nd || a.lat->nc != b.lat->nc) return false;
+  for (int mu = 0; mu < 4; ++mu)
+    if (a.lat->dims[mu] != b.lat->dims[mu]) return false;
+  for (int k = 0; k < a.nlevels - 1; ++k) {
+    if (a.params.lvl[k].nvec != b.params.lvl[k].nvec) return false;
+    for (int mu = 0; mu < 4; ++mu)
+      if (a.params.lvl[k].agg[mu] != b.params.lvl[k].agg[mu]) return false;
+  }
+  return true;
+}
+
+// Galerkin-build every coarse operator of h at h.mass from its transfers.
+void rebuild_coarse_ops(kdmg_hierarchy& h, hipStream_t st) {
+  Ctx c{};
+  c.st = st;
+  galerkin_level1(h, c);
+  for (int k = 1; k < h.nlevels - 1; ++k) galerkin_coarse(h, k, c);
+  KDMG_HIP(hipStreamSynchronize(st));
+}
+
+void copy_tuned(const kdmg_hierarchy& from, kdmg_hierarchy& to) {
+  for (int l = 1; l < from.nlevels; ++l) {
+    std::map<long, TileShape> t;
+    {
+      std::lock_guard<std::mutex> g(*from.L[l].tune_mu);
+      t = from.L[l].tuned;
+    }
+    std::lock_guard<std::mutex> g(*to.L[l].tune_mu);
+    to.L[l].tuned = t;  // the base's launch shapes, so results depend on (base, mass, b) only
+  }
+}
+
+}  // namespace
+
+extern "C" kdmg_status kdmg_hierarchy_at_mass(const kdmg_hierarchy* base, double mass, void* stream,
+                                              kdmg_hierarchy** out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(base && out, KDMG_EINVAL, "kdmg_hierarchy_at_mass: null argument");
+  *out = nullptr;
+  KDMG_CHECK(mass > 0.0, KDMG_EINVAL, "mass must be positive");
+  auto h = std::make_unique<kdmg_hierarchy>();
+  h->lat = base->lat;
+  h->mass = mass;
+  h->params = base->params;
+  h->nlevels = base->nlevels;
+  h->T = base->T;
+  h->derived = true;
+  h->L.resize(h->nlevels);
+  rebuild_coarse_ops(*h, (hipStream_t)stream);
+  copy_tuned(*base, *h);
+  *out = h.release();
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_set_mass(kdmg_hierarchy* h, const kdmg_hierarchy* base, double mass,
+                                               void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h, KDMG_EINVAL, "kdmg_hierarchy_set_mass: null hierarchy");
+  KDMG_CHECK(mass > 0.0, KDMG_EINVAL, "mass must be positive");
+  if (base && base != h) {
+    KDMG_CHECK(same_shape(*h, *base), KDMG_EINVAL,
+               "kdmg_hierarchy_set_mass: base has a different lattice shape or level structure");
+    KDMG_CHECK(!ws_busy(h->ws), KDMG_EBUSY, "hierarchy busy");
+    h->lat = base->lat;
+    h->T = base->T;
+    h->derived = true;
+    copy_tuned(*base, *h);
+  }
+  h->mass = mass;
+  rebuild_coarse_ops(*h, (hipStream_t)stream);
   KDMG_API_END
 }
 

@@ -5,6 +5,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -149,11 +150,21 @@ struct Transfer {
   int nchild = 0, nZ = 0, nsf = 0, ndf = 0;  // k >= 1
   DevBuf P64, P16;               // prolongator values [ndof_k][nv]
   DevBuf children, parent;       // k >= 1: int [nZ][nchild], int [nsf]
+  DevBuf gdir;                   // k >= 1: int [ndir][nsf], coarse direction of each fine hop (0: internal)
   DevBuf relaxed;                // relaxed null vectors, FP64, internal layout [nv][n_k]
   long nfine = 0;                // entries per null vector (internal layout)
   size_t bytes() const {
-    return P64.bytes + P16.bytes + children.bytes + parent.bytes + relaxed.bytes;
+    return P64.bytes + P16.bytes + children.bytes + parent.bytes + gdir.bytes + relaxed.bytes;
   }
+};
+
+// The transfers of a hierarchy, shared (read-only) between a hierarchy and
+// the hierarchies derived from it at other masses.
+struct TransferSet {
+  std::shared_ptr<std::vector<Transfer>> p = std::make_shared<std::vector<Transfer>>();
+  Transfer& operator[](size_t i) const { return (*p)[i]; }
+  void resize(size_t n) { p->resize(n); }
+  size_t size() const { return p->size(); }
 };
 
 void autotune_level(const CoarseLevel& L, int nrhs, bool fp32, hipStream_t st);
@@ -161,6 +172,8 @@ bool autotune_enabled();
 
 struct SolveWS;  // solver workspace (solver.hip)
 void destroy_ws(SolveWS*);
+bool ws_busy(const SolveWS*);
+size_t derived_footprint(const kdmg_hierarchy& base, int nrhs, kdmg_prec prec);
 
 }  // namespace kdmg
 
@@ -169,13 +182,24 @@ struct kdmg_hierarchy {
   double mass = 0.0;
   kdmg_mg_params params{};
   int nlevels = 0;
-  std::vector<kdmg::Transfer> T;
+  kdmg::TransferSet T;                // null vectors and prolongators (mass independent)
+  bool derived = false;               // T borrowed from another hierarchy (kdmg_hierarchy_at_mass)
   std::vector<kdmg::CoarseLevel> L;   // index by level; L[0] unused
+  kdmg::DevBuf gal_w;                 // Galerkin scratch W = B^-1 P (level 1), kept for rebuilds
   kdmg::SolveWS* ws = nullptr;
+  // event timing of the coarsest CGNE kernels (kdmg_hierarchy_kernel_timing)
+  struct KTimer {
+    bool on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double ms = 0.0;
+    long long launches = 0;
+  } timer;
   ~kdmg_hierarchy();
+  // device bytes owned by this hierarchy (borrowed transfers not included)
   size_t bytes() const {
-    size_t b = 0;
-    for (auto& t : T) b += t.bytes();
+    size_t b = gal_w.bytes;
+    if (!derived)
+      for (size_t k = 0; k < T.size(); ++k) b += T[k].bytes();
     for (auto& l : L) b += l.bytes();
     return b;
   }
@@ -213,8 +237,19 @@ inline void capply_shape(int ndc, int nrhs, int& js, int& rpb) {
   } while (0)
 
 // Raise the dynamic-LDS limit of a kernel once (needed above 64 KB).
+// Raise a kernel's dynamic-LDS limit above the 64 KB default, once per
+// (device, kernel, size); the attribute call is not repeated on every launch.
 inline void ensure_smem(const void* fn, size_t bytes) {
-  if (bytes > 65536) KDMG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  if (bytes <= 65536) return;
+  int dev = 0;
+  KDMG_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> done;
+  std::lock_guard<std::mutex> g(mu);
+  size_t& d = done[{dev, fn}];
+  if (d >= bytes) return;
+  KDMG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  d = bytes;
 }
 
 inline TileArgs tile_args(const TileShape& s) { return TileArgs{s.RT, s.TI, s.TR, s.KS, s.MT, s.NT}; }

@@ -49,6 +49,7 @@ struct SolveWS {
 };
 
 void destroy_ws(SolveWS* w) { delete w; }
+bool ws_busy(const SolveWS* w) { return w && w->busy.load() != 0; }
 
 namespace {
 
@@ -83,7 +84,7 @@ struct OpResidNorm {  // ||r||^2 -> out[r]
 // Fused CGNE on the coarsest level: two kernels per iteration (see
 // coarse_fast.cuh), host reads the active flags every `poll` iterations.
 int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c64* b, c64* x, c64* r,
-               c64* p, double tol, int maxit, const int* parent, int poll) {
+               c64* p, double tol, int maxit, const int* parent, int poll, kdmg_hierarchy::KTimer* tm) {
   CgneState s;
   s.rr = W.cg_rr.as<double>();
   s.target = W.cg_target.as<double>();
@@ -112,6 +113,22 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
   KDMG_TILE_DISPATCH(sh, KDMG_L_INIT2);
 #undef KDMG_L_INIT2
   KDMG_LAUNCH_CHECK();
+  // timing: e0 after the first launch of a run between polls, e1 at the poll;
+  // the poll's own stream synchronisation completes e1
+  const bool timed = tm && tm->on;
+  int run_launches = 0;
+  auto mark_end = [&]() {
+    if (timed && run_launches >= 2) KDMG_HIP(hipEventRecord(tm->e1, c.st));
+  };
+  auto close_run = [&]() {
+    if (timed && run_launches >= 2) {
+      float ms = 0.f;
+      KDMG_HIP(hipEventElapsedTime(&ms, tm->e0, tm->e1));
+      tm->ms += ms;
+      tm->launches += run_launches - 1;
+    }
+    run_launches = 0;
+  };
   int k = 0;
   for (; k < maxit; ++k) {
 #define KDMG_L_A(C_, TI_, TR_, YL_)                                                                          \
@@ -129,11 +146,26 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
                        L.ndir, ta, nrhs, s, k);                                                         \
   }
     KDMG_TILE_DISPATCH(sh, KDMG_L_A);
+    if (timed && run_launches == 0) KDMG_HIP(hipEventRecord(tm->e0, c.st));
     KDMG_TILE_DISPATCH(sh, KDMG_L_B);
 #undef KDMG_L_A
 #undef KDMG_L_B
     KDMG_LAUNCH_CHECK();
-    if ((k + 1) % poll == 0 && !any_active(c, s.act + ((k + 1) & 1) * nrhs, nrhs)) { ++k; break; }
+    run_launches += 2;
+    if ((k + 1) % poll == 0) {
+      mark_end();
+      const bool more = any_active(c, s.act + ((k + 1) & 1) * nrhs, nrhs);
+      close_run();
+      if (!more) {
+        ++k;
+        break;
+      }
+    }
+  }
+  if (timed && run_launches) {
+    mark_end();
+    KDMG_HIP(hipStreamSynchronize(c.st));
+    close_run();
   }
   return k;
 }
@@ -230,7 +262,7 @@ class Runner {
       if (l == h_.nlevels - 1) {
         if constexpr (sizeof(T) == 8) {
           cgne_fused(c_, h_.L[l], L, nrhs_, b, x, r, L.v<T>(L.p), P.coarse_tol, P.coarse_maxit, parent,
-                     poll_);
+                     poll_, &h_.timer);
         } else {
           auto opd = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, true); };
           auto opn = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, false); };
@@ -370,6 +402,15 @@ size_t ws_bytes_estimate(const kdmg_hierarchy& h, int nrhs, kdmg_prec prec) {
 }
 
 }  // namespace
+
+// Device bytes a hierarchy derived from `base` (kdmg_hierarchy_at_mass) holds
+// once it has solved `nrhs` right-hand sides at `prec`.
+size_t derived_footprint(const kdmg_hierarchy& base, int nrhs, kdmg_prec prec) {
+  size_t b = base.gal_w.bytes + ws_bytes_estimate(base, nrhs, prec);
+  for (const auto& l : base.L) b += l.bytes();
+  return b;
+}
+
 }  // namespace kdmg
 
 extern "C" kdmg_status kdmg_hierarchy_footprint(const kdmg_hierarchy* h, int nrhs, size_t* bytes) {
@@ -387,7 +428,14 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   KDMG_CHECK(tol > 0.0 && tol < 1.0, KDMG_EINVAL, "kdmg_solve: tol must be in (0, 1)");
   KDMG_CHECK(prec == KDMG_FP64 || prec == KDMG_MIXED, KDMG_EINVAL, "kdmg_solve: bad precision");
   hipStream_t st = (hipStream_t)stream;
-  if (!h->ws || h->ws->nrhs != nrhs || h->ws->prec != prec || h->ws->ctx.c.st != st) {
+  if (h->ws && h->ws->nrhs == nrhs && h->ws->prec == prec && h->ws->ctx.c.st != st) {
+    // same shape on another stream: keep the buffers, move the work
+    // (kdmg_solve synchronises its stream before returning, so nothing of
+    // the previous call is still in flight on the old stream)
+    KDMG_CHECK(h->ws->busy.load() == 0, KDMG_EBUSY, "hierarchy busy");
+    h->ws->ctx.c.st = st;
+  }
+  if (!h->ws || h->ws->nrhs != nrhs || h->ws->prec != prec) {
     KDMG_CHECK(!h->ws || h->ws->busy.load() == 0, KDMG_EBUSY, "hierarchy busy");
     if (h->ws) destroy_ws(h->ws);
     h->ws = nullptr;
@@ -469,5 +517,24 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   }
   (void)its;
   if (!all) throw Error(KDMG_ENOCONV, "kdmg_solve: some right-hand sides did not converge");
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_kernel_timing(kdmg_hierarchy* h, int enable, double* ms,
+                                                    long long* launches) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && enable >= -1 && enable <= 1, KDMG_EINVAL, "kdmg_hierarchy_kernel_timing: bad argument");
+  auto& t = h->timer;
+  if (enable == 1) {
+    if (!t.e0) KDMG_HIP(hipEventCreate(&t.e0));
+    if (!t.e1) KDMG_HIP(hipEventCreate(&t.e1));
+    t.ms = 0.0;
+    t.launches = 0;
+    t.on = true;
+  } else if (enable == 0) {
+    t.on = false;
+  }
+  if (ms) *ms = t.ms;
+  if (launches) *launches = t.launches;
   KDMG_API_END
 }

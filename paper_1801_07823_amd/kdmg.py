@@ -78,6 +78,18 @@ _SIGS = {
     "kdmg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(kdmg_solve_info), _P]),
     "kdmg_hierarchy_footprint": (_I, [_P, _I, ctypes.POINTER(_S)]),
     "kdmg_hierarchy_autotune": (_I, [_P, _I, _I, _P]),
+    "kdmg_hierarchy_at_mass": (_I, [_P, _D, _P, ctypes.POINTER(_P)]),
+    "kdmg_hierarchy_set_mass": (_I, [_P, _P, _D, _P]),
+    "kdmg_hierarchy_kernel_timing": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
+    "kdmg_server_create": (_I, [_I, _S, ctypes.POINTER(_P)]),
+    "kdmg_server_add_config": (_I, [_P, _P, ctypes.POINTER(_I)]),
+    "kdmg_server_request_bytes": (_I, [_P, _I, _I, _I, ctypes.POINTER(_S)]),
+    "kdmg_server_submit": (_I, [_P, _I, _D, _P, _P, _I, _D, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "kdmg_server_poll": (_I, [_P, ctypes.c_longlong, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                              _P, ctypes.POINTER(_D)]),
+    "kdmg_server_stats": (_I, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_I),
+                               ctypes.POINTER(_I), ctypes.POINTER(_S), ctypes.POINTER(_S)]),
+    "kdmg_server_destroy": (None, [_P]),
     "kdmg_status_string": (ctypes.c_char_p, [_I]),
     "kdmg_last_error": (ctypes.c_char_p, []),
 }
@@ -155,7 +167,7 @@ class Lattice:
         return b.value
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.kdmg_lattice_destroy(self.handle)
             self.handle = None
 
@@ -182,6 +194,7 @@ class Hierarchy:
         """psi0: list of complex128 numpy arrays [nvec, ndof_k] per coarsening."""
         self.lat = lat
         self.params = params
+        self.mass = mass
         self._psi0 = [np.ascontiguousarray(v, dtype=np.complex128) for v in psi0]
         ptrs = (_P * len(self._psi0))(*[v.ctypes.data_as(_P) for v in self._psi0])
         h = _P()
@@ -189,6 +202,28 @@ class Hierarchy:
                                          1 if relaxed else 0, _stream(stream), ctypes.byref(h)))
         self.handle = h
         self.nlevels = params.nlevels
+
+    @classmethod
+    def _wrap(cls, handle, lat, params, mass):
+        self = cls.__new__(cls)
+        self.lat, self.params, self.mass = lat, params, mass
+        self.handle = handle
+        self.nlevels = params.nlevels
+        return self
+
+    def at_mass(self, mass, stream=None):
+        """kdmg_hierarchy_at_mass: same null vectors and P, coarse operators at `mass`."""
+        h = _P()
+        _check(_lib.kdmg_hierarchy_at_mass(self.handle, mass, _stream(stream), ctypes.byref(h)))
+        return Hierarchy._wrap(h, self.lat, self.params, mass)
+
+    def set_mass(self, mass, base=None, stream=None):
+        """kdmg_hierarchy_set_mass: rebuild in place (optionally onto `base`)."""
+        _check(_lib.kdmg_hierarchy_set_mass(self.handle, base.handle if base is not None else None,
+                                            mass, _stream(stream)))
+        if base is not None:
+            self.lat = base.lat
+        self.mass = mass
 
     def level_info(self, level):
         dims = (_I * 4)()
@@ -227,7 +262,7 @@ class Hierarchy:
         return b.value
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.kdmg_hierarchy_destroy(self.handle)
             self.handle = None
 
@@ -249,9 +284,77 @@ def kdmg_hierarchy_autotune(h, nrhs, prec=KDMG_FP64, stream=None):
     _check(_lib.kdmg_hierarchy_autotune(h.handle, nrhs, prec, _stream(stream)))
 
 
+def kdmg_hierarchy_kernel_timing(h, enable=-1):
+    """enable: 1 start (zeroes the counters), 0 stop, -1 read only -> (ms, launches)."""
+    ms = _D()
+    n = ctypes.c_longlong()
+    _check(_lib.kdmg_hierarchy_kernel_timing(h.handle, enable, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 def kdmg_solve(h, b, x, nrhs, tol=1e-10, prec=KDMG_FP64, stream=None, raise_on_noconv=True):
     info = (kdmg_solve_info * nrhs)()
     st = _lib.kdmg_solve(h.handle, _ptr(b), _ptr(x), nrhs, tol, prec, info, _stream(stream))
     if st != KDMG_OK and (st != KDMG_ENOCONV or raise_on_noconv):
         _check(st)
     return [i.as_dict() for i in info], st
+
+
+class Server:
+    """kdmg_server_*: continuous-batching solve service over resident configurations.
+
+    Keeps the caller's b / x tensors alive until their request is collected."""
+
+    def __init__(self, slots, hbm_budget):
+        h = _P()
+        _check(_lib.kdmg_server_create(slots, hbm_budget, ctypes.byref(h)))
+        self.handle = h
+        self._configs = []
+        self._live = {}
+
+    def add_config(self, hierarchy):
+        cid = _I()
+        _check(_lib.kdmg_server_add_config(self.handle, hierarchy.handle, ctypes.byref(cid)))
+        self._configs.append(hierarchy)
+        return cid.value
+
+    def request_bytes(self, config_id, nrhs=1, prec=KDMG_MIXED):
+        b = _S()
+        _check(_lib.kdmg_server_request_bytes(self.handle, config_id, nrhs, prec, ctypes.byref(b)))
+        return b.value
+
+    def submit(self, config_id, mass, b, x, nrhs=1, tol=1e-10, prec=KDMG_MIXED):
+        t = ctypes.c_longlong()
+        _check(_lib.kdmg_server_submit(self.handle, config_id, mass, _ptr(b), _ptr(x), nrhs, tol, prec,
+                                       ctypes.byref(t)))
+        self._live[t.value] = (b, x, nrhs)
+        return t.value
+
+    def poll(self, ticket, wait=False):
+        """None while running, else (status, [info dicts], (queued_s, run_s, total_s))."""
+        nrhs = self._live[ticket][2]
+        done, st = _I(), _I()
+        info = (kdmg_solve_info * nrhs)()
+        times = (_D * 3)()
+        _check(_lib.kdmg_server_poll(self.handle, ticket, 1 if wait else 0, ctypes.byref(done),
+                                     ctypes.byref(st), ctypes.cast(info, _P), times))
+        if not done.value:
+            return None
+        del self._live[ticket]
+        return st.value, [i.as_dict() for i in info], tuple(times)
+
+    def stats(self):
+        c, r, pr = ctypes.c_longlong(), _I(), _I()
+        a, pa = _S(), _S()
+        _check(_lib.kdmg_server_stats(self.handle, ctypes.byref(c), ctypes.byref(r), ctypes.byref(pr),
+                                      ctypes.byref(a), ctypes.byref(pa)))
+        return {"completed": c.value, "running": r.value, "peak_running": pr.value,
+                "allocated": a.value, "peak_allocated": pa.value}
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.kdmg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

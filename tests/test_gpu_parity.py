@@ -368,3 +368,54 @@ def test_batched_solve_mfma_path(K, prec):
         assert info[r]["converged"]
         assert np.linalg.norm(b[r] - D @ xs[r]) / np.linalg.norm(b[r]) <= 1e-10
         assert np.linalg.norm(xs[r] - xd[r]) / np.linalg.norm(xd[r]) < 1e-8
+
+
+def test_hierarchy_at_mass_and_rebind(K):
+    """kdmg_hierarchy_at_mass / kdmg_hierarchy_set_mass: coarse operators
+    Galerkin-built at a new mass from the same null vectors equal the oracle's
+    (built from those vectors at that mass) to rounding; moving back to the
+    first mass reproduces the first operators bit for bit; moving onto another
+    configuration of the same shape equals that configuration's oracle; the
+    moved hierarchy solves to 1e-10 and matches dense LU."""
+    dims, beta, m0, m1 = (32, 32), 6.0, 0.02, 0.15
+    levels = [((2, 2), 8), ((2, 2), 8)]
+    olevels = MGParams(levels=[LevelParams(a, nv) for a, nv in levels])
+    olat = OLattice(dims)
+    U = field(dims, beta)
+    oh0, _ = oracle_setup(dims, U, m0, levels, 21)
+    lat = K.Lattice(dims, U)
+    base = K.Hierarchy(lat, m0, gpu_params(K, levels), oh0.nullvecs, relaxed=True)
+    oh1 = OHierarchy(olat, U, m1, olevels, [("relaxed", v) for v in oh0.nullvecs])
+    h = base.at_mass(m1)
+    for k in (1, 2):
+        dims_c, _ = h.level_info(k)
+        assert relerr(assemble(h.coarse_op(k), dims_c), oh1.ops[k].toarray()) < 1e-11
+    h.set_mass(m0)
+    for k in (1, 2):
+        assert np.array_equal(h.coarse_op(k), base.coarse_op(k))
+    U2 = field(dims, beta, seed=8)
+    oh2, _ = oracle_setup(dims, U2, m0, levels, 22)
+    lat2 = K.Lattice(dims, U2)
+    base2 = K.Hierarchy(lat2, m0, gpu_params(K, levels), oh2.nullvecs, relaxed=True)
+    h.set_mass(m1, base=base2)
+    oh2b = OHierarchy(olat, U2, m1, olevels, [("relaxed", v) for v in oh2.nullvecs])
+    for k in (1, 2):
+        dims_c, _ = h.level_info(k)
+        assert relerr(assemble(h.coarse_op(k), dims_c), oh2b.ops[k].toarray()) < 1e-11
+    b = gaussian_vectors(2, olat.volume, 5, tag=0)
+    x = torch.empty((2, olat.volume), dtype=torch.complex128, device="cuda")
+    for prec in (K.KDMG_FP64, K.KDMG_MIXED):
+        info, _ = K.kdmg_solve(h, dev(b), x, 2, 1e-10, prec=prec)
+        xs = x.cpu().numpy()
+        D = dirac_matrix(olat, U2, m1)
+        for r in range(2):
+            assert info[r]["converged"]
+            assert np.linalg.norm(b[r] - D @ xs[r]) / np.linalg.norm(b[r]) <= 1e-10
+            xd = dense_solve(olat, U2, m1, b[r])
+            assert np.linalg.norm(xs[r] - xd) / np.linalg.norm(xd) < 1e-8
+    other = K.Hierarchy(K.Lattice((16, 32), field((16, 32), beta)), m0, gpu_params(K, levels),
+                        oracle_setup((16, 32), field((16, 32), beta), m0, levels, 23)[0].nullvecs,
+                        relaxed=True)
+    with pytest.raises(K.KdmgError) as e:
+        h.set_mass(m0, base=other)
+    assert e.value.status == K.KDMG_EINVAL
