@@ -229,6 +229,14 @@ kdmg_status kdmg_hierarchy_at_mass(const kdmg_hierarchy* base, double mass, void
 kdmg_status kdmg_hierarchy_set_mass(kdmg_hierarchy* h, const kdmg_hierarchy* base, double mass,
                                     void* stream);
 
+/* Implementation switch, not an operation of the method: replay captured
+   hipGraphs for chunks of coarsest-level CGNE iterations (enable = 1, the
+   default) or launch every kernel from the host (0); -1 leaves the setting.
+   Both run the same kernels in the same order and give identical results.
+   `replays` (may be NULL) receives the number of chunk graphs replayed on
+   this hierarchy so far. */
+kdmg_status kdmg_hierarchy_graphs(kdmg_hierarchy* h, int enable, long long* replays);
+
 /* Measurement hook (not an operation of the method): HIP-event timing of the
    two fused kernels of each coarsest-level CGNE iteration, on the solve's own
    stream, during later kdmg_solve calls.  enable = 1 starts (and zeroes) the

@@ -62,7 +62,10 @@ struct CtxAlloc {
     partials.alloc(sizeof(double) * (size_t)slots * 3 * RED_MAX_BLOCKS);
     counters.alloc(sizeof(unsigned) * slots);
     KDMG_HIP(hipMemset(counters.p, 0, counters.bytes));
-    KDMG_HIP(hipHostMalloc((void**)&h_poll, sizeof(int) * (nrhs_max + 8), hipHostMallocDefault));
+    {
+      std::lock_guard<std::mutex> g(hip_mem_mutex());
+      KDMG_HIP(hipHostMalloc((void**)&h_poll, sizeof(int) * (nrhs_max + 8), hipHostMallocDefault));
+    }
     c.st = st;
     c.rs.partials = partials.as<double>();
     c.rs.counters = counters.as<unsigned>();
@@ -70,7 +73,10 @@ struct CtxAlloc {
     c.h_poll = h_poll;
   }
   ~CtxAlloc() {
-    if (h_poll) (void)hipHostFree(h_poll);
+    if (h_poll) {
+      std::lock_guard<std::mutex> g(hip_mem_mutex());
+      (void)hipHostFree(h_poll);
+    }
   }
 };
 

@@ -108,6 +108,68 @@ void autotune_level(const CoarseLevel& L, int nrhs, bool fp32, hipStream_t st) {
   L.tuned.emplace(key, best);  // a concurrent tuner that finished first wins
 }
 
+// The fused coarsest-level CGNE pair has its own tuned shape: it adds the
+// partial-sum reduction and the vector updates to the stencil work.  Each
+// candidate runs init + 2 warm-up iterations, then 10 timed iterations of a
+// genuine CGNE (b = 1 on every dof, tolerance 0 so no rhs stops).
+void autotune_cgne(const CoarseLevel& L, int nrhs, hipStream_t st) {
+  const long key = cgne_key(nrhs);
+  {
+    std::lock_guard<std::mutex> g(*L.tune_mu);
+    if (L.tuned.count(key)) return;
+  }
+  const char* ev = std::getenv("KDMG_TUNE_VERBOSE");
+  const bool verbose = ev && ev[0] == '1';
+  const size_t n = (size_t)nrhs * L.nsites * L.ndc;
+  DevBuf b(sizeof(c64) * n), x(sizeof(c64) * n), r(sizeof(c64) * n), p(sizeof(c64) * n);
+  DevBuf rr(sizeof(double) * 2 * nrhs), tg(sizeof(double) * nrhs), act(sizeof(int) * 2 * nrhs),
+      ints(sizeof(int) * 3 * nrhs), PA(sizeof(double) * nrhs * L.nsites), PB(sizeof(double) * nrhs * L.nsites);
+  std::vector<c64> ones(n, c64{1.0, 0.0});
+  KDMG_HIP(hipMemcpyAsync(b.p, ones.data(), b.bytes, hipMemcpyHostToDevice, st));
+  KDMG_HIP(hipMemsetAsync(ints.p, 0, ints.bytes, st));
+  CgneState s;
+  s.rr = rr.as<double>();
+  s.target = tg.as<double>();
+  s.act = act.as<int>();
+  s.its = ints.as<int>();
+  s.tot = s.its + nrhs;
+  s.calls = s.tot + nrhs;
+  s.parent = nullptr;
+  s.PA = PA.as<double>();
+  s.PB = PB.as<double>();
+  hipEvent_t e0, e1;
+  KDMG_HIP(hipEventCreate(&e0));
+  KDMG_HIP(hipEventCreate(&e1));
+  std::vector<TileShape> cands = tile_candidates(L.ndc, nrhs, L.ndir, sizeof(c64));
+  TileShape best = cgne_shape(L, nrhs);
+  float best_ms = 1e30f;
+  for (const TileShape& sh : cands) {
+    launch_cgne_init(sh, L, x.as<c64>(), r.as<c64>(), p.as<c64>(), b.as<c64>(), s, nrhs, 0.0, st);
+    for (int k = 0; k < 2; ++k) launch_cgne_iter(sh, L, x.as<c64>(), r.as<c64>(), p.as<c64>(), s, nrhs, k, st);
+    KDMG_HIP(hipEventRecord(e0, st));
+    const int reps = 10;
+    for (int k = 2; k < 2 + reps; ++k)
+      launch_cgne_iter(sh, L, x.as<c64>(), r.as<c64>(), p.as<c64>(), s, nrhs, k, st);
+    KDMG_HIP(hipEventRecord(e1, st));
+    KDMG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    KDMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    if (verbose)
+      std::fprintf(stderr, "[kdmg-tune-cgne] nsites %d ndc %d nrhs %d core %d RT %d TI %d KS %d ylds %d thr %d: "
+                   "%.2f us per iteration\n", L.nsites, L.ndc, nrhs, sh.core, sh.RT, sh.TI, sh.KS, sh.ylds,
+                   sh.threads, ms * 1e3);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = sh;
+    }
+  }
+  KDMG_HIP(hipEventDestroy(e0));
+  KDMG_HIP(hipEventDestroy(e1));
+  std::lock_guard<std::mutex> g(*L.tune_mu);
+  L.tuned.emplace(key, best);
+}
+
 bool autotune_enabled() {
   static const bool on = [] {
     const char* e = std::getenv("KDMG_AUTOTUNE");
@@ -127,6 +189,7 @@ extern "C" kdmg_status kdmg_hierarchy_autotune(kdmg_hierarchy* h, int nrhs, kdmg
     const bool fp32 = prec == KDMG_MIXED && !coarsest;
     autotune_level(h->L[l], nrhs, fp32, st);
   }
+  autotune_cgne(h->L[h->nlevels - 1], nrhs, st);
   KDMG_HIP(hipStreamSynchronize(st));
   KDMG_API_END
 }

@@ -2,8 +2,9 @@
 // two compute cores:
 //   * MFMA core (>= 16 rhs): the per-site product out(X) = sum_dir Y_dir(X)
 //     V(nbr(X, dir)) is a complex (ndc x K) . (K x RT) GEMM, K = ndir*ndc.
-//     Complex arithmetic is split into four real products
-//       Re C += Yr Vr - Yi Vi,   Im C += Yr Vi + Yi Vr,
+//     Complex arithmetic takes three real products (Gauss)
+//       P1 = Yr Vr, P2 = Yi Vi, P3 = (Yr + Yi)(Vr + Vi),
+//       Re C = P1 - P2,  Im C = P3 - P1 - P2,
 //     each a v_mfma_{f32,f64}_16x16x4 on 16x16 output tiles; one wavefront
 //     owns one (16 dofs x 16 rhs) tile and runs two independent accumulator
 //     sets over even/odd k-chunks to keep the matrix pipe busy;
@@ -79,6 +80,28 @@ struct LdsLayout {
 // stores of the dof-fastest gather off a single bank
 __host__ __device__ __forceinline__ int panel_stride(int RT) { return RT + 1; }
 
+// floor(e / n) through the float reciprocal inv = 1.0f / n: exact whenever
+// 0 <= e and e + n < 2^22 (the relative error of the product, < 2^-23, stays
+// below the distance 0.5 / n of (e + 0.5) / n to the nearest integer).  All
+// index arithmetic of these kernels is far inside that range (< 2^17).
+__device__ __forceinline__ int fdiv(int e, float inv) { return (int)(((float)e + 0.5f) * inv); }
+
+// Lanes per rhs for the per-rhs reductions: a power of two <= 64 with
+// GS * RT <= blockDim, so every group lies inside one wavefront.
+__device__ __forceinline__ int group_size(int RT) {
+  int g = 64;
+  while (g > 1 && g * RT > (int)blockDim.x) g >>= 1;
+  return g;
+}
+
+// Sum of v over the GS lanes of each aligned lane group, by an xor butterfly:
+// a fixed tree, and every lane of the group ends with the same bits.  Called
+// by every lane of the wavefront.
+__device__ __forceinline__ double group_sum(double v, int GS) {
+  for (int o = GS >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz) {
   LdsLayout L;
   size_t o = 0;
@@ -144,64 +167,91 @@ inline TileShape choose_tile(int ndc, int nrhs, int ndir, size_t esz) {
 
 // ------------------------------------------------------------------ staging
 
-constexpr int STAGE_UNROLL = 16;
+// Neighbour sites of X in every direction; the addresses are uniform across
+// the workgroup, so these are scalar loads issued once at kernel entry.
+constexpr int MAX_DIR = 9;
+struct Nbrs {
+  int s[MAX_DIR];
+};
 
-// Ys[(d*ndc + j)*ndc + i] = Y_dir(X)[i][j]  (the column-major block, contiguous per dir).
-// Loads are batched STAGE_UNROLL deep so many are in flight per thread.
-template <class R, class OT>
-__device__ __forceinline__ void stage_blocks(Cx<R>* Ys, const Cx<OT>* __restrict__ Yt, int X, int nsites,
-                                             int ndc, int ndir) {
-  const int per = ndc * ndc, tot = ndir * per;
-  const int step = blockDim.x * STAGE_UNROLL;
-  for (int base = threadIdx.x; base < tot; base += step) {
-    Cx<R> tmp[STAGE_UNROLL];
+__device__ __forceinline__ Nbrs load_nbrs(const int* __restrict__ nbr, int X, int nsites, int ndir) {
+  Nbrs n;
 #pragma unroll
-    for (int u = 0; u < STAGE_UNROLL; ++u) {
-      const int e = base + u * blockDim.x;
-      tmp[u] = Cx<R>{0, 0};
-      if (e < tot) {
-        const int d = e / per, q = e - d * per;
-        tmp[u] = ld<R>(Yt[((long)d * nsites + X) * per + q]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < STAGE_UNROLL; ++u) {
-      const int e = base + u * blockDim.x;
-      if (e < tot) Ys[e] = tmp[u];
-    }
-  }
+  for (int d = 0; d < MAX_DIR; ++d) n.s[d] = d < ndir ? nbr[(long)d * nsites + X] : X;
+  return n;
 }
 
-// Vs[(d*ndc + j)*RTP + r] = v[r0 + r][nbr(X, d)][j] (RTP = RT + 1); rhs past
-// nrhs read as 0.  Threads walk j fastest so each (rhs, dir) row of ndc
-// entries is one contiguous global segment.
-template <class R, class VI>
-__device__ __forceinline__ void stage_panel(Cx<R>* Vs, const Cx<VI>* __restrict__ v, const int* nbr, int X,
-                                            int nsites, int ndc, int ndir, int r0, int RT, int nrhs) {
-  const int tot = ndir * ndc * RT, RTP = panel_stride(RT);
-  const int step = blockDim.x * STAGE_UNROLL;
-  for (int base = threadIdx.x; base < tot; base += step) {
-    Cx<R> tmp[STAGE_UNROLL];
+
+// Per-thread loads per pass: stencil-block entries and partial sums (the
+// panel takes one element in every direction).
+constexpr int YU = 4, SU = 8;
+
+// Stages the workgroup's operands into LDS, one pass per batch:
+// every load of a pass (stencil blocks, panel, partial sums) is issued before
+// any is consumed, so the common shapes pay a single memory round trip.
+//   Ys[(d*ndc + j)*ndc + i] = Y_dir(X)[i][j]            (when Ys != null)
+//   Vs[(d*ndc + j)*RTP + r] = v[r0 + r][nbr(X, d)][j]    (rhs >= nrhs read as 0)
+// With P != null ([rhs][site] partial sums of the previous kernel) the lane
+// g of rhs group t (t = tid / GS, g = tid % GS, GS = group_size(RT)) sums
+// P[r0 + t][g + k GS] over k in increasing order; the group's lanes are then
+// added by group_sum() and lane 0 stores the total in tot[t].  The order is
+// fixed, so every workgroup obtains bit-identical totals.
+template <class R, class OT, class VI>
+__device__ __forceinline__ void stage_all(Cx<R>* Ys, Cx<R>* Vs, const Cx<OT>* __restrict__ Yt,
+                                          const Cx<VI>* __restrict__ v, const Nbrs& nb, int X, int nsites,
+                                          int ndc, int ndir, int r0, int RT, int nrhs,
+                                          const double* __restrict__ P, double* tot) {
+  const int per = ndc * ndc, totY = Ys ? ndir * per : 0, totE = RT * ndc, RTP = panel_stride(RT);
+  const float inv_per = 1.0f / (float)per, inv_ndc = 1.0f / (float)ndc;
+  const int nthr = blockDim.x, tid = threadIdx.x;
+  const int GS = group_size(RT), t = tid / GS, g = tid - t * GS;
+  const bool sum_on = P != nullptr && t < RT && r0 + t < nrhs;
+  const double* prow = P ? P + (long)(r0 + (t < RT ? t : 0)) * nsites : nullptr;
+  double acc = 0.0;
+  for (int b = 0;; ++b) {
+    // per pass: one (rhs, dof) panel element in every direction, YU stencil
+    // entries and SU partial sums per thread
+    const int e = b * nthr + tid, yb = b * YU * nthr, sb = b * SU;
+    if (b * nthr >= totE && yb >= totY && (!P || sb * GS >= nsites)) break;
+    const bool pe = e < totE;
+    const int r = pe ? fdiv(e, inv_ndc) : 0, j = e - r * ndc;
+    const bool pl = pe && r0 + r < nrhs;
+    const long vrow = (long)(r0 + r) * nsites;
+    Cx<R> tv[MAX_DIR], ty[YU];
+    double ts[SU];
 #pragma unroll
-    for (int u = 0; u < STAGE_UNROLL; ++u) {
-      const int e = base + u * blockDim.x;
-      tmp[u] = Cx<R>{0, 0};
-      if (e < tot) {
-        const int j = e % ndc, q = e / ndc;
-        const int d = q % ndir, r = q / ndir;
-        const int rr = r0 + r;
-        if (rr < nrhs) tmp[u] = ld<R>(v[((long)rr * nsites + nbr[(long)d * nsites + X]) * ndc + j]);
+    for (int d = 0; d < MAX_DIR; ++d) {  // the direction index is a constant here: nb.s[d] stays scalar
+      tv[d] = Cx<R>{0, 0};
+      if (pl && d < ndir) tv[d] = ld<R>(v[(vrow + nb.s[d]) * ndc + j]);
+    }
+#pragma unroll
+    for (int u = 0; u < YU; ++u) {
+      const int ey = yb + tid + u * nthr;
+      ty[u] = Cx<R>{0, 0};
+      if (ey < totY) {
+        const int d = fdiv(ey, inv_per), q = ey - d * per;
+        ty[u] = ld<R>(Yt[((long)d * nsites + X) * per + q]);
       }
     }
 #pragma unroll
-    for (int u = 0; u < STAGE_UNROLL; ++u) {
-      const int e = base + u * blockDim.x;
-      if (e < tot) {
-        const int j = e % ndc, q = e / ndc;
-        const int d = q % ndir, r = q / ndir;
-        Vs[(d * ndc + j) * RTP + r] = tmp[u];
-      }
+    for (int u = 0; u < SU; ++u) {
+      const int Xs = g + (sb + u) * GS;
+      ts[u] = (sum_on && Xs < nsites) ? prow[Xs] : 0.0;
     }
+#pragma unroll
+    for (int d = 0; d < MAX_DIR; ++d)
+      if (pe && d < ndir) Vs[(d * ndc + j) * RTP + r] = tv[d];
+#pragma unroll
+    for (int u = 0; u < YU; ++u) {
+      const int ey = yb + tid + u * nthr;
+      if (ey < totY) Ys[ey] = ty[u];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) acc += ts[u];
+  }
+  if (P) {
+    const double sum = group_sum(acc, GS);
+    if (g == 0 && t < RT) tot[t] = sum;
   }
 }
 
@@ -242,9 +292,10 @@ __device__ __forceinline__ void core_simt(Frag<R, TI * TR>& f, const Cx<OT>* __r
     const int nk = ndir * ndc;
     const int i0 = ib * TI, r0l = rb * TR, RTP = panel_stride(RT);
     const long per = (long)ndc * ndc;
+    const float inv_ndc = 1.0f / (float)ndc;
 #pragma unroll 8
     for (int k = ks; k < nk; k += KS) {
-      const int d = k / ndc, j = k - d * ndc;
+      const int d = fdiv(k, inv_ndc), j = k - d * ndc;
       const Cx<OT>* yp = Yt + ((long)d * nsites + X) * per + (long)j * ndc + i0;
       Cx<R> y[TI], v[TR];
 #pragma unroll
@@ -308,13 +359,18 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const 
     if constexpr (YL == 1) {
       return Ys[k * ndc + ia];
     } else {
-      const int d = k / ndc, j = k - d * ndc;
+      const int d = fdiv(k, 1.0f / (float)ndc), j = k - d * ndc;
       return ld<R>(Yt[((long)d * nsites + X) * per + (long)j * ndc + ia]);
     }
   };
   const int RTP = panel_stride(RT);
   auto loadB = [&](int k) -> Cx<R> { return k < K ? Vs[k * RTP + cb] : Cx<R>{0, 0}; };
-  v4 cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
+  // Three real products per complex one (Gauss): with P1 = Ar Br,
+  // P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi):  Re = P1 - P2, Im = P3 - P1 - P2.
+  // Two accumulator sets (even / odd k-chunks) keep independent MFMAs in
+  // flight.
+  v4 p1a = {0, 0, 0, 0}, p2a = {0, 0, 0, 0}, p3a = {0, 0, 0, 0};
+  v4 p1b = {0, 0, 0, 0}, p2b = {0, 0, 0, 0}, p3b = {0, 0, 0, 0};
   if (on) {
     Cx<R> a0 = loadA(kk), a1 = loadA(kk + 4), b0 = loadB(kk), b1 = loadB(kk + 4);
     for (int kc = 0; kc < nkc; kc += 2) {
@@ -322,14 +378,12 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const 
       // operands of the next chunk pair, fetched before this pair's MFMAs
       const Cx<R> na0 = loadA(k0 + 8), na1 = loadA(k1 + 8);
       const Cx<R> nb0 = loadB(k0 + 8), nb1 = loadB(k1 + 8);
-      cr0 = M::op(a0.re, b0.re, cr0);
-      ci0 = M::op(a0.re, b0.im, ci0);
-      cr1 = M::op(a1.re, b1.re, cr1);
-      ci1 = M::op(a1.re, b1.im, ci1);
-      cr0 = M::op(-a0.im, b0.im, cr0);
-      ci0 = M::op(a0.im, b0.re, ci0);
-      cr1 = M::op(-a1.im, b1.im, cr1);
-      ci1 = M::op(a1.im, b1.re, ci1);
+      p1a = M::op(a0.re, b0.re, p1a);
+      p1b = M::op(a1.re, b1.re, p1b);
+      p2a = M::op(a0.im, b0.im, p2a);
+      p2b = M::op(a1.im, b1.im, p2b);
+      p3a = M::op(a0.re + a0.im, b0.re + b0.im, p3a);
+      p3b = M::op(a1.re + a1.im, b1.re + b1.im, p3b);
       a0 = na0;
       a1 = na1;
       b0 = nb0;
@@ -340,7 +394,8 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const 
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = mt * 16 + M::row(l, v);
-    f.val[v] = Cx<R>{cr0[v] + cr1[v], ci0[v] + ci1[v]};
+    const R q1 = p1a[v] + p1b[v], q2 = p2a[v] + p2b[v], q3 = p3a[v] + p3b[v];
+    f.val[v] = Cx<R>{q1 - q2, q3 - q1 - q2};
     f.i[v] = i;
     f.t[v] = cb;
     f.ok[v] = on && i < ndc && cb < RT;
@@ -395,15 +450,18 @@ __global__ __launch_bounds__(1024) void k_capply_fast(Cx<VO>* __restrict__ out, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>));
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT;
-  if (CORE == 1 && YL == 1) stage_blocks<R, OT>(reinterpret_cast<Cx<R>*>(smem_raw + L.ys), Yt, X, nsites, ndc, ndir);
-  stage_panel<R, VI>(reinterpret_cast<Cx<R>*>(smem_raw + L.vs), in, nbr, X, nsites, ndc, ndir, r0, ta.RT, nrhs);
+  const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
+  stage_all<R, OT, VI>(CORE == 1 && YL == 1 ? reinterpret_cast<Cx<R>*>(smem_raw + L.ys) : nullptr,
+                       reinterpret_cast<Cx<R>*>(smem_raw + L.vs), Yt, in, nb, X, nsites, ndc, ndir, r0, ta.RT,
+                       nrhs, nullptr, nullptr);
   __syncthreads();
   Frag<R, FragN<CORE, TI, TR>::value> f;
   run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yt, X, nsites, ndc, ndir, ta.RT, ta.KS, ta.MT, ta.NT);
   Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
   frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  const float inv_ndc = 1.0f / (float)ndc;
   for (int e = threadIdx.x; e < ta.RT * ndc; e += blockDim.x) {
-    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    const int t = fdiv(e, inv_ndc), i = e - t * ndc, rr = r0 + t;
     if (rr >= nrhs || !is_active(act, rr)) continue;
     const long o = ((long)rr * nsites + X) * ndc + i;
     Cx<R> res = sgn * O[e];
@@ -423,42 +481,9 @@ struct CgneState {
   int* tot;           // [nrhs]     iterations over all calls
   int* calls;         // [nrhs]     calls while active
   const int* parent;  // rhs the caller wants solved
-  double* PA;         // [nsites][nrhs] partial ||r||^2
-  double* PB;         // [nsites][nrhs] partial ||p||^2
+  double* PA;         // [nrhs][nsites] partial ||r||^2
+  double* PB;         // [nrhs][nsites] partial ||p||^2
 };
-
-// out[t] = sum_X P[X][r0 + t] for t < RT, summed in a fixed order: thread
-// (t, g) adds sites g, g + G, ... (G = blockDim / RT) in TS_UNROLL interleaved
-// running sums (all their loads in flight together), the running sums are
-// combined in order, then the G partial sums are added in g order.
-constexpr int TS_UNROLL = 16;
-__device__ __forceinline__ void tile_sums(const double* P, int nsites, int nrhs, int r0, int RT, double* out,
-                                          double* scratch) {
-  const int G = blockDim.x / RT;
-  const int t = threadIdx.x % RT, g = threadIdx.x / RT;
-  double acc = 0.0;
-  if (g < G && r0 + t < nrhs) {
-    const double* col = P + r0 + t;
-    for (int X0 = g; X0 < nsites; X0 += TS_UNROLL * G) {
-      double v[TS_UNROLL];
-#pragma unroll
-      for (int u = 0; u < TS_UNROLL; ++u) {
-        const int X = X0 + u * G;
-        v[u] = X < nsites ? col[(long)X * nrhs] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < TS_UNROLL; ++u) acc += v[u];
-    }
-  }
-  if (g < G) scratch[g * RT + t] = acc;
-  __syncthreads();
-  if (threadIdx.x < RT) {
-    double a = 0.0;
-    for (int q = 0; q < G; ++q) a += scratch[q * RT + threadIdx.x];
-    out[threadIdx.x] = a;
-  }
-  __syncthreads();
-}
 
 // Scatter a thread's fragment into the workgroup's output tile O[t*ndc + i]
 // (every (t < RT, i < ndc) entry is owned by exactly one thread), so the
@@ -471,16 +496,18 @@ __device__ __forceinline__ void frag_to_tile(Cx<R>* O, const Frag<R, N>& f, int 
   __syncthreads();
 }
 
-// P[X][r0 + t] = sum_i |O[t*ndc + i]|^2, dofs in order.
+// P[r0 + t][X] = sum_i |O[t*ndc + i]|^2: lane g of rhs group t adds dofs
+// g, g + GS, ... in order, then the group's lanes are added by group_sum().
 template <class R>
-__device__ __forceinline__ void tile_partials(double* P, const Cx<R>* O, int X, int nrhs, int r0, int RT, int ndc) {
+__device__ __forceinline__ void tile_partials(double* P, const Cx<R>* O, int X, int nsites, int nrhs, int r0,
+                                              int RT, int ndc) {
   __syncthreads();
-  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
-    if (r0 + t >= nrhs) continue;
-    double s = 0.0;
-    for (int i = 0; i < ndc; ++i) s += (double)norm2(O[t * ndc + i]);
-    P[(long)X * nrhs + r0 + t] = s;
-  }
+  const int GS = group_size(RT), t = threadIdx.x / GS, g = threadIdx.x - t * GS;
+  double s = 0.0;
+  if (t < RT)
+    for (int i = g; i < ndc; i += GS) s += (double)norm2(O[t * ndc + i]);
+  s = group_sum(s, GS);
+  if (g == 0 && t < RT && r0 + t < nrhs) P[(long)(r0 + t) * nsites + X] = s;
 }
 
 // init 1: x = 0, r = b, PA = partial ||b||^2 (one thread per rhs, dofs in order).
@@ -500,17 +527,33 @@ __global__ __launch_bounds__(256) void k_cgne_init1(Cx<R>* x, Cx<R>* r, const Cx
       }
       acc += (double)norm2(v);
     }
-    s.PA[(long)X * nrhs + rr] = acc;
+    s.PA[(long)rr * nsites + X] = acc;
   }
 }
 
-// Common prologue pieces of the CGNE kernels.
+// Common prologue of the CGNE kernels: stages the operands with the previous
+// kernel's partial sums, whose per-rhs totals land in tot[0 .. RT).
 template <class R, class OT, int CORE, int YL>
 __device__ __forceinline__ void cgne_stage(unsigned char* raw, const LdsLayout& L, const Cx<OT>* Y, const Cx<R>* v,
-                                           const int* nbr, int X, int nsites, int ndc, int ndir, int r0, int RT,
-                                           int nrhs) {
-  if (CORE == 1 && YL == 1) stage_blocks<R, OT>(reinterpret_cast<Cx<R>*>(raw + L.ys), Y, X, nsites, ndc, ndir);
-  stage_panel<R, R>(reinterpret_cast<Cx<R>*>(raw + L.vs), v, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
+                                           const Nbrs& nb, int X, int nsites, int ndc, int ndir, int r0, int RT,
+                                           int nrhs, const double* P, double* tot) {
+  stage_all<R, OT, R>(CORE == 1 && YL == 1 ? reinterpret_cast<Cx<R>*>(raw + L.ys) : nullptr,
+                      reinterpret_cast<Cx<R>*>(raw + L.vs), Y, v, nb, X, nsites, ndc, ndir, r0, RT, nrhs, P, tot);
+}
+
+// Prefetch of the thread's first epilogue element (e = threadIdx.x of the
+// RT x ndc output tile).
+struct FirstElem {
+  bool on;
+  long o;
+};
+
+__device__ __forceinline__ FirstElem first_elem(int X, int nsites, int ndc, int r0, int RT, int nrhs) {
+  const int e = threadIdx.x, t = fdiv(e, 1.0f / (float)ndc), i = e - t * ndc;
+  FirstElem f;
+  f.on = e < RT * ndc && r0 + t < nrhs;
+  f.o = ((long)(r0 + t) * nsites + X) * ndc + i;
+  return f;
 }
 
 // init 2: rr_0, target, act_0 ; p = A^dag r ; PB = partial ||p||^2
@@ -523,12 +566,15 @@ __global__ __launch_bounds__(1024) void k_cgne_init2(Cx<R>* p, const Cx<R>* r, c
   double* sc = reinterpret_cast<double*>(smem_raw + L.sc);
   int* live = reinterpret_cast<int*>(smem_raw + L.live);
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT;
-  tile_sums(s.PA, nsites, nrhs, r0, RT, sc, sc + 2 * RT);
-  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
-    const int rr = r0 + t;
+  const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
+  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nb, X, nsites, ndc, ndir, r0, RT, nrhs, s.PA, sc + 2 * RT);
+  __syncthreads();
+  if (threadIdx.x < RT) {
+    const int t = threadIdx.x, rr = r0 + t;
+    const double b2 = sc[2 * RT + t];
     int lv = 0;
     if (rr < nrhs) {
-      const double b2 = sc[t], tg = tol2 * b2;
+      const double tg = tol2 * b2;
       const bool on = s.parent == nullptr || s.parent[rr] != 0;
       lv = on && b2 > tg && b2 > 0.0;
       if (X == 0) {
@@ -541,21 +587,20 @@ __global__ __launch_bounds__(1024) void k_cgne_init2(Cx<R>* p, const Cx<R>* r, c
     }
     live[t] = lv;
   }
-  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
-  __syncthreads();
   Frag<R, FragN<CORE, TI, TR>::value> f;
   run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yd, X, nsites, ndc, ndir, RT, ta.KS, ta.MT, ta.NT);
   Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
   frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  const float inv_ndc = 1.0f / (float)ndc;
   for (int e = threadIdx.x; e < RT * ndc; e += blockDim.x) {
-    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    const int t = fdiv(e, inv_ndc), i = e - t * ndc, rr = r0 + t;
     if (rr >= nrhs || !live[t]) {
       O[e] = Cx<R>{0, 0};
       continue;
     }
     p[((long)rr * nsites + X) * ndc + i] = O[e];
   }
-  tile_partials<R>(s.PB, O, X, nrhs, r0, RT, ndc);
+  tile_partials<R>(s.PB, O, X, nsites, nrhs, r0, RT, ndc);
 }
 
 
@@ -569,36 +614,51 @@ __global__ __launch_bounds__(1024) void k_cgne_A(Cx<R>* x, Cx<R>* r, const Cx<R>
   double* sc = reinterpret_cast<double*>(smem_raw + L.sc);
   int* live = reinterpret_cast<int*>(smem_raw + L.live);
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT, sl = (k & 1) * nrhs;
-  tile_sums(s.PB, nsites, nrhs, r0, RT, sc, sc + 2 * RT);
-  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
-    const int rr = r0 + t;
+  // nothing to do once every rhs of the tile has stopped (the host polls the
+  // flags asynchronously, so a few iterations past convergence are launched)
+  const int mine = threadIdx.x < RT && r0 + (int)threadIdx.x < nrhs ? s.act[sl + r0 + threadIdx.x] : 0;
+  if (!__syncthreads_or(mine)) return;
+  const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
+  const FirstElem fe = first_elem(X, nsites, ndc, r0, RT, nrhs);
+  Cx<R> x0{0, 0}, r0v{0, 0};
+  if (fe.on) {
+    x0 = x[fe.o];
+    r0v = r[fe.o];
+  }
+  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yt, p, nb, X, nsites, ndc, ndir, r0, RT, nrhs, s.PB, sc + 2 * RT);
+  __syncthreads();
+  if (threadIdx.x < RT) {
+    const int t = threadIdx.x, rr = r0 + t;
+    const double pp = sc[2 * RT + t];
     const int lv = rr < nrhs ? s.act[sl + rr] : 0;
     live[t] = lv;
-    sc[RT + t] = lv ? s.rr[sl + rr] / sc[t] : 0.0;  // alpha
+    sc[RT + t] = lv ? s.rr[sl + rr] / pp : 0.0;  // alpha
   }
-  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yt, p, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
-  __syncthreads();
   Frag<R, FragN<CORE, TI, TR>::value> f;
   run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yt, X, nsites, ndc, ndir, RT, ta.KS, ta.MT, ta.NT);
   const Cx<R>* Vs = reinterpret_cast<const Cx<R>*>(smem_raw + L.vs);
   const int RTP = panel_stride(RT);
   Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
   frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  const float inv_ndc = 1.0f / (float)ndc;
   for (int e = threadIdx.x; e < RT * ndc; e += blockDim.x) {
-    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    const int t = fdiv(e, inv_ndc), i = e - t * ndc, rr = r0 + t;
     if (rr >= nrhs || !live[t]) {
       O[e] = Cx<R>{0, 0};
       continue;
     }
     const R al = (R)sc[RT + t];
     const long o = ((long)rr * nsites + X) * ndc + i;
+    const bool first = e == (int)threadIdx.x;
+    const Cx<R> xv = first ? x0 : x[o];
+    const Cx<R> rv_old = first ? r0v : r[o];
     const Cx<R> pv = Vs[i * RTP + t];  // direction 0 is the site itself
-    x[o] = x[o] + al * pv;
-    const Cx<R> rv = r[o] - al * O[e];
+    x[o] = xv + al * pv;
+    const Cx<R> rv = rv_old - al * O[e];
     r[o] = rv;
     O[e] = rv;
   }
-  tile_partials<R>(s.PA, O, X, nrhs, r0, RT, ndc);
+  tile_partials<R>(s.PA, O, X, nsites, nrhs, r0, RT, ndc);
 }
 
 
@@ -613,14 +673,30 @@ __global__ __launch_bounds__(1024) void k_cgne_B(Cx<R>* p, const Cx<R>* r, const
   int* live = reinterpret_cast<int*>(smem_raw + L.live);
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT;
   const int sl = (k & 1) * nrhs, sn = ((k + 1) & 1) * nrhs;
-  tile_sums(s.PA, nsites, nrhs, r0, RT, sc, sc + 2 * RT);
-  for (int t = threadIdx.x; t < RT; t += blockDim.x) {
-    const int rr = r0 + t;
+  const int mine = threadIdx.x < RT && r0 + (int)threadIdx.x < nrhs ? s.act[sl + r0 + threadIdx.x] : 0;
+  if (!__syncthreads_or(mine)) {
+    // every rhs of the tile has stopped: carry the state into the next slot
+    if (X == 0 && threadIdx.x < RT && r0 + (int)threadIdx.x < nrhs) {
+      const int rr = r0 + threadIdx.x;
+      s.rr[sn + rr] = s.rr[sl + rr];
+      s.act[sn + rr] = 0;
+    }
+    return;
+  }
+  const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
+  const FirstElem fe = first_elem(X, nsites, ndc, r0, RT, nrhs);
+  Cx<R> p0{0, 0};
+  if (fe.on) p0 = p[fe.o];
+  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nb, X, nsites, ndc, ndir, r0, RT, nrhs, s.PA, sc + 2 * RT);
+  __syncthreads();
+  if (threadIdx.x < RT) {
+    const int t = threadIdx.x, rr = r0 + t;
+    const double rn = sc[2 * RT + t];
     int lv = 0;
     double beta = 0.0;
     if (rr < nrhs) {
       const int was = s.act[sl + rr];
-      const double rn = sc[t], ro = s.rr[sl + rr];
+      const double ro = s.rr[sl + rr];
       lv = was && rn > s.target[rr];
       beta = lv ? rn / ro : 0.0;
       if (X == 0) {
@@ -635,25 +711,25 @@ __global__ __launch_bounds__(1024) void k_cgne_B(Cx<R>* p, const Cx<R>* r, const
     live[t] = lv;
     sc[RT + t] = beta;
   }
-  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nbr, X, nsites, ndc, ndir, r0, RT, nrhs);
-  __syncthreads();
   Frag<R, FragN<CORE, TI, TR>::value> f;
   run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yd, X, nsites, ndc, ndir, RT, ta.KS, ta.MT, ta.NT);
   Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
   frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
+  const float inv_ndc = 1.0f / (float)ndc;
   for (int e = threadIdx.x; e < RT * ndc; e += blockDim.x) {
-    const int t = e / ndc, i = e - t * ndc, rr = r0 + t;
+    const int t = fdiv(e, inv_ndc), i = e - t * ndc, rr = r0 + t;
     if (rr >= nrhs || !live[t]) {
       O[e] = Cx<R>{0, 0};
       continue;
     }
     const R be = (R)sc[RT + t];
     const long o = ((long)rr * nsites + X) * ndc + i;
-    const Cx<R> pv = O[e] + be * p[o];
+    const Cx<R> pold = e == (int)threadIdx.x ? p0 : p[o];
+    const Cx<R> pv = O[e] + be * pold;
     p[o] = pv;
     O[e] = pv;
   }
-  tile_partials<R>(s.PB, O, X, nrhs, r0, RT, ndc);
+  tile_partials<R>(s.PB, O, X, nsites, nrhs, r0, RT, ndc);
 }
 
 

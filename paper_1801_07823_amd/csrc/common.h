@@ -6,6 +6,7 @@
 #include <hip/hip_fp16.h>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -108,6 +109,14 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 // --------------------------------------------------------------- device memory
 
+// Serialises the library's device and pinned allocations and frees with its
+// hipGraph captures: a free synchronises the device, which must not happen
+// while another thread has a stream in capture.
+inline std::mutex& hip_mem_mutex() {
+  static std::mutex m;
+  return m;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -124,6 +133,7 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) return;
+    std::lock_guard<std::mutex> g(hip_mem_mutex());
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
       p = nullptr;
@@ -132,7 +142,10 @@ struct DevBuf {
     bytes = n;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      std::lock_guard<std::mutex> g(hip_mem_mutex());
+      (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
   }

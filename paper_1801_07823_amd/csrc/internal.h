@@ -186,6 +186,7 @@ struct kdmg_hierarchy {
   bool derived = false;               // T borrowed from another hierarchy (kdmg_hierarchy_at_mass)
   std::vector<kdmg::CoarseLevel> L;   // index by level; L[0] unused
   kdmg::DevBuf gal_w;                 // Galerkin scratch W = B^-1 P (level 1), kept for rebuilds
+  bool use_graphs = true;             // replay captured chunks of the coarsest CGNE
   kdmg::SolveWS* ws = nullptr;
   // event timing of the coarsest CGNE kernels (kdmg_hierarchy_kernel_timing)
   struct KTimer {
@@ -193,6 +194,7 @@ struct kdmg_hierarchy {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     double ms = 0.0;
     long long launches = 0;
+    long long graph_replays = 0;  // captured CGNE chunks replayed (counted whether or not timing is on)
   } timer;
   ~kdmg_hierarchy();
   // device bytes owned by this hierarchy (borrowed transfers not included)
@@ -236,7 +238,6 @@ inline void capply_shape(int ndc, int nrhs, int& js, int& rpb) {
     else KERNEL(0, 1, 1, 0)                                \
   } while (0)
 
-// Raise the dynamic-LDS limit of a kernel once (needed above 64 KB).
 // Raise a kernel's dynamic-LDS limit above the 64 KB default, once per
 // (device, kernel, size); the attribute call is not repeated on every launch.
 inline void ensure_smem(const void* fn, size_t bytes) {
@@ -254,6 +255,58 @@ inline void ensure_smem(const void* fn, size_t bytes) {
 
 inline TileArgs tile_args(const TileShape& s) { return TileArgs{s.RT, s.TI, s.TR, s.KS, s.MT, s.NT}; }
 
+// ------------------------------------------------------------ fused CGNE launchers
+
+// Key of the CGNE-specific tuned shape in CoarseLevel::tuned.
+inline long cgne_key(int nrhs) { return (1L << 40) + (long)nrhs * 64 + (long)sizeof(c64); }
+
+inline void launch_cgne_init(const TileShape& sh, const CoarseLevel& L, c64* x, c64* r, c64* p, const c64* b,
+                             const CgneState& s, int nrhs, double tol2, hipStream_t st) {
+  const dim3 grid(L.nsites, cdiv(nrhs, sh.RT));
+  const TileArgs ta = tile_args(sh);
+  hipLaunchKernelGGL(k_cgne_init1<double>, dim3(L.nsites), dim3(64), 0, st, x, r, b, L.nsites, L.ndc, nrhs, s);
+#define KDMG_L_INIT2(C_, TI_, TR_, YL_)                                                                   \
+  {                                                                                                  \
+    auto fn = k_cgne_init2<double, double, C_, TI_, TR_, YL_>;                                         \
+    ensure_smem((const void*)fn, sh.smem);                                                           \
+    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, st, p, r, L.Yd64.as<c64>(), L.nbr.as<int>(), \
+                       L.nsites, L.ndc, L.ndir, ta, nrhs, s, tol2);                                  \
+  }
+  KDMG_TILE_DISPATCH(sh, KDMG_L_INIT2);
+#undef KDMG_L_INIT2
+  KDMG_LAUNCH_CHECK();
+}
+
+// iteration k: kernel A then kernel B
+inline void launch_cgne_iter(const TileShape& sh, const CoarseLevel& L, c64* x, c64* r, c64* p,
+                             const CgneState& s, int nrhs, int k, hipStream_t st, hipEvent_t after_A = nullptr) {
+  const dim3 grid(L.nsites, cdiv(nrhs, sh.RT));
+  const TileArgs ta = tile_args(sh);
+  const int* nbr = L.nbr.as<int>();
+#define KDMG_L_A(C_, TI_, TR_, YL_)                                                                        \
+  {                                                                                                   \
+    auto fn = k_cgne_A<double, double, C_, TI_, TR_, YL_>;                                              \
+    ensure_smem((const void*)fn, sh.smem);                                                            \
+    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, st, x, r, p, L.Yt64.as<c64>(), nbr, L.nsites, \
+                       L.ndc, L.ndir, ta, nrhs, s, k);                                                \
+  }
+#define KDMG_L_B(C_, TI_, TR_, YL_)                                                                        \
+  {                                                                                                   \
+    auto fn = k_cgne_B<double, double, C_, TI_, TR_, YL_>;                                              \
+    ensure_smem((const void*)fn, sh.smem);                                                            \
+    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, st, p, r, L.Yd64.as<c64>(), nbr, L.nsites,   \
+                       L.ndc, L.ndir, ta, nrhs, s, k);                                                \
+  }
+  KDMG_TILE_DISPATCH(sh, KDMG_L_A);
+  if (after_A) KDMG_HIP(hipEventRecord(after_A, st));
+  KDMG_TILE_DISPATCH(sh, KDMG_L_B);
+#undef KDMG_L_A
+#undef KDMG_L_B
+  KDMG_LAUNCH_CHECK();
+}
+
+
+
 // The launch shape for a coarse level: the autotuned one if present, else the
 // default heuristic.
 inline TileShape level_shape(const CoarseLevel& L, int nrhs, size_t esz) {
@@ -264,6 +317,19 @@ inline TileShape level_shape(const CoarseLevel& L, int nrhs, size_t esz) {
   }
   return choose_tile(L.ndc, nrhs, L.ndir, esz);
 }
+
+// launch shape of the fused CGNE: its own tuned shape if present, else the
+// level's stencil shape
+inline TileShape cgne_shape(const CoarseLevel& L, int nrhs) {
+  {
+    std::lock_guard<std::mutex> g(*L.tune_mu);
+    auto it = L.tuned.find(cgne_key(nrhs));
+    if (it != L.tuned.end()) return it->second;
+  }
+  return level_shape(L, nrhs, sizeof(c64));
+}
+
+void autotune_cgne(const CoarseLevel& L, int nrhs, hipStream_t st);
 
 template <class R, class OT>
 void coarse_apply_shape(const CoarseLevel& L, bool dag, Cx<R>* out, const Cx<R>* in, const Cx<R>* add,

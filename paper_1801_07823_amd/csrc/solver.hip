@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 
 #include "algos.h"
 #include "api_guard.h"
@@ -24,6 +25,61 @@ void with_prec(Prec p, F f) {
   else f(float{});
 }
 
+// Two pinned host slots and events for polling device flags without
+// draining the stream: the copy of chunk c is checked while chunk c + 1 runs.
+struct AsyncPoll {
+  int* host = nullptr;  // [2][n]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int n = 0;
+  void init(int nflags) {
+    n = nflags;
+    std::lock_guard<std::mutex> g(hip_mem_mutex());
+    KDMG_HIP(hipHostMalloc((void**)&host, sizeof(int) * 2 * n, hipHostMallocDefault));
+    for (auto& e : ev) KDMG_HIP(hipEventCreate(&e));
+  }
+  AsyncPoll() = default;
+  AsyncPoll(const AsyncPoll&) = delete;
+  AsyncPoll& operator=(const AsyncPoll&) = delete;
+  ~AsyncPoll() {
+    std::lock_guard<std::mutex> g(hip_mem_mutex());
+    if (host) (void)hipHostFree(host);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// A captured chunk of fused CGNE iterations (k = 0 .. n-1, so parities
+// match any chunk that starts at an even k) for one workspace and launch
+// shape, replayed with hipGraphLaunch.  The kernels read their per-rhs state
+// from device memory, so one capture serves every call on the workspace.
+struct ChunkGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;  // private stream the chunk is captured on (the solve stream may be the null stream)
+  long long replays = 0;
+  TileShape sh;
+  int n = 0, nrhs = 0;
+  bool failed = false;
+  bool matches(const TileShape& s, int iters, int nr) const {
+    return exec && n == iters && nrhs == nr && sh.core == s.core && sh.RT == s.RT && sh.TI == s.TI &&
+           sh.TR == s.TR && sh.KS == s.KS && sh.MT == s.MT && sh.NT == s.NT && sh.ylds == s.ylds &&
+           sh.threads == s.threads && sh.smem == s.smem;
+  }
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (g) (void)hipGraphDestroy(g);
+    exec = nullptr;
+    g = nullptr;
+  }
+  ChunkGraph() = default;
+  ChunkGraph(const ChunkGraph&) = delete;
+  ChunkGraph& operator=(const ChunkGraph&) = delete;
+  ~ChunkGraph() {
+    reset();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 struct LevelWS {
   Prec prec = Prec::F64;
   long n = 0;                 // complex entries per rhs in this level's solve space
@@ -32,6 +88,8 @@ struct LevelWS {
   DevBuf t, w;                // level-0 Schur temporaries (full layout)
   DevBuf b, xs, rs, Z, W, p;  // coarse solve: input, solution, residual, GCR basis / CGNE p
   DevBuf cg_rr, cg_target, cg_act, PA, PB;  // fused CGNE state (coarsest level)
+  std::unique_ptr<AsyncPoll> cg_poll;        // its flag copies and events
+  std::unique_ptr<ChunkGraph> cg_graph;      // captured CGNE chunk
   KrylovAlloc ks, kmr;
   template <class T> Cx<T>* v(DevBuf& d) const { return d.as<Cx<T>>(); }
 };
@@ -83,8 +141,39 @@ struct OpResidNorm {  // ||r||^2 -> out[r]
 
 // Fused CGNE on the coarsest level: two kernels per iteration (see
 // coarse_fast.cuh), host reads the active flags every `poll` iterations.
+// Capture `n` CGNE iterations on the (idle-by-construction) capture of c.st.
+bool capture_chunk(ChunkGraph& G, const TileShape& sh, const CoarseLevel& L, c64* x, c64* r, c64* p,
+                   const CgneState& s, int nrhs, int n) {
+  std::lock_guard<std::mutex> lock(hip_mem_mutex());
+  G.reset();
+  if (!G.cap && hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking) != hipSuccess) {
+    G.cap = nullptr;
+    return false;
+  }
+  hipStream_t st = G.cap;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  hipGraph_t g = nullptr;
+  try {
+    for (int k = 0; k < n; ++k) launch_cgne_iter(sh, L, x, r, p, s, nrhs, k, st);
+  } catch (const Error&) {
+    if (hipStreamEndCapture(st, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    return false;
+  }
+  if (hipStreamEndCapture(st, &g) != hipSuccess || !g) return false;
+  G.g = g;
+  if (hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    G.reset();
+    return false;
+  }
+  G.sh = sh;
+  G.n = n;
+  G.nrhs = nrhs;
+  return true;
+}
+
 int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c64* b, c64* x, c64* r,
-               c64* p, double tol, int maxit, const int* parent, int poll, kdmg_hierarchy::KTimer* tm) {
+               c64* p, double tol, int maxit, const int* parent, int poll, kdmg_hierarchy::KTimer* tm,
+               bool graphs) {
   CgneState s;
   s.rr = W.cg_rr.as<double>();
   s.target = W.cg_target.as<double>();
@@ -95,77 +184,71 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
   s.parent = parent;
   s.PA = W.PA.as<double>();
   s.PB = W.PB.as<double>();
-  const TileShape sh = level_shape(L, nrhs, sizeof(c64));
+  const TileShape sh = cgne_shape(L, nrhs);
   KDMG_CHECK(sh.smem <= LDS_LIMIT, KDMG_EUNSUPPORTED, "coarsest operator too large for the fused CGNE");
-  const dim3 grid(L.nsites, cdiv(nrhs, sh.RT));
-  const TileArgs ta = tile_args(sh);
-  const c64* Yt = L.Yt64.as<c64>();
-  const c64* Yd = L.Yd64.as<c64>();
-  const int* nbr = L.nbr.as<int>();
-  hipLaunchKernelGGL(k_cgne_init1<double>, dim3(L.nsites), dim3(64), 0, c.st, x, r, b, L.nsites, L.ndc, nrhs, s);
-#define KDMG_L_INIT2(C_, TI_, TR_, YL_)                                                                     \
-  {                                                                                                    \
-    auto fn = k_cgne_init2<double, double, C_, TI_, TR_, YL_>;                                              \
-    ensure_smem((const void*)fn, sh.smem);                                                             \
-    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, c.st, p, r, Yd, nbr, L.nsites, L.ndc, L.ndir, \
-                       ta, nrhs, s, tol * tol);                                                        \
-  }
-  KDMG_TILE_DISPATCH(sh, KDMG_L_INIT2);
-#undef KDMG_L_INIT2
-  KDMG_LAUNCH_CHECK();
-  // timing: e0 after the first launch of a run between polls, e1 at the poll;
-  // the poll's own stream synchronisation completes e1
+  launch_cgne_init(sh, L, x, r, p, b, s, nrhs, tol * tol, c.st);
+  // Chunks of `poll` iterations.  After each chunk the active flags are
+  // copied to pinned host memory behind an event, and the previous chunk's
+  // copy is checked while this chunk runs, so the stream never drains;
+  // iterations launched past convergence return at once (all flags off).
+  AsyncPoll& ap = *W.cg_poll;
   const bool timed = tm && tm->on;
-  int run_launches = 0;
-  auto mark_end = [&]() {
-    if (timed && run_launches >= 2) KDMG_HIP(hipEventRecord(tm->e1, c.st));
-  };
-  auto close_run = [&]() {
-    if (timed && run_launches >= 2) {
+  bool pending[2] = {false, false};
+  int done_its[2] = {0, 0};
+  int cs = 0, k = 0;
+  bool stop = false;
+  auto account = [&](int slot) {  // kernel time from the first B launch to the end of a chunk
+    if (timed && done_its[slot] * 2 - 1 > 0) {
       float ms = 0.f;
-      KDMG_HIP(hipEventElapsedTime(&ms, tm->e0, tm->e1));
+      KDMG_HIP(hipEventElapsedTime(&ms, tm->e0, ap.ev[slot]));
       tm->ms += ms;
-      tm->launches += run_launches - 1;
+      tm->launches += done_its[slot] * 2 - 1;
     }
-    run_launches = 0;
   };
-  int k = 0;
-  for (; k < maxit; ++k) {
-#define KDMG_L_A(C_, TI_, TR_, YL_)                                                                          \
-  {                                                                                                     \
-    auto fn = k_cgne_A<double, double, C_, TI_, TR_, YL_>;                                                   \
-    ensure_smem((const void*)fn, sh.smem);                                                              \
-    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, c.st, x, r, p, Yt, nbr, L.nsites, L.ndc,    \
-                       L.ndir, ta, nrhs, s, k);                                                         \
-  }
-#define KDMG_L_B(C_, TI_, TR_, YL_)                                                                          \
-  {                                                                                                     \
-    auto fn = k_cgne_B<double, double, C_, TI_, TR_, YL_>;                                                   \
-    ensure_smem((const void*)fn, sh.smem);                                                              \
-    hipLaunchKernelGGL(fn, grid, dim3(sh.threads), sh.smem, c.st, p, r, Yd, nbr, L.nsites, L.ndc,       \
-                       L.ndir, ta, nrhs, s, k);                                                         \
-  }
-    KDMG_TILE_DISPATCH(sh, KDMG_L_A);
-    if (timed && run_launches == 0) KDMG_HIP(hipEventRecord(tm->e0, c.st));
-    KDMG_TILE_DISPATCH(sh, KDMG_L_B);
-#undef KDMG_L_A
-#undef KDMG_L_B
-    KDMG_LAUNCH_CHECK();
-    run_launches += 2;
-    if ((k + 1) % poll == 0) {
-      mark_end();
-      const bool more = any_active(c, s.act + ((k + 1) & 1) * nrhs, nrhs);
-      close_run();
-      if (!more) {
-        ++k;
-        break;
+  ChunkGraph& G = *W.cg_graph;
+  while (k < maxit && !stop) {
+    const int kend = std::min(k + poll, maxit);
+    // the first chunk of a call runs eagerly (it also sets the kernels' LDS
+    // limits and takes the timing start); later full chunks replay a graph
+    bool replayed = false;
+    if (graphs && k > 0 && kend - k == poll && k % 2 == 0 && !G.failed) {
+      if (!G.matches(sh, poll, nrhs) && !capture_chunk(G, sh, L, x, r, p, s, nrhs, poll)) {
+        (void)hipGetLastError();
+        G.failed = true;  // capture unavailable: stay eager on this workspace
+      }
+      if (!G.failed) {
+        KDMG_HIP(hipGraphLaunch(G.exec, c.st));
+        ++G.replays;
+        if (tm) ++tm->graph_replays;
+        k = kend;
+        replayed = true;
       }
     }
+    if (!replayed)
+      for (; k < kend; ++k)
+        launch_cgne_iter(sh, L, x, r, p, s, nrhs, k, c.st, timed && k == 0 ? tm->e0 : nullptr);
+    KDMG_HIP(hipMemcpyAsync(ap.host + cs * nrhs, s.act + (k & 1) * nrhs, sizeof(int) * nrhs,
+                            hipMemcpyDeviceToHost, c.st));
+    KDMG_HIP(hipEventRecord(ap.ev[cs], c.st));
+    pending[cs] = true;
+    done_its[cs] = k;
+    const int ps = cs ^ 1;
+    if (pending[ps]) {
+      KDMG_HIP(hipEventSynchronize(ap.ev[ps]));
+      pending[ps] = false;
+      bool any = false;
+      for (int q = 0; q < nrhs; ++q) any = any || ap.host[ps * nrhs + q] != 0;
+      if (!any) {
+        account(ps);
+        stop = true;
+      }
+    }
+    cs = ps;
   }
-  if (timed && run_launches) {
-    mark_end();
-    KDMG_HIP(hipStreamSynchronize(c.st));
-    close_run();
+  if (!stop && timed) {  // ended at maxit: account the last chunk
+    const int last = cs ^ 1;
+    KDMG_HIP(hipEventSynchronize(ap.ev[last]));
+    account(last);
   }
   return k;
 }
@@ -262,7 +345,7 @@ class Runner {
       if (l == h_.nlevels - 1) {
         if constexpr (sizeof(T) == 8) {
           cgne_fused(c_, h_.L[l], L, nrhs_, b, x, r, L.v<T>(L.p), P.coarse_tol, P.coarse_maxit, parent,
-                     poll_, &h_.timer);
+                     poll_, &h_.timer, h_.use_graphs);
         } else {
           auto opd = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, true); };
           auto opn = [&](Cx<T>* o, const Cx<T>* i, const int* a) { op<T>(l, o, i, nullptr, a, false); };
@@ -370,6 +453,9 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
         A(L.cg_act, sizeof(int) * 2 * nrhs);
         A(L.PA, sizeof(double) * (size_t)nrhs * h.L[l].nsites);
         A(L.PB, sizeof(double) * (size_t)nrhs * h.L[l].nsites);
+        L.cg_graph = std::make_unique<ChunkGraph>();
+        L.cg_poll = std::make_unique<AsyncPoll>();
+        L.cg_poll->init(nrhs);
       } else {
         A(L.Z, v * P.inter_restart);
         A(L.W, v * P.inter_restart);
@@ -441,9 +527,11 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
     h->ws = nullptr;
     h->ws = make_ws(*h, nrhs, prec, st);
   }
-  if (autotune_enabled())
+  if (autotune_enabled()) {
     for (int l = 1; l < h->nlevels; ++l)
       autotune_level(h->L[l], nrhs, prec == KDMG_MIXED && l < h->nlevels - 1, st);
+    autotune_cgne(h->L[h->nlevels - 1], nrhs, st);
+  }
   SolveWS& ws = *h->ws;
   int expect = 0;
   KDMG_CHECK(ws.busy.compare_exchange_strong(expect, 1), KDMG_EBUSY, "hierarchy busy");
@@ -536,5 +624,13 @@ extern "C" kdmg_status kdmg_hierarchy_kernel_timing(kdmg_hierarchy* h, int enabl
   }
   if (ms) *ms = t.ms;
   if (launches) *launches = t.launches;
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_graphs(kdmg_hierarchy* h, int enable, long long* replays) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && enable >= -1 && enable <= 1, KDMG_EINVAL, "kdmg_hierarchy_graphs: bad argument");
+  if (enable >= 0) h->use_graphs = enable != 0;
+  if (replays) *replays = h->timer.graph_replays;
   KDMG_API_END
 }

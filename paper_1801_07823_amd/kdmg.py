@@ -80,6 +80,7 @@ _SIGS = {
     "kdmg_hierarchy_autotune": (_I, [_P, _I, _I, _P]),
     "kdmg_hierarchy_at_mass": (_I, [_P, _D, _P, ctypes.POINTER(_P)]),
     "kdmg_hierarchy_set_mass": (_I, [_P, _P, _D, _P]),
+    "kdmg_hierarchy_graphs": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_hierarchy_kernel_timing": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_server_create": (_I, [_I, _S, ctypes.POINTER(_P)]),
     "kdmg_server_add_config": (_I, [_P, _P, ctypes.POINTER(_I)]),
@@ -256,6 +257,14 @@ class Hierarchy:
         _check(_lib.kdmg_hierarchy_get_coarse_op(self.handle, level, out.ctypes.data_as(_P)))
         return out
 
+    def graphs(self, enable=None):
+        """kdmg_hierarchy_graphs: replay captured coarsest-CGNE chunks (default) or
+        not; returns the number of chunk replays so far."""
+        n = ctypes.c_longlong()
+        _check(_lib.kdmg_hierarchy_graphs(self.handle, -1 if enable is None else (1 if enable else 0),
+                                          ctypes.byref(n)))
+        return n.value
+
     def footprint(self, nrhs=1):
         b = _S()
         _check(_lib.kdmg_hierarchy_footprint(self.handle, nrhs, ctypes.byref(b)))
@@ -311,6 +320,7 @@ class Server:
         self.handle = h
         self._configs = []
         self._live = {}
+        self.last_error = ""
 
     def add_config(self, hierarchy):
         cid = _I()
@@ -341,6 +351,7 @@ class Server:
         if not done.value:
             return None
         del self._live[ticket]
+        self.last_error = (_lib.kdmg_last_error() or b"").decode() if st.value != KDMG_OK else ""
         return st.value, [i.as_dict() for i in info], tuple(times)
 
     def stats(self):

@@ -419,3 +419,29 @@ def test_hierarchy_at_mass_and_rebind(K):
     with pytest.raises(K.KdmgError) as e:
         h.set_mass(m0, base=other)
     assert e.value.status == K.KDMG_EINVAL
+
+
+def test_cgne_graph_replay_matches_eager(K):
+    """The coarsest CGNE replays captured hipGraph chunks (the default); with
+    eager launches and host work between every replay, the same solve gives
+    bit-identical results, solve after solve (several hundred replays)."""
+    dims, beta, m = (64, 64), 6.0, 0.01
+    levels = [((4, 4), 8), ((2, 2), 12)]
+    U = field(dims, beta)
+    oh, _ = oracle_setup(dims, U, m, levels, 31)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), oh.nullvecs, relaxed=True)
+    nrhs = 20
+    b = dev(gaussian_vectors(nrhs, dims[0] * dims[1], 8, tag=0))
+    outs = {}
+    for graphs in (False, True, True, False, True):
+        gh.graphs(graphs)
+        x = torch.zeros_like(b)
+        info, _ = K.kdmg_solve(gh, b, x, nrhs, 1e-10, prec=K.KDMG_MIXED)
+        assert all(i["converged"] for i in info)
+        outs.setdefault(graphs, []).append(x.cpu().numpy())
+    assert gh.graphs() > 0  # chunks were really replayed
+    ref = outs[False][0]
+    for arrs in outs.values():
+        for a in arrs:
+            assert np.array_equal(a, ref)

@@ -83,11 +83,11 @@ def serve(K, configs, reqs, slots, budget, all_at_once):
                 tickets.append(t)
             else:
                 st, info, _ = srv.poll(t, wait=True)
-                assert st == K.KDMG_OK
+                assert st == K.KDMG_OK, srv.last_error
                 xs[i], infos[i] = xd.cpu().numpy()[0], info[0]
         for i, t in enumerate(tickets):
             st, info, _ = srv.poll(t, wait=True)
-            assert st == K.KDMG_OK
+            assert st == K.KDMG_OK, srv.last_error
             xs[i], infos[i] = bufs[i][1].cpu().numpy()[0], info[0]
         stats = srv.stats()
     finally:
