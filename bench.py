@@ -297,6 +297,7 @@ def main():
                     help="short run for hardware-counter passes: a 64 MiB copy, then one mixed "
                          "32-rhs solve cut off after one outer iteration; prints no metric")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the out-of-cache Dslash sweep")
     ap.add_argument("--fp64-rhs", type=int, default=1)
     ap.add_argument("--cpu-child", type=int, default=None)
     ap.add_argument("--serve", action="store_true", help="served-stream measurement instead of the bench line")
@@ -397,6 +398,33 @@ def main():
                             "bytes": bytes_d64},
               "mixed_32rhs": {"GB/s": bytes_d32 / t_d32 / 1e9, "us": t_d32 * 1e6,
                               "bytes": bytes_d32}}
+
+    # the same Dslash kernel out of cache: lattices and rhs counts whose
+    # traffic exceeds the 256 MB Infinity Cache (random U(1) links)
+    sweep = []
+    if not a.no_sweep:
+        rng = np.random.default_rng(5)
+        for dims_s, nr, prec in (((256, 256), 256, kdmg.KDMG_MIXED), ((2048, 2048), 1, kdmg.KDMG_FP64),
+                                 ((4096, 4096), 1, kdmg.KDMG_FP64), ((4096, 4096), 4, kdmg.KDMG_MIXED)):
+            Vs = dims_s[0] * dims_s[1]
+            Us = np.exp(1j * rng.uniform(0, 2 * np.pi, size=(2, Vs, 1, 1)))
+            lat_s = kdmg.Lattice(dims_s, Us)
+            del Us
+            dt = torch.complex128 if prec == kdmg.KDMG_FP64 else torch.complex64
+            vi = torch.randn((nr, Vs), dtype=dt, device="cuda")
+            vo = torch.empty_like(vi)
+            reps = 200 if Vs * nr <= (1 << 20) else 30
+            t_s = event_time(lambda: kdmg.kdmg_apply_D(lat_s, MASS, vi, vo, nr, prec=prec), reps)
+            # per site: in + out per rhs (32 B FP64, 16 B mixed) + two folded links (32 B / 8 B)
+            nbytes = Vs * (32 * nr + 32) if prec == kdmg.KDMG_FP64 else Vs * (16 * nr + 8)
+            sweep.append({"lattice": list(dims_s), "nrhs": nr, "prec": "fp64" if prec == 0 else "mixed",
+                          "bytes": nbytes, "us": t_s * 1e6, "GB/s": nbytes / t_s / 1e9,
+                          "frac_of_hbm_peak": nbytes / t_s / 1e9 / HBM_PEAK_GBS})
+            print("dslash %s x %d %s: %.1f us, %.0f GB/s" % (dims_s, nr, sweep[-1]["prec"], t_s * 1e6,
+                                                             sweep[-1]["GB/s"]), file=sys.stderr, flush=True)
+            del vi, vo, lat_s
+            torch.cuda.empty_cache()
+    dslash["out_of_cache_sweep"] = sweep
 
     # dominant kernel: the coarsest level's fused CGNE iteration (k_cgne_A then
     # k_cgne_B, FP64, 32 rhs), timed with HIP events on the solve stream during

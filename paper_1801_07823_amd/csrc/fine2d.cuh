@@ -218,27 +218,44 @@ __global__ __launch_bounds__(256) void k_dslash_blk(Cx<VT>* out, long so, const 
   }
 }
 
-// D in natural site order (one thread per site); links_nat[mu][site] folded.
-template <class R, class LT, class VT>
+// D in natural site order: one thread per site and RB right-hand sides (the
+// site's four links are loaded once for all of them; every vector load of
+// the RB rhs is issued before any is used).  links_nat[mu][site] folded.
+template <class R, class LT, class VT, int RB>
 __global__ __launch_bounds__(256) void k_dslash_nat(Cx<VT>* __restrict__ out, const Cx<VT>* __restrict__ in,
                                                     const Cx<LT>* __restrict__ Ux,
                                                     const Cx<LT>* __restrict__ Ut, int Lx, int Lt,
-                                                    long vol, R m) {
+                                                    long vol, R m, int nrhs) {
   const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB;
   if (x >= vol) return;
-  const int x0 = (int)(x % Lx), x1 = (int)(x / Lx);
+  const int x1 = (int)(x / Lx), x0 = (int)(x - (long)x1 * Lx);
   const int x0p = x0 + 1 == Lx ? 0 : x0 + 1, x0m = x0 == 0 ? Lx - 1 : x0 - 1;
   const int x1p = x1 + 1 == Lt ? 0 : x1 + 1, x1m = x1 == 0 ? Lt - 1 : x1 - 1;
-  const Cx<VT>* v = in + r * vol;
   const long ixp = (long)x1 * Lx + x0p, ixm = (long)x1 * Lx + x0m;
   const long itp = (long)x1p * Lx + x0, itm = (long)x1m * Lx + x0;
-  Cx<R> acc = m * ld<R>(v[x]);
-  acc += ld<R>(Ux[x]) * ld<R>(v[ixp]);
-  acc -= cmul_conj(ld<R>(Ux[ixm]), ld<R>(v[ixm]));
-  acc += ld<R>(Ut[x]) * ld<R>(v[itp]);
-  acc -= cmul_conj(ld<R>(Ut[itm]), ld<R>(v[itm]));
-  out[r * vol + x] = st<VT>(acc);
+  const Cx<R> ux = ld<R>(Ux[x]), uxm = ld<R>(Ux[ixm]), ut = ld<R>(Ut[x]), utm = ld<R>(Ut[itm]);
+  Cx<R> v0[RB], v1[RB], v2[RB], v3[RB], v4[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const bool on = r0 + b < nrhs;
+    const Cx<VT>* v = in + (long)(r0 + b) * vol;
+    v0[b] = on ? ld<R>(v[x]) : Cx<R>{0, 0};
+    v1[b] = on ? ld<R>(v[ixp]) : Cx<R>{0, 0};
+    v2[b] = on ? ld<R>(v[ixm]) : Cx<R>{0, 0};
+    v3[b] = on ? ld<R>(v[itp]) : Cx<R>{0, 0};
+    v4[b] = on ? ld<R>(v[itm]) : Cx<R>{0, 0};
+  }
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    if (r0 + b >= nrhs) continue;
+    Cx<R> acc = m * v0[b];
+    acc += ux * v1[b];
+    acc -= cmul_conj(uxm, v2[b]);
+    acc += ut * v3[b];
+    acc -= cmul_conj(utm, v4[b]);
+    out[(long)(r0 + b) * vol + x] = st<VT>(acc);
+  }
 }
 
 // gather / scatter between an external ordering and the block layout:

@@ -143,15 +143,26 @@ extern "C" kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const 
   KDMG_CHECK(in != out, KDMG_EINVAL, "kdmg_apply_D: in and out must not alias");
   hipStream_t st = (hipStream_t)stream;
   const long V = lat->volume;
-  dim3 grid(cdiv(V, 256), nrhs);
+  // several rhs per thread (links read once per site) when there are enough
+  // sites to fill the device
+  const int RB = (nrhs >= 4 && V >= 16384) ? 4 : 1;
+  dim3 grid(cdiv(V, 256), cdiv(nrhs, RB));
   if (prec == KDMG_FP64) {
     const c64* U = lat->nat64.as<c64>();
-    hipLaunchKernelGGL((k_dslash_nat<double, double, double>), grid, dim3(256), 0, st, (c64*)out,
-                       (const c64*)in, U, U + V, lat->dims[0], lat->dims[1], V, mass);
+    if (RB == 4)
+      hipLaunchKernelGGL((k_dslash_nat<double, double, double, 4>), grid, dim3(256), 0, st, (c64*)out,
+                         (const c64*)in, U, U + V, lat->dims[0], lat->dims[1], V, mass, nrhs);
+    else
+      hipLaunchKernelGGL((k_dslash_nat<double, double, double, 1>), grid, dim3(256), 0, st, (c64*)out,
+                         (const c64*)in, U, U + V, lat->dims[0], lat->dims[1], V, mass, nrhs);
   } else if (prec == KDMG_MIXED) {
     const c16* U = lat->nat16.as<c16>();
-    hipLaunchKernelGGL((k_dslash_nat<float, _Float16, float>), grid, dim3(256), 0, st, (c32*)out,
-                       (const c32*)in, U, U + V, lat->dims[0], lat->dims[1], V, (float)mass);
+    if (RB == 4)
+      hipLaunchKernelGGL((k_dslash_nat<float, _Float16, float, 4>), grid, dim3(256), 0, st, (c32*)out,
+                         (const c32*)in, U, U + V, lat->dims[0], lat->dims[1], V, (float)mass, nrhs);
+    else
+      hipLaunchKernelGGL((k_dslash_nat<float, _Float16, float, 1>), grid, dim3(256), 0, st, (c32*)out,
+                         (const c32*)in, U, U + V, lat->dims[0], lat->dims[1], V, (float)mass, nrhs);
   } else {
     throw Error(KDMG_EINVAL, "kdmg_apply_D: bad precision");
   }
