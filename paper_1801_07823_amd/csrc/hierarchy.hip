@@ -126,7 +126,13 @@ void upload(const Ctx& c, DevBuf& dst, const double* host, size_t bytes) {
 // Level-1 Galerkin operator at the hierarchy's mass (Sec. 3, Sec. 4):
 // W = B^-1 P block by block, then A_hat = 1 + P^dag C W.  Storage is reused
 // when the level already exists (a rebuild at another mass).
+void galerkin_level1_4d(kdmg_hierarchy& h, const Ctx& c);
+
 void galerkin_level1(kdmg_hierarchy& h, const Ctx& c) {
+  if (h.lat->nd == 4) {
+    galerkin_level1_4d(h, c);
+    return;
+  }
   const kdmg_lattice& lat = *h.lat;
   const Geo2& g = lat.g;
   const Transfer& T = h.T[0];
@@ -174,6 +180,137 @@ void galerkin_coarse(kdmg_hierarchy& h, int k, const Ctx& c) {
                      T.children.as<int>(), T.nchild, T.nsf, T.ndf, T.nZ, T.nv, Lf.ndir);
   KDMG_LAUNCH_CHECK();
   finish_coarse_level(c, Lc);
+}
+
+// ------------------------------------------------------------------ 4D SU(3), level 1
+
+// Level-1 Galerkin operator on a 4D lattice at h.mass: B^-1 blocks at this
+// mass, W = B^-1 P block by block, then A_hat = 1 + P^dag C W per (coarse
+// site, direction).
+void galerkin_level1_4d(kdmg_hierarchy& h, const Ctx& c) {
+  const kdmg_lattice& lat = *h.lat;
+  const Geo4& g = lat.g4;
+  const Transfer& T = h.T[0];
+  const int nv = T.nv, ndc = 2 * nv;
+  const long f = 2 * g.half;
+  build_binv4(h.binv64, h.binv32, lat, h.mass, c.st);
+  if (!h.gal_w.p) h.gal_w.alloc(sizeof(c64) * f * ndc);
+  hipLaunchKernelGGL(k4_gal_w, dim3(g.Nb2, 1, 2), dim3(256), 0, c.st, h.gal_w.as<c64>(), T.P64.as<c64>(),
+                     h.binv64.as<c64>(), g, nv);
+  KDMG_LAUNCH_CHECK();
+  CoarseLevel& C1 = h.L[1];
+  if (!C1.Yt64.p) {
+    C1.nd = 4;
+    for (int mu = 0; mu < 4; ++mu) C1.dims[mu] = g.NB[mu] / T.agg4[mu];
+    C1.ndc = ndc;
+    make_nbr(C1);
+    C1.Yt64.alloc(sizeof(c64) * (size_t)C1.ndir * C1.nsites * ndc * ndc);
+  }
+  KDMG_CHECK(ndc * ndc <= 16 * 256, KDMG_EUNSUPPORTED, "4D Galerkin: 2 n_vec must be <= 64");
+  const size_t smem = sizeof(c64) * GB4 * 3 * (nv + ndc) + sizeof(int) * 3 * GB4;
+  hipLaunchKernelGGL(k4_galerkin, dim3(C1.nsites, C1.ndir), dim3(256), smem, c.st, C1.Yt64.as<c64>(),
+                     T.P64.as<c64>(), h.gal_w.as<c64>(), lat.lk64.as<c64>(), lat.nb4.as<int>(), g, T.agg4[0],
+                     T.agg4[1], T.agg4[2], T.agg4[3], C1.nsites, nv);
+  KDMG_LAUNCH_CHECK();
+  finish_coarse_level(c, C1);
+}
+
+// Cholesky-QR applied twice per (aggregate, chirality) group: the thin QR
+// with positive real diagonal of the group's rows of V (unique, so equal to
+// the oracle's Householder QR up to rounding).  V(dof, i) = V[i sv + dof sd];
+// P receives Q in the prolongator layout [dof][nv].
+void block_cholqr2(c64* P, const c64* V, long sv, long sd, const Transfer& T, long f, hipStream_t st) {
+  const int nv = T.nv, ng = 2 * T.nZ;
+  DevBuf G(sizeof(c64) * ng * nv * nv), Ri(sizeof(c64) * ng * nv * nv), Q1(sizeof(c64) * f * nv);
+  const int* rows = T.rows4.as<int>();
+  const int ychunks = (T.nrows4 + 255) / 256 < 64 ? (T.nrows4 + 255) / 256 : 64;
+  // pass 1: V -> Q1
+  hipLaunchKernelGGL(k4_gram, dim3(ng), dim3(256), 0, st, G.as<c64>(), V, sv, sd, rows, T.nrows4, nv);
+  hipLaunchKernelGGL(k4_chol_inv, dim3(cdiv(ng, 64)), dim3(64), 0, st, Ri.as<c64>(), G.as<c64>(), ng, nv);
+  hipLaunchKernelGGL(k4_qapply, dim3(ng, ychunks), dim3(256), 0, st, Q1.as<c64>(), V, sv, sd, Ri.as<c64>(), rows,
+                     T.nrows4, nv);
+  // pass 2: Q1 -> P
+  hipLaunchKernelGGL(k4_gram, dim3(ng), dim3(256), 0, st, G.as<c64>(), Q1.as<c64>(), 1L, (long)nv, rows, T.nrows4, nv);
+  hipLaunchKernelGGL(k4_chol_inv, dim3(cdiv(ng, 64)), dim3(64), 0, st, Ri.as<c64>(), G.as<c64>(), ng, nv);
+  hipLaunchKernelGGL(k4_qapply, dim3(ng, ychunks), dim3(256), 0, st, P, Q1.as<c64>(), 1L, (long)nv, Ri.as<c64>(),
+                     rows, T.nrows4, nv);
+  KDMG_LAUNCH_CHECK();
+  KDMG_HIP(hipStreamSynchronize(st));
+}
+
+// fine 4D lattice -> first coarse lattice
+void build_level1_4d(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int relaxed) {
+  const kdmg_lattice& lat = *h.lat;
+  const Geo4& g = lat.g4;
+  const kdmg_level_params& lp = h.params.lvl[0];
+  const int nv = lp.nvec;
+  Transfer& T = h.T[0];
+  T.k = 0;
+  T.nv = nv;
+  int nblk = 1;
+  T.nZ = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    T.agg4[mu] = lp.agg[mu];
+    KDMG_CHECK(lp.agg[mu] >= 1 && g.NB[mu] % lp.agg[mu] == 0, KDMG_EINVAL,
+               "first aggregate must divide the KD-block lattice");
+    nblk *= lp.agg[mu];
+    T.nZ *= g.NB[mu] / lp.agg[mu];
+  }
+  T.nrows4 = nblk * 16 * 3 / 2;
+  KDMG_CHECK(nv >= 1 && nv <= T.nrows4 && 2 * nv <= 64 && nv <= 32, KDMG_EINVAL,
+             "n_vec must not exceed the dofs of one aggregate chirality (and n_vec <= 32)");
+  const long f = 2 * g.half, V = lat.volume, nd = lat.ndof;
+  T.nfine = f;
+  // (aggregate, chirality) groups, dofs in increasing block-layout order
+  std::vector<int> rows((size_t)2 * T.nZ * T.nrows4), dgrp(f), fill(2 * T.nZ, 0);
+  int Lc[4];
+  for (int mu = 0; mu < 4; ++mu) Lc[mu] = g.NB[mu] / T.agg4[mu];
+  for (int p = 0; p < 2; ++p)
+    for (int b = 0; b < g.Nb2; ++b) {
+      int Bc[4];
+      blk4_coords(g, p, b, Bc);
+      int Z = 0, str = 1;
+      for (int mu = 0; mu < 4; ++mu) {
+        Z += (Bc[mu] / T.agg4[mu]) * str;
+        str *= Lc[mu];
+      }
+      for (int s = 0; s < 16; ++s)
+        for (int a = 0; a < 3; ++a) {
+          const long dof = (((long)p * g.Nb2 + b) * 16 + s) * 3 + a;
+          const int gid = 2 * Z + chir4(s);
+          rows[(size_t)gid * T.nrows4 + fill[gid]++] = (int)dof;
+          dgrp[dof] = gid;
+        }
+    }
+  for (int q = 0; q < 2 * T.nZ; ++q) KDMG_CHECK(fill[q] == T.nrows4, KDMG_EINVAL, "aggregate group size mismatch");
+  T.rows4.alloc(sizeof(int) * rows.size());
+  T.dgrp4.alloc(sizeof(int) * dgrp.size());
+  KDMG_HIP(hipMemcpy(T.rows4.p, rows.data(), T.rows4.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(T.dgrp4.p, dgrp.data(), T.dgrp4.bytes, hipMemcpyHostToDevice));
+  // starting vectors: natural order -> block layout
+  DevBuf nat;
+  upload(c, nat, psi0, sizeof(c64) * nd * nv);
+  DevBuf Vb(sizeof(c64) * f * nv);
+  launch_permute<double, double>(Vb.as<c64>(), f, nat.as<c64>(), nd, lat.perm_full.as<int>(), nd, 1, nv, c.st);
+  if (!relaxed) {
+    build_binv4(h.binv64, h.binv32, lat, h.mass, c.st);
+    const Fine4<double, double> F{lat.lk64.as<c64>(), lat.nb4.as<int>(), h.binv64.as<c64>(), g, h.mass};
+    DevBuf u(sizeof(c64) * f * nv), t(sizeof(c64) * f * nv);
+    auto normal = [&](c64* out, const c64* in, const int* act) {
+      fullAdag_apply4<double, double>(u.as<c64>(), in, t.as<c64>(), F, act, nv, c.st);
+      fullA_apply4<double, double>(out, u.as<c64>(), t.as<c64>(), F, act, nv, c.st);
+    };
+    relax(c, Vb.as<c64>(), f, nv, h.params.setup_tol, h.params.setup_maxit, normal);
+  }
+  T.relaxed.alloc(Vb.bytes);
+  KDMG_HIP(hipMemcpyAsync(T.relaxed.p, Vb.p, Vb.bytes, hipMemcpyDeviceToDevice, c.st));
+  global_mgs(c, Vb.as<c64>(), f, nv);
+  T.P64.alloc(sizeof(c64) * f * nv);
+  block_cholqr2(T.P64.as<c64>(), Vb.as<c64>(), f, 1, T, f, c.st);
+  T.P16.alloc(sizeof(c16) * f * nv);
+  convert<_Float16, double>(T.P16.as<c16>(), T.P64.as<c64>(), f * nv, 1, nullptr, c.st);
+  galerkin_level1_4d(h, c);
+  KDMG_HIP(hipStreamSynchronize(c.st));
 }
 
 // fine lattice -> first coarse lattice (2D U(1))
@@ -351,7 +488,10 @@ extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass
   for (int k = 0; k < h->nlevels - 1; ++k) nvmax = std::max(nvmax, params->lvl[k].nvec);
   CtxAlloc ca;
   ca.init((hipStream_t)stream, nvmax * 2 + 8, nvmax);
-  build_level1(*h, ca.c, psi0_host[0], relaxed);
+  if (lat->nd == 4)
+    build_level1_4d(*h, ca.c, psi0_host[0], relaxed);
+  else
+    build_level1(*h, ca.c, psi0_host[0], relaxed);
   for (int k = 1; k < h->nlevels - 1; ++k) build_coarse(*h, k, ca.c, psi0_host[k], relaxed);
   KDMG_HIP(hipStreamSynchronize((hipStream_t)stream));
   *out = h.release();
@@ -454,7 +594,7 @@ extern "C" kdmg_status kdmg_hierarchy_get_nullvecs(const kdmg_hierarchy* h, int 
   const long n = T.nfine;
   if (k == 0) {
     const kdmg_lattice& lat = *h->lat;
-    const long V = lat.volume;
+    const long V = lat.ndof;
     DevBuf nat(sizeof(c64) * V * T.nv);
     launch_permute<double, double>(nat.as<c64>(), V, T.relaxed.as<c64>(), n, lat.perm_full.as<int>(), V,
                                    0, T.nv, 0);
@@ -474,7 +614,7 @@ extern "C" kdmg_status kdmg_hierarchy_get_prolongator(const kdmg_hierarchy* h, i
   c64* o = reinterpret_cast<c64*>(host_out);
   if (k == 0) {
     const kdmg_lattice& lat = *h->lat;
-    for (long x = 0; x < lat.volume; ++x)
+    for (long x = 0; x < lat.ndof; ++x)
       for (int i = 0; i < T.nv; ++i) o[x * T.nv + i] = buf[(size_t)lat.h_perm_full[x] * T.nv + i];
   } else {
     std::memcpy(o, buf.data(), T.P64.bytes);
@@ -520,7 +660,7 @@ extern "C" kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void*
   const Transfer& T = h->T[k];
   if (k == 0) {
     const kdmg_lattice& lat = *h->lat;
-    const long f = 2 * lat.g.half, V = lat.volume;
+    const long f = 2 * lat.half, V = lat.ndof;
     DevBuf a(sizeof(c64) * f * nrhs);
     launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, V, lat.perm_full.as<int>(), V, 1,
                                    nrhs, st);
@@ -543,7 +683,7 @@ extern "C" kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* 
   const Transfer& T = h->T[k];
   if (k == 0) {
     const kdmg_lattice& lat = *h->lat;
-    const long f = 2 * lat.g.half, V = lat.volume;
+    const long f = 2 * lat.half, V = lat.ndof;
     DevBuf a(sizeof(c64) * f * nrhs);
     transfer_prolong<double, double, double, double>(T, lat, a.as<c64>(), f, nullptr, 0, (const c64*)in,
                                                      2, nullptr, nrhs, st);

@@ -11,6 +11,7 @@
 #include "common.h"
 #include "blas.cuh"
 #include "fine2d.cuh"
+#include "fine4d.cuh"
 #include "coarse.cuh"
 #include "coarse_fast.cuh"
 
@@ -27,8 +28,14 @@ struct kdmg_lattice {
   long volume = 0;
   int antiperiodic = 1;
   kdmg::Geo2 g{};
+  long ndof = 0;   // complex entries of a fine vector (volume * nc)
+  long half = 0;   // complex entries of one KD-block parity half (the Schur space)
   // folded links (1/2 eta bc U), block layout [2][Nb2][8]
   kdmg::DevBuf links64, links16, links32;
+  // 4D SU(3): geometry, folded forward links [site][mu][3][3] and neighbour
+  // table [site][8] in block layout (see fine4d.cuh)
+  kdmg::Geo4 g4{};
+  kdmg::DevBuf lk64, lk32, lk16, nb4;
   // folded links in natural order, per direction [mu][site]
   kdmg::DevBuf nat64, nat16;
   // natural site -> block-layout index; even-block rank -> index in the even half
@@ -36,7 +43,7 @@ struct kdmg_lattice {
   std::vector<int> h_perm_full, h_perm_even;
   size_t footprint() const {
     return links64.bytes + links16.bytes + links32.bytes + nat64.bytes + nat16.bytes +
-           perm_full.bytes + perm_even.bytes;
+           perm_full.bytes + perm_even.bytes + lk64.bytes + lk32.bytes + lk16.bytes + nb4.bytes;
   }
 };
 
@@ -124,6 +131,81 @@ void fullAdag_apply(c64* out, c64* out2, const c64* v, c64* t, const Cx<LT>* lin
   launch_binv<double, LT, double>(out, f, out2, f, t, f, v, f, links, g, 0, 2, m, 1, act, nrhs, st);
 }
 
+// ------------------------------------------------------------ 4D fine operators
+
+template <class R, class LT>
+void launch4_hop(Cx<R>* out, long so, const Cx<R>* in, long si, const Cx<R>* add, long sa, const Cx<R>* add2,
+                 long sa2, double c2, double sgn, const Cx<LT>* lk, const int* nb4, const Geo4& g, int p0, int npar,
+                 double m, int mode, int eps_in, const int* act, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k4_hop<R, LT, R>), dim3(cdiv(16L * g.Nb2, 256), nrhs, npar), dim3(256), 0, st, out, so, in, si,
+                     add, sa, add2, sa2, (R)c2, (R)sgn, lk, nb4, g, p0, (R)m, mode, eps_in, act);
+  KDMG_LAUNCH_CHECK();
+}
+
+template <class R, class BT>
+void launch4_binv(Cx<R>* out, long so, const Cx<R>* in, long si, const Cx<R>* add, long sa, const Cx<BT>* Bv,
+                  const Geo4& g, int p0, int npar, int eps_out, const int* act, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k4_binv<R, BT, R>), dim3(g.Nb2, cdiv(nrhs, B4_RB), npar), dim3(64), 0, st, out, so, in, si, add,
+                     sa, Bv, g, p0, eps_out, act, nrhs);
+  KDMG_LAUNCH_CHECK();
+}
+
+// Operands of the 4D fine operators in one precision: links, neighbours and
+// B^-1 at the operator's mass.
+template <class LT, class BT>
+struct Fine4 {
+  const Cx<LT>* lk;
+  const int* nb4;
+  const Cx<BT>* Bv;
+  Geo4 g;
+  double m;
+};
+
+// S = 1 - A_eo A_oe on even-half vectors (as schur_apply):
+//   t_e = B_e^-1 v ; w_o = C_oe t_e ; t_o = B_o^-1 w_o ;
+//   out = v - C_eo t_o   or   out = resid - v + C_eo t_o
+template <class R, class LT, class BT>
+void schur_apply4(Cx<R>* out, const Cx<R>* v, const Cx<R>* resid, Cx<R>* t, Cx<R>* w, const Fine4<LT, BT>& F,
+                  const int* act, int nrhs, hipStream_t st) {
+  const long h = F.g.half, f = 2 * h;
+  launch4_binv<R, BT>(t, f, v, h, nullptr, 0, F.Bv, F.g, 0, 1, 0, act, nrhs, st);
+  launch4_hop<R, LT>(w, f, t, f, nullptr, 0, nullptr, 0, 0.0, 1.0, F.lk, F.nb4, F.g, 1, 1, F.m, 0, 0, act, nrhs, st);
+  launch4_binv<R, BT>(t, f, w, f, nullptr, 0, F.Bv, F.g, 1, 1, 0, act, nrhs, st);
+  if (!resid)
+    launch4_hop<R, LT>(out, h, t, f, v, h, nullptr, 0, 0.0, -1.0, F.lk, F.nb4, F.g, 0, 1, F.m, 0, 0, act, nrhs, st);
+  else
+    launch4_hop<R, LT>(out, h, t, f, resid, h, v, h, -1.0, 1.0, F.lk, F.nb4, F.g, 0, 1, F.m, 0, 0, act, nrhs, st);
+}
+
+// A = 1 + C B^-1 on full vectors:  t = B^-1 v ; out = v + C t
+template <class LT, class BT>
+void fullA_apply4(c64* out, const c64* v, c64* t, const Fine4<LT, BT>& F, const int* act, int nrhs, hipStream_t st) {
+  const long f = 2 * F.g.half;
+  launch4_binv<double, BT>(t, f, v, f, nullptr, 0, F.Bv, F.g, 0, 2, 0, act, nrhs, st);
+  launch4_hop<double, LT>(out, f, t, f, v, f, nullptr, 0, 0.0, 1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 0, 0, act, nrhs, st);
+}
+
+// A^dag = 1 + eps B^-1 C eps:  t = C (eps v) ; out = v + eps B^-1 t
+template <class LT, class BT>
+void fullAdag_apply4(c64* out, const c64* v, c64* t, const Fine4<LT, BT>& F, const int* act, int nrhs,
+                     hipStream_t st) {
+  const long f = 2 * F.g.half;
+  launch4_hop<double, LT>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 0, 1, act, nrhs,
+                          st);
+  launch4_binv<double, BT>(out, f, t, f, v, f, F.Bv, F.g, 0, 2, 1, act, nrhs, st);
+}
+
+// Dense B^-1 blocks of a 4D lattice at mass m (FP64 and an FP32 copy).
+inline void build_binv4(DevBuf& b64, DevBuf& b32, const kdmg_lattice& lat, double m, hipStream_t st) {
+  const Geo4& g = lat.g4;
+  const long n = 2L * g.Nb2 * 48 * 48;
+  if (!b64.p) b64.alloc(sizeof(c64) * n);
+  if (!b32.p) b32.alloc(sizeof(c32) * n);
+  hipLaunchKernelGGL(k4_binv_build, dim3(g.Nb2, 1, 2), dim3(256), 0, st, b64.as<c64>(), lat.lk64.as<c64>(), g, m);
+  KDMG_LAUNCH_CHECK();
+  launch_map(OpCopy<float, double>{b32.as<c32>(), b64.as<c64>(), n, nullptr}, n, 1, st);
+}
+
 }  // namespace kdmg
 
 namespace kdmg {
@@ -151,10 +233,16 @@ struct Transfer {
   DevBuf P64, P16;               // prolongator values [ndof_k][nv]
   DevBuf children, parent;       // k >= 1: int [nZ][nchild], int [nsf]
   DevBuf gdir;                   // k >= 1: int [ndir][nsf], coarse direction of each fine hop (0: internal)
+  // k == 0 on a 4D lattice: aggregates of agg4 KD blocks; rows4 = fine dofs of
+  // each (aggregate, chirality) group [2 nZ][nrows4], dgrp4 = group of each dof
+  int agg4[4] = {1, 1, 1, 1};
+  int nrows4 = 0;
+  DevBuf rows4, dgrp4;
   DevBuf relaxed;                // relaxed null vectors, FP64, internal layout [nv][n_k]
   long nfine = 0;                // entries per null vector (internal layout)
   size_t bytes() const {
-    return P64.bytes + P16.bytes + children.bytes + parent.bytes + gdir.bytes + relaxed.bytes;
+    return P64.bytes + P16.bytes + children.bytes + parent.bytes + gdir.bytes + relaxed.bytes + rows4.bytes +
+           dgrp4.bytes;
   }
 };
 
@@ -186,6 +274,7 @@ struct kdmg_hierarchy {
   bool derived = false;               // T borrowed from another hierarchy (kdmg_hierarchy_at_mass)
   std::vector<kdmg::CoarseLevel> L;   // index by level; L[0] unused
   kdmg::DevBuf gal_w;                 // Galerkin scratch W = B^-1 P (level 1), kept for rebuilds
+  kdmg::DevBuf binv64, binv32;        // 4D: dense B^-1 blocks at this mass (FP64, FP32)
   bool use_graphs = true;             // replay captured chunks of the coarsest CGNE
   kdmg::SolveWS* ws = nullptr;
   // event timing of the coarsest CGNE kernels (kdmg_hierarchy_kernel_timing)
@@ -199,7 +288,7 @@ struct kdmg_hierarchy {
   ~kdmg_hierarchy();
   // device bytes owned by this hierarchy (borrowed transfers not included)
   size_t bytes() const {
-    size_t b = gal_w.bytes;
+    size_t b = gal_w.bytes + binv64.bytes + binv32.bytes;
     if (!derived)
       for (size_t k = 0; k < T.size(); ++k) b += T[k].bytes();
     for (auto& l : L) b += l.bytes();
@@ -379,7 +468,11 @@ void transfer_restrict(const Transfer& T, const kdmg_lattice& lat, const CoarseL
                        Cx<VO>* out, const Cx<VI>* in, long si, int even_only, const int* act,
                        int nrhs, hipStream_t st) {
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
-  if (T.k == 0) {
+  if (T.k == 0 && lat.nd == 4) {
+    dim3 grid(2 * T.nZ, cdiv(T.nv, R4_RI), cdiv(nrhs, R4_RR));
+    hipLaunchKernelGGL((k4_restrict<R, PT, VI, VO>), grid, dim3(256), 0, st, out, in, si, P, T.rows4.as<int>(),
+                       T.nrows4, T.nv, even_only, lat.half, act, nrhs);
+  } else if (T.k == 0) {
     const int ndc = 2 * T.nv;
     int parts = 256 / ndc;
     if (parts < 1) parts = 1;
@@ -403,7 +496,12 @@ void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, l
                       const Cx<VO>* add, long sa, const Cx<VI>* in, int npar, const int* act,
                       int nrhs, hipStream_t st) {
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
-  if (T.k == 0) {
+  if (T.k == 0 && lat.nd == 4) {
+    const long n_out = npar == 1 ? lat.half : 2 * lat.half;
+    dim3 grid(cdiv(n_out, 256), nrhs);
+    hipLaunchKernelGGL((k4_prolong<R, PT, VI, VO>), grid, dim3(256), 0, st, out, so, add, sa, in, P,
+                       T.dgrp4.as<int>(), T.nv, n_out, (long)T.nZ * 2 * T.nv, act);
+  } else if (T.k == 0) {
     dim3 grid(cdiv(lat.g.Nb2, 256), nrhs, npar);
     hipLaunchKernelGGL((k_prolong1<R, PT, VI, VO>), grid, dim3(256), 0, st, out, so, add, sa, in, P,
                        lat.g, T.a2, act);

@@ -35,6 +35,78 @@ void fold_links_2d(const kdmg_lattice& lat, const double* links, std::vector<c64
   }
 }
 
+// 4D SU(3): geometry, folded links, neighbour table and permutations.
+void create_4d(kdmg_lattice& lat, const double* links) {
+  Geo4& g = lat.g4;
+  for (int mu = 0; mu < 4; ++mu) {
+    g.L[mu] = lat.dims[mu];
+    g.NB[mu] = lat.dims[mu] / 2;
+  }
+  const long V = lat.volume;
+  g.Nb2 = (int)(V / 16 / 2);
+  g.half = (long)g.Nb2 * 48;
+  lat.ndof = 3 * V;
+  lat.half = g.half;
+  const int* L = g.L;
+  auto nat_index = [&](const int x[4]) { return x[0] + (long)L[0] * (x[1] + (long)L[1] * (x[2] + (long)L[2] * x[3])); };
+  auto blk_site = [&](const int x[4]) {
+    int Bc[4], s = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+      Bc[mu] = x[mu] >> 1;
+      s |= (x[mu] & 1) << mu;
+    }
+    return ((long)blk4_parity(Bc) * g.Nb2 + blk4_index(g, Bc)) * 16 + s;
+  };
+  std::vector<c64> lk((size_t)V * 4 * 9);
+  std::vector<int> nb((size_t)V * 8);
+  lat.h_perm_full.assign(3 * V, 0);
+  int x[4];
+  for (long n = 0; n < V; ++n) {
+    long r = n;
+    for (int mu = 0; mu < 4; ++mu) {
+      x[mu] = (int)(r % L[mu]);
+      r /= L[mu];
+    }
+    const long ib = blk_site(x);
+    for (int c = 0; c < 3; ++c) lat.h_perm_full[3 * n + c] = (int)(3 * ib + c);
+    int parity = 0;  // sum_{nu < mu} x_nu
+    for (int mu = 0; mu < 4; ++mu) {
+      const double eta = (parity & 1) ? -1.0 : 1.0;
+      parity += x[mu];
+      const double bc = (mu == 3 && lat.antiperiodic && x[3] == L[3] - 1) ? -1.0 : 1.0;
+      const double* u = links + 2 * (((long)mu * V + n) * 9);
+      for (int e = 0; e < 9; ++e)
+        lk[((size_t)ib * 4 + mu) * 9 + e] = c64{0.5 * eta * bc * u[2 * e], 0.5 * eta * bc * u[2 * e + 1]};
+      int y[4] = {x[0], x[1], x[2], x[3]};
+      y[mu] = (x[mu] + 1) % L[mu];
+      nb[ib * 8 + 2 * mu] = (int)blk_site(y);
+      y[mu] = (x[mu] + L[mu] - 1) % L[mu];
+      nb[ib * 8 + 2 * mu + 1] = (int)blk_site(y);
+    }
+  }
+  lat.h_perm_even.assign(3 * V / 2, 0);
+  long rank = 0;
+  for (long n = 0; n < V; ++n) {
+    const long bd = lat.h_perm_full[3 * n];
+    if (bd < 3 * (V / 2))
+      for (int c = 0; c < 3; ++c) lat.h_perm_even[rank++] = (int)(bd + c);
+  }
+  KDMG_CHECK(rank == 3 * V / 2, KDMG_EINVAL, "even-block count mismatch");
+  lat.lk64.alloc(lk.size() * sizeof(c64));
+  lat.lk32.alloc(lk.size() * sizeof(c32));
+  lat.lk16.alloc(lk.size() * sizeof(c16));
+  lat.nb4.alloc(nb.size() * sizeof(int));
+  lat.perm_full.alloc(lat.h_perm_full.size() * sizeof(int));
+  lat.perm_even.alloc(lat.h_perm_even.size() * sizeof(int));
+  KDMG_HIP(hipMemcpy(lat.lk64.p, lk.data(), lat.lk64.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(lat.nb4.p, nb.data(), lat.nb4.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(lat.perm_full.p, lat.h_perm_full.data(), lat.perm_full.bytes, hipMemcpyHostToDevice));
+  KDMG_HIP(hipMemcpy(lat.perm_even.p, lat.h_perm_even.data(), lat.perm_even.bytes, hipMemcpyHostToDevice));
+  convert<_Float16, double>(lat.lk16.as<c16>(), lat.lk64.as<c64>(), (long)lk.size(), 1, nullptr, 0);
+  convert<float, double>(lat.lk32.as<c32>(), lat.lk64.as<c64>(), (long)lk.size(), 1, nullptr, 0);
+  KDMG_HIP(hipStreamSynchronize(0));
+}
+
 }  // namespace
 
 extern "C" kdmg_status kdmg_init(int device) {
@@ -52,8 +124,8 @@ extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
   KDMG_API_BEGIN
   KDMG_CHECK(out && dims && links_host, KDMG_EINVAL, "kdmg_lattice_create: null argument");
   *out = nullptr;
-  if (!(nd == 2 && ncolor == 1))
-    throw Error(KDMG_EUNSUPPORTED, "kdmg_lattice_create: only nd=2 with ncolor=1 is built");
+  if (!((nd == 2 && ncolor == 1) || (nd == 4 && ncolor == 3)))
+    throw Error(KDMG_EUNSUPPORTED, "kdmg_lattice_create: built for nd=2 with ncolor=1 and nd=4 with ncolor=3");
   for (int mu = 0; mu < nd; ++mu)
     KDMG_CHECK(dims[mu] >= 4 && dims[mu] % 4 == 0, KDMG_EINVAL,
                "kdmg_lattice_create: extents must be positive multiples of 4");
@@ -66,6 +138,12 @@ extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
     lat->volume *= dims[mu];
   }
   lat->antiperiodic = antiperiodic_time ? 1 : 0;
+  if (nd == 4) {
+    KDMG_CHECK(lat->volume <= (1L << 26), KDMG_EINVAL, "kdmg_lattice_create: 4D volume too large");
+    create_4d(*lat, links_host);
+    *out = lat.release();
+    return KDMG_OK;
+  }
   Geo2& g = lat->g;
   g.Lx = dims[0];
   g.Lt = dims[1];
@@ -74,6 +152,8 @@ extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
   g.hBx = g.Bx / 2;
   g.Nb2 = g.Bx * g.Bt / 2;
   g.half = 4L * g.Nb2;
+  lat->ndof = lat->volume;
+  lat->half = g.half;
   const long V = lat->volume;
 
   std::vector<c64> nat;
@@ -143,6 +223,31 @@ extern "C" kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const 
   KDMG_CHECK(in != out, KDMG_EINVAL, "kdmg_apply_D: in and out must not alias");
   hipStream_t st = (hipStream_t)stream;
   const long V = lat->volume;
+  if (lat->nd == 4) {
+    // block layout: gather, D, scatter
+    const long f = 2 * lat->half, n = lat->ndof;
+    const int* perm = lat->perm_full.as<int>();
+    if (prec == KDMG_FP64) {
+      DevBuf a(sizeof(c64) * f * nrhs), b(sizeof(c64) * f * nrhs);
+      launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, n, perm, n, 1, nrhs, st);
+      launch4_hop<double, double>(b.as<c64>(), f, a.as<c64>(), f, nullptr, 0, nullptr, 0, 0.0, 1.0,
+                                  lat->lk64.as<c64>(), lat->nb4.as<int>(), lat->g4, 0, 2, mass, 2, 0, nullptr, nrhs,
+                                  st);
+      launch_permute<double, double>((c64*)out, n, b.as<c64>(), f, perm, n, 0, nrhs, st);
+      KDMG_HIP(hipStreamSynchronize(st));
+    } else if (prec == KDMG_MIXED) {
+      DevBuf a(sizeof(c32) * f * nrhs), b(sizeof(c32) * f * nrhs);
+      launch_permute<float, float>(a.as<c32>(), f, (const c32*)in, n, perm, n, 1, nrhs, st);
+      launch4_hop<float, _Float16>(b.as<c32>(), f, a.as<c32>(), f, nullptr, 0, nullptr, 0, 0.0, 1.0,
+                                   lat->lk16.as<c16>(), lat->nb4.as<int>(), lat->g4, 0, 2, mass, 2, 0, nullptr,
+                                   nrhs, st);
+      launch_permute<float, float>((c32*)out, n, b.as<c32>(), f, perm, n, 0, nrhs, st);
+      KDMG_HIP(hipStreamSynchronize(st));
+    } else {
+      throw Error(KDMG_EINVAL, "kdmg_apply_D: bad precision");
+    }
+    return KDMG_OK;
+  }
   // several rhs per thread (links read once per site) when there are enough
   // sites to fill the device
   const int RB = (nrhs >= 4 && V >= 16384) ? 4 : 1;
@@ -179,10 +284,36 @@ void fine_op_natural(const kdmg_lattice* lat, double mass, const void* in, void*
   KDMG_CHECK(lat && in && out, KDMG_EINVAL, "null argument");
   KDMG_CHECK(nrhs >= 1 && nrhs <= 65535, KDMG_EINVAL, "bad nrhs");
   const Geo2& g = lat->g;
-  const long f = 2 * g.half, V = lat->volume;
+  const long f = 2 * lat->half, V = lat->ndof;
   DevBuf a(sizeof(c64) * f * nrhs), b(sizeof(c64) * f * nrhs), t(sizeof(c64) * f * nrhs),
       w(sizeof(c64) * f * nrhs);
   const c64* L = lat->links64.as<c64>();
+  if (lat->nd == 4) {
+    DevBuf b64, b32;
+    build_binv4(b64, b32, *lat, mass, st);
+    const Fine4<double, double> F{lat->lk64.as<c64>(), lat->nb4.as<int>(), b64.as<c64>(), lat->g4, mass};
+    const long h = lat->half;
+    if (op == OP_SCHUR) {
+      launch_permute<double, double>(a.as<c64>(), h, (const c64*)in, V / 2, lat->perm_even.as<int>(), V / 2, 1,
+                                     nrhs, st);
+      schur_apply4<double, double, double>(b.as<c64>(), a.as<c64>(), nullptr, t.as<c64>(), w.as<c64>(), F, nullptr,
+                                           nrhs, st);
+      launch_permute<double, double>((c64*)out, V / 2, b.as<c64>(), h, lat->perm_even.as<int>(), V / 2, 0, nrhs,
+                                     st);
+    } else {
+      launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, V, lat->perm_full.as<int>(), V, 1, nrhs, st);
+      if (op == OP_A)
+        fullA_apply4<double, double>(b.as<c64>(), a.as<c64>(), t.as<c64>(), F, nullptr, nrhs, st);
+      else if (op == OP_ADAG)
+        fullAdag_apply4<double, double>(b.as<c64>(), a.as<c64>(), t.as<c64>(), F, nullptr, nrhs, st);
+      else
+        launch4_binv<double, double>(b.as<c64>(), f, a.as<c64>(), f, nullptr, 0, F.Bv, F.g, 0, 2, 0, nullptr, nrhs,
+                                     st);
+      launch_permute<double, double>((c64*)out, V, b.as<c64>(), f, lat->perm_full.as<int>(), V, 0, nrhs, st);
+    }
+    KDMG_HIP(hipStreamSynchronize(st));
+    return;
+  }
   if (op == OP_SCHUR) {
     launch_permute<double, double>(a.as<c64>(), g.half, (const c64*)in, V / 2,
                                    lat->perm_even.as<int>(), V / 2, 1, nrhs, st);

@@ -263,12 +263,19 @@ class Runner {
     if (l == 0) {
       LevelWS& L = ws_.lv[0];
       const kdmg_lattice& lat = *h_.lat;
-      if constexpr (sizeof(T) == 8)
+      if (lat.nd == 4) {
+        if constexpr (sizeof(T) == 8)
+          schur_apply4<T, double, double>(out, in, resid, L.v<T>(L.t), L.v<T>(L.w), fine4_64(), act, nrhs_, c_.st);
+        else
+          schur_apply4<T, _Float16, float>(out, in, resid, L.v<T>(L.t), L.v<T>(L.w), fine4_mixed(), act, nrhs_,
+                                           c_.st);
+      } else if constexpr (sizeof(T) == 8) {
         schur_apply<T, double>(out, in, resid, L.v<T>(L.t), L.v<T>(L.w), lat.links64.as<c64>(), lat.g,
                                h_.mass, act, nrhs_, c_.st);
-      else
+      } else {
         schur_apply<T, _Float16>(out, in, resid, L.v<T>(L.t), L.v<T>(L.w), lat.links16.as<c16>(),
                                  lat.g, h_.mass, act, nrhs_, c_.st);
+      }
     } else {
       if constexpr (sizeof(T) == 8)
         coarse_apply<T, double>(h_.L[l], dag, out, in, resid, resid ? -1.0 : 1.0, act, nrhs_, c_.st);
@@ -286,7 +293,7 @@ class Runner {
     with_prec(N.prec, [&](auto tag) {
       using TO = decltype(tag);
       Cx<TO>* out = N.v<TO>(N.b);
-      const long si = l == 0 ? h_.lat->g.half : ws_.lv[l].n;
+      const long si = l == 0 ? h_.lat->half : ws_.lv[l].n;
       if (p16)
         transfer_restrict<TO, _Float16, TI, TO>(T, *h_.lat, &h_.L[l], out, in, si, l == 0, act, nrhs_, c_.st);
       else
@@ -300,7 +307,7 @@ class Runner {
     LevelWS& N = ws_.lv[l + 1];
     const Transfer& T = h_.T[l];
     const bool p16 = ws_.prec == KDMG_MIXED;
-    const long so = l == 0 ? h_.lat->g.half : ws_.lv[l].n;
+    const long so = l == 0 ? h_.lat->half : ws_.lv[l].n;
     with_prec(N.prec, [&](auto tag) {
       using TI = decltype(tag);
       const Cx<TI>* in = N.v<TI>(N.xs);
@@ -365,11 +372,15 @@ class Runner {
   int outer(double tol) {
     const kdmg_mg_params& P = h_.params;
     const kdmg_lattice& lat = *h_.lat;
-    const long n = lat.g.half;
+    const long n = lat.half;
     LevelWS& L0 = ws_.lv[0];
     auto op64 = [&](c64* o, const c64* i, const c64* res, const int* a) {
-      schur_apply<double, double>(o, i, res, ws_.tfull.as<c64>(), ws_.wfull.as<c64>(), lat.links64.as<c64>(),
-                                  lat.g, h_.mass, a, nrhs_, c_.st);
+      if (lat.nd == 4)
+        schur_apply4<double, double, double>(o, i, res, ws_.tfull.as<c64>(), ws_.wfull.as<c64>(), fine4_64(), a,
+                                             nrhs_, c_.st);
+      else
+        schur_apply<double, double>(o, i, res, ws_.tfull.as<c64>(), ws_.wfull.as<c64>(), lat.links64.as<c64>(),
+                                    lat.g, h_.mass, a, nrhs_, c_.st);
     };
     auto prec = [&](c64* z, const c64* r, const int* a) {
       if (L0.prec == Prec::F64) {
@@ -390,6 +401,16 @@ class Runner {
 
   int poll_ = 8;
 
+  // 4D fine operands at the hierarchy's mass
+  Fine4<double, double> fine4_64() const {
+    const kdmg_lattice& lat = *h_.lat;
+    return Fine4<double, double>{lat.lk64.as<c64>(), lat.nb4.as<int>(), h_.binv64.as<c64>(), lat.g4, h_.mass};
+  }
+  Fine4<_Float16, float> fine4_mixed() const {
+    const kdmg_lattice& lat = *h_.lat;
+    return Fine4<_Float16, float>{lat.lk16.as<c16>(), lat.nb4.as<int>(), h_.binv32.as<c32>(), lat.g4, h_.mass};
+  }
+
  private:
   kdmg_hierarchy& h_;
   SolveWS& ws_;
@@ -403,7 +424,7 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
   ws->prec = prec;
   const kdmg_mg_params& P = h.params;
   const kdmg_lattice& lat = *h.lat;
-  const long half = lat.g.half, f = 2 * half;
+  const long half = lat.half, f = 2 * half;
   const int maxr = std::max(P.outer_restart, P.inter_restart);
   ws->ctx.init(st, maxr * nrhs + nrhs + 8, nrhs);
   size_t tot = 0;
@@ -472,7 +493,7 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
 
 size_t ws_bytes_estimate(const kdmg_hierarchy& h, int nrhs, kdmg_prec prec) {
   const kdmg_mg_params& P = h.params;
-  const long half = h.lat->g.half, f = 2 * half;
+  const long half = h.lat->half, f = 2 * half;
   size_t b = sizeof(c64) * (size_t)nrhs * (5 * f + (3 + 2 * P.outer_restart) * half);
   for (int l = 0; l < h.nlevels; ++l) {
     const bool coarsest = l == h.nlevels - 1;
@@ -539,9 +560,11 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   const auto t0 = std::chrono::steady_clock::now();
   const kdmg_lattice& lat = *h->lat;
   const Geo2& g = lat.g;
-  const long half = g.half, f = 2 * half, V = lat.volume;
+  const long half = lat.half, f = 2 * half, V = lat.ndof;
   const Ctx& c = ws.ctx.c;
   const c64* L64 = lat.links64.as<c64>();
+  const bool d4 = lat.nd == 4;
+  Runner run(*h, ws);
   // reset statistics
   KDMG_HIP(hipMemsetAsync(ws.kout.ints.p, 0, ws.kout.ints.bytes, st));
   for (auto& L : ws.lv)
@@ -551,24 +574,47 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
                                  nrhs, st);
   launch_map_reduce<1>(OpResidNorm{ws.bfull.as<c64>(), f, f, ws.bnorm2.as<double>()}, f, nrhs, 1, c.rs, st);
   // b~_e = b_e - A_eo b_o = b_e - C_eo B_o^-1 b_o
-  launch_binv<double, double, double>(ws.tfull.as<c64>(), f, nullptr, 0, ws.bfull.as<c64>(), f, nullptr, 0,
-                                      L64, g, 1, 1, h->mass, 0, nullptr, nrhs, st);
-  launch_hop<double, double, double>(ws.bt.as<c64>(), half, ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f,
-                                     nullptr, 0, 0.0, -1.0, L64, g, 0, 1, h->mass, 0, 0, nullptr, nrhs, st);
-  Runner run(*h, ws);
+  if (d4) {
+    const Fine4<double, double> F = run.fine4_64();
+    launch4_binv<double, double>(ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f, nullptr, 0, F.Bv, F.g, 1, 1, 0,
+                                 nullptr, nrhs, st);
+    launch4_hop<double, double>(ws.bt.as<c64>(), half, ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f, nullptr, 0,
+                                0.0, -1.0, F.lk, F.nb4, F.g, 0, 1, F.m, 0, 0, nullptr, nrhs, st);
+  } else {
+    launch_binv<double, double, double>(ws.tfull.as<c64>(), f, nullptr, 0, ws.bfull.as<c64>(), f, nullptr, 0,
+                                        L64, g, 1, 1, h->mass, 0, nullptr, nrhs, st);
+    launch_hop<double, double, double>(ws.bt.as<c64>(), half, ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f,
+                                       nullptr, 0, 0.0, -1.0, L64, g, 0, 1, h->mass, 0, 0, nullptr, nrhs, st);
+  }
   const int its = run.outer(tol);
   // y_o = b_o - C_oe B_e^-1 y_e ; x = B^-1 y
   launch_map(OpStridedCopy{ws.yfull.as<c64>(), f, ws.ye.as<c64>(), half, half}, half, nrhs, st);
-  launch_binv<double, double, double>(ws.tfull.as<c64>(), f, nullptr, 0, ws.ye.as<c64>(), half, nullptr, 0,
-                                      L64, g, 0, 1, h->mass, 0, nullptr, nrhs, st);
-  launch_hop<double, double, double>(ws.yfull.as<c64>(), f, ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f,
-                                     nullptr, 0, 0.0, -1.0, L64, g, 1, 1, h->mass, 0, 0, nullptr, nrhs, st);
-  launch_binv<double, double, double>(ws.xfull.as<c64>(), f, nullptr, 0, ws.yfull.as<c64>(), f, nullptr, 0,
-                                      L64, g, 0, 2, h->mass, 0, nullptr, nrhs, st);
+  if (d4) {
+    const Fine4<double, double> F = run.fine4_64();
+    launch4_binv<double, double>(ws.tfull.as<c64>(), f, ws.ye.as<c64>(), half, nullptr, 0, F.Bv, F.g, 0, 1, 0,
+                                 nullptr, nrhs, st);
+    launch4_hop<double, double>(ws.yfull.as<c64>(), f, ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f, nullptr, 0,
+                                0.0, -1.0, F.lk, F.nb4, F.g, 1, 1, F.m, 0, 0, nullptr, nrhs, st);
+    launch4_binv<double, double>(ws.xfull.as<c64>(), f, ws.yfull.as<c64>(), f, nullptr, 0, F.Bv, F.g, 0, 2, 0,
+                                 nullptr, nrhs, st);
+  } else {
+    launch_binv<double, double, double>(ws.tfull.as<c64>(), f, nullptr, 0, ws.ye.as<c64>(), half, nullptr, 0,
+                                        L64, g, 0, 1, h->mass, 0, nullptr, nrhs, st);
+    launch_hop<double, double, double>(ws.yfull.as<c64>(), f, ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f,
+                                       nullptr, 0, 0.0, -1.0, L64, g, 1, 1, h->mass, 0, 0, nullptr, nrhs, st);
+    launch_binv<double, double, double>(ws.xfull.as<c64>(), f, nullptr, 0, ws.yfull.as<c64>(), f, nullptr, 0,
+                                        L64, g, 0, 2, h->mass, 0, nullptr, nrhs, st);
+  }
   launch_permute<double, double>((c64*)x, V, ws.xfull.as<c64>(), f, lat.perm_full.as<int>(), V, 0, nrhs, st);
   // true residual ||b - D x|| in FP64
-  launch_dslash_blk<double, double, double>(ws.tfull.as<c64>(), f, ws.xfull.as<c64>(), f, ws.bfull.as<c64>(),
-                                            f, L64, g, h->mass, nullptr, nrhs, st);
+  if (d4) {
+    const Fine4<double, double> F = run.fine4_64();
+    launch4_hop<double, double>(ws.tfull.as<c64>(), f, ws.xfull.as<c64>(), f, ws.bfull.as<c64>(), f, nullptr, 0,
+                                0.0, -1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 2, 0, nullptr, nrhs, st);
+  } else {
+    launch_dslash_blk<double, double, double>(ws.tfull.as<c64>(), f, ws.xfull.as<c64>(), f, ws.bfull.as<c64>(),
+                                              f, L64, g, h->mass, nullptr, nrhs, st);
+  }
   launch_map_reduce<1>(OpResidNorm{ws.tfull.as<c64>(), f, f, ws.rnorm2.as<double>()}, f, nrhs, 1, c.rs, st);
   std::vector<double> bn(nrhs), rn(nrhs);
   std::vector<int> kints(4 * nrhs);
