@@ -162,7 +162,7 @@ def serve_main(a):
     from paper_1801_07823_amd import kdmg
     kdmg.kdmg_init(0)
     nv1, nv2 = SERVE_NV
-    params = kdmg.make_params([((4, 4), nv1), ((2, 2), nv2)], coarse_maxit=COARSE_MAXIT, outer_maxit=150)
+    params = kdmg.make_params([((4, 4), nv1), ((2, 2), nv2)], coarse_maxit=COARSE_MAXIT, outer_maxit=80)
     cfgs = []
     t0 = time.perf_counter()
     for L, c, beta, U, plaq in fields:
@@ -287,6 +287,74 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
     return 0
 
 
+# ------------------------------------------------------------------ 4D SU(3)
+
+SU3_DIMS = (24, 24, 24, 24)
+SU3_MASS, SU3_NRHS, SU3_NV = 0.01, 8, 24
+
+
+def su3_main(a):
+    """4D SU(3) workload: 24^4, m = 0.01, smooth random links exp(i 0.4 H)
+    with 5 APE steps (alpha 0.5), 8 Gaussian rhs, two-level KD-MG (2^4 KD
+    blocks, aggregates of 4^4 KD blocks, n_vec 24), FP32 / FP16 V-cycle under
+    FP64 FGCR to 1e-10."""
+    import numpy as np
+    from synth import su3_smooth_random, su3_plaquette, gaussian_vectors
+    t0 = time.perf_counter()
+    U = su3_smooth_random(SU3_DIMS, 0.4, 5, 0.5, 2404)
+    plaq = su3_plaquette(U, SU3_DIMS)
+    print("SU(3) field: %.1f s, plaquette %.4f" % (time.perf_counter() - t0, plaq), file=sys.stderr, flush=True)
+    import torch
+    from paper_1801_07823_amd import kdmg
+    kdmg.kdmg_init(0)
+    lat = kdmg.Lattice(SU3_DIMS, U)
+    n = lat.volume * 3
+    del U
+    params = kdmg.make_params([((4, 4, 4, 4), SU3_NV)], coarse_maxit=1024, outer_maxit=300)
+    psi0 = [gaussian_vectors(SU3_NV, n, 2404, tag=1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = kdmg.Hierarchy(lat, SU3_MASS, params, psi0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print("setup %.2f s" % setup_s, file=sys.stderr, flush=True)
+    b = torch.from_numpy(gaussian_vectors(SU3_NRHS, n, 2404, tag=0)).to("cuda")
+    x = torch.empty_like(b)
+    for i in range(a.warmup):
+        kdmg.kdmg_solve(h, b, x, SU3_NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        info, _ = kdmg.kdmg_solve(h, b, x, SU3_NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
+        print("step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info64, _ = kdmg.kdmg_solve(h, b, x, SU3_NRHS, 1e-10, prec=kdmg.KDMG_FP64)
+    torch.cuda.synchronize()
+    T64 = time.perf_counter() - t1
+    res = {"metric": "KD-MG solves/s, 4D SU(3) 24^4 (mixed precision, 8 rhs, to 1e-10)",
+           "value": SU3_NRHS * a.steps / T, "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": T / a.steps * 1e3, "higher_is_better": True,
+           "dtype": "fp64 outer / fp32 V-cycle (fp16 links, P; fp32 B^-1) / fp64 coarsest",
+           "data": "synthetic", "config": {"workload": "4D SU(3) staggered KD-MG solve", "lattice": list(SU3_DIMS),
+                                            "mass": SU3_MASS, "nrhs": SU3_NRHS,
+                                            "levels": "2: 2^4 KD blocks; 4^4 aggregates n_vec 24 (48x48 complex "
+                                                      "coarse blocks on 3^4 sites)",
+                                            "gauge": "exp(i 0.4 H), 5 APE steps alpha 0.5", "plaquette": plaq},
+           "setup_s": setup_s,
+           "max_true_rel_resid": max(i["true_rel_resid"] for i in info),
+           "iterations": {"outer": [i["outer_its"] for i in info],
+                          "coarse_avg": [round(i["level_avg_its"][0], 1) for i in info]},
+           "fp64_8rhs": {"solves_per_s": SU3_NRHS / T64, "outer": [i["outer_its"] for i in info64],
+                         "max_true_rel_resid": max(i["true_rel_resid"] for i in info64)}}
+    assert all(i["converged"] for i in info)
+    print(json.dumps(res))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +369,7 @@ def main():
     ap.add_argument("--fp64-rhs", type=int, default=1)
     ap.add_argument("--cpu-child", type=int, default=None)
     ap.add_argument("--serve", action="store_true", help="served-stream measurement instead of the bench line")
+    ap.add_argument("--su3", action="store_true", help="4D SU(3) 24^4 measurement instead of the bench line")
     ap.add_argument("--serve-configs", type=int, default=8)
     ap.add_argument("--serve-sweeps", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -320,6 +389,8 @@ def main():
         return 2
     if a.serve:
         return serve_main(a)
+    if a.su3:
+        return su3_main(a)
     cpu = None if (a.no_cpu or a.kernel_profile) else start_cpu_leg(a.cpu_its)
 
     import numpy as np
