@@ -29,13 +29,16 @@ WORKLOAD = {"workload": "2D U(1) staggered KD-MG solve", "lattice": [256, 256], 
             "gauge": "quenched heatbath, 200 sweeps"}
 # HBM traffic of the dominant kernels from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE) over `bench.py --kernel-profile`, in bytes
-# per launch averaged over k_cgne_A and k_cgne_B.  FETCH_SIZE read 32784 KiB
+# per launch averaged over k_cgne_A and k_cgne_B, for the launch shape the
+# tuner picks here (MFMA, blocks staged in LDS, 32 rhs per workgroup, 1024
+# threads; taken from the dispatches of its timing runs, where every rhs is
+# active).  FETCH_SIZE read 32784 KiB
 # and WRITE_SIZE 65536 KiB for a 64 MiB elementwise copy, so FETCH_SIZE is
 # scaled by 2.0 and WRITE_SIZE by 1.0.  Valid only for the kernel source it
 # was measured on (sha256 of coarse_fast.cuh); otherwise reported as null.
-TRAFFIC = {"coarse_fast_sha256": "c122569b3ca739944a0b5499e613fe959e4d3149eebe04e3828e4e8f938d72d5",
+TRAFFIC = {"coarse_fast_sha256": "1242e6f6b6ce2faa674bad0d65b26729eaeefcd747f80f45ff6688223f9b8593",
            "n_vec_2": 12,
-           "bytes_per_launch": ((13658.1 + 12238.0) * 2.0 + (5760.5 + 2911.8) * 1.0) / 2 * 1024}
+           "bytes_per_launch": ((13671.7 + 12258.3) * 2.0 + (6400.0 + 3328.6) * 1.0) / 2 * 1024}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 

@@ -203,6 +203,15 @@ kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int nrhs, doub
    given nrhs unless KDMG_AUTOTUNE=0).  Synchronises `stream`. */
 kdmg_status kdmg_hierarchy_autotune(kdmg_hierarchy* h, int nrhs, kdmg_prec prec, void* stream);
 
+/* Verification of the autotuner's search space (not an operation of the
+   method): applies the level's stencil (or its adjoint) with every launch
+   shape the tuner may pick for (nrhs, prec), candidate c writing
+   out[c][rhs][site][dof] (caller-allocated, at least max_out candidates).
+   *ncand receives the number of candidates.  Synchronises `stream`. */
+kdmg_status kdmg_coarse_apply_candidates(const kdmg_hierarchy* h, int level, int dagger, const void* in,
+                                         void* out, int nrhs, kdmg_prec prec, int max_out, int* ncand,
+                                         void* stream);
+
 /* Device bytes held by the hierarchy including its solve workspace for
    `nrhs` right-hand sides (admission control). */
 kdmg_status kdmg_hierarchy_footprint(const kdmg_hierarchy* h, int nrhs, size_t* bytes);

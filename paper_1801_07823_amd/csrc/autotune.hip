@@ -21,16 +21,20 @@ std::vector<TileShape> tile_candidates(int ndc, int nrhs, int ndir, size_t esz) 
     for (int NT : {1, 2}) {
       if (NT == 2 && nrhs < 32) continue;
       for (int ylds : {1, 0}) {
-        for (int minthr : {256, 512, 1024}) {
-          TileShape s;
-          s.core = 1;
-          s.MT = (ndc + 15) / 16;
-          s.NT = NT;
-          s.RT = 16 * NT;
-          s.ylds = ylds;
-          s.threads = std::max(64 * s.MT * s.NT, minthr);
-          s.smem = lds_layout(s, ndc, ndir, esz).total;
-          if (s.smem <= LDS_LIMIT && s.threads <= 1024) out.push_back(s);
+        for (int ks : {1, 2, 3, 4}) {  // k-split of the MFMA contraction over wave groups
+          for (int minthr : {256, 512, 1024}) {
+            TileShape s;
+            s.core = 1;
+            s.MT = (ndc + 15) / 16;
+            s.NT = NT;
+            s.RT = 16 * NT;
+            s.ylds = ylds;
+            s.KS = ks;
+            s.threads = std::max(64 * s.MT * s.NT * ks, minthr);
+            if (ks > 1 && minthr != 256) continue;  // k-split shapes: exactly the waves they use
+            s.smem = lds_layout(s, ndc, ndir, esz).total;
+            if (s.smem <= LDS_LIMIT && s.threads <= 1024) out.push_back(s);
+          }
         }
       }
     }
@@ -190,6 +194,32 @@ extern "C" kdmg_status kdmg_hierarchy_autotune(kdmg_hierarchy* h, int nrhs, kdmg
     autotune_level(h->L[l], nrhs, fp32, st);
   }
   autotune_cgne(h->L[h->nlevels - 1], nrhs, st);
+  KDMG_HIP(hipStreamSynchronize(st));
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_coarse_apply_candidates(const kdmg_hierarchy* h, int level, int dagger, const void* in,
+                                                    void* out, int nrhs, kdmg_prec prec, int max_out, int* ncand,
+                                                    void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && in && out && ncand && nrhs >= 1 && max_out >= 0, KDMG_EINVAL,
+             "kdmg_coarse_apply_candidates: bad argument");
+  KDMG_CHECK(level >= 1 && level < h->nlevels, KDMG_EINVAL, "kdmg_coarse_apply_candidates: bad level");
+  const CoarseLevel& L = h->L[level];
+  hipStream_t st = (hipStream_t)stream;
+  const bool f32 = prec == KDMG_MIXED;
+  const size_t esz = f32 ? sizeof(c32) : sizeof(c64);
+  const auto cands = tile_candidates(L.ndc, nrhs, L.ndir, esz);
+  *ncand = (int)cands.size();
+  const long n = (long)nrhs * L.nsites * L.ndc;
+  for (int c = 0; c < (int)cands.size() && c < max_out; ++c) {
+    if (f32)
+      coarse_apply_shape<float, float>(L, dagger != 0, (c32*)out + c * n, (const c32*)in, nullptr, 1.0, nullptr, nrhs,
+                                       st, cands[c]);
+    else
+      coarse_apply_shape<double, double>(L, dagger != 0, (c64*)out + c * n, (const c64*)in, nullptr, 1.0, nullptr,
+                                         nrhs, st, cands[c]);
+  }
   KDMG_HIP(hipStreamSynchronize(st));
   KDMG_API_END
 }

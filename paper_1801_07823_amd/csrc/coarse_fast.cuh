@@ -26,6 +26,8 @@
 // parity because workgroup 0 updates it while other workgroups of the same
 // kernel still read the previous values.
 #pragma once
+#include <algorithm>
+
 #include "common.h"
 #include "blas.cuh"
 
@@ -110,7 +112,10 @@ inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz) {
     o += (bytes + 15) & ~size_t(15);
     return at;
   };
-  L.ys = take(s.core && s.ylds ? (size_t)ndir * ndc * ndc * esz : 0);  // else blocks read from global
+  // stencil blocks (else read from global); also the MFMA k-split partials,
+  // written after the contraction
+  L.ys = take(std::max(s.core && s.ylds ? (size_t)ndir * ndc * ndc * esz : 0,
+                       s.core && s.KS > 1 ? (size_t)(s.KS - 1) * s.MT * s.NT * 256 * esz : 0));
   L.vs = take((size_t)ndir * ndc * panel_stride(s.RT) * esz);
   int nib = s.core ? 0 : ndc / s.TI, nrb = s.core ? 0 : s.RT / s.TR;
   L.red = take(s.core ? 0 : (size_t)(s.KS - 1) * nib * nrb * s.TI * s.TR * esz);
@@ -341,14 +346,21 @@ __device__ __forceinline__ void core_simt(Frag<R, TI * TR>& f, const Cx<OT>* __r
 // operand (stencil blocks) comes from LDS (YL = 1) or straight from global
 // memory with loads issued one chunk pair ahead (YL = 0).
 template <class R, class OT, int YL>
-__device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const Cx<OT>* __restrict__ Yt, int X,
-                                          int nsites, const Cx<R>* Vs, int ndc, int ndir, int RT, int MT, int NT) {
+__device__ __forceinline__ void core_mfma(Frag<R, 4>& f, Cx<R>* Ys, const Cx<OT>* __restrict__ Yt, int X,
+                                          int nsites, const Cx<R>* Vs, int ndc, int ndir, int RT, int MT, int NT,
+                                          int KS) {
   using M = Mfma<R>;
   typedef typename M::v4 v4;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const bool on = w < MT * NT;
-  const int mt = on ? w % MT : 0, nt = on ? w / MT : 0;
+  const int ntile = MT * NT, tile = w % ntile, split = w / ntile;
+  // k-split factor, limited to the wave groups the workgroup actually has
+  const int KSP = max(1, min(KS, (int)(blockDim.x >> 6) / ntile));
+  const bool on = split < KSP;
+  const int mt = on ? tile % MT : 0, nt = on ? tile / MT : 0;
   const int K = ndir * ndc, nkc = (K + 3) / 4;
+  // k-split: wave group `split` takes a contiguous range of chunk pairs
+  const int npairs = (nkc + 1) / 2, share = (npairs + KSP - 1) / KSP;
+  const int pb = on ? split * share : 0, pe = on ? min(npairs, (split + 1) * share) : 0;
   const int ia = mt * 16 + (l & 15);      // A-operand row held by this lane
   const int cb = nt * 16 + (l & 15);      // B-operand column held by this lane
   const int kk = l >> 4;
@@ -371,9 +383,10 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const 
   // flight.
   v4 p1a = {0, 0, 0, 0}, p2a = {0, 0, 0, 0}, p3a = {0, 0, 0, 0};
   v4 p1b = {0, 0, 0, 0}, p2b = {0, 0, 0, 0}, p3b = {0, 0, 0, 0};
-  if (on) {
-    Cx<R> a0 = loadA(kk), a1 = loadA(kk + 4), b0 = loadB(kk), b1 = loadB(kk + 4);
-    for (int kc = 0; kc < nkc; kc += 2) {
+  if (on && pb < pe) {
+    const int kb0 = 8 * pb + kk;
+    Cx<R> a0 = loadA(kb0), a1 = loadA(kb0 + 4), b0 = loadB(kb0), b1 = loadB(kb0 + 4);
+    for (int kc = 2 * pb; kc < 2 * pe; kc += 2) {
       const int k0 = 4 * kc + kk, k1 = k0 + 4;
       // operands of the next chunk pair, fetched before this pair's MFMAs
       const Cx<R> na0 = loadA(k0 + 8), na1 = loadA(k1 + 8);
@@ -390,7 +403,7 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const 
       b1 = nb1;
     }
   }
-  f.slot = on ? mt * 4 + (l >> 4) : -1;
+  f.slot = on && split == 0 ? mt * 4 + (l >> 4) : -1;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = mt * 16 + M::row(l, v);
@@ -398,7 +411,20 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, const Cx<R>* Ys, const 
     f.val[v] = Cx<R>{q1 - q2, q3 - q1 - q2};
     f.i[v] = i;
     f.t[v] = cb;
-    f.ok[v] = on && i < ndc && cb < RT;
+    f.ok[v] = on && split == 0 && i < ndc && cb < RT;
+  }
+  if (KSP > 1) {
+    // wave groups 1 .. KSP-1 hand their partial tiles to group 0 through the
+    // (now unused) stencil-block region; group 0 adds them in split order
+    __syncthreads();
+    if (on && split > 0)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ys[((split - 1) * ntile + tile) * 256 + l * 4 + v] = f.val[v];
+    __syncthreads();
+    if (on && split == 0)
+      for (int q = 1; q < KSP; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f.val[v] += Ys[((q - 1) * ntile + tile) * 256 + l * 4 + v];
   }
 }
 
@@ -406,10 +432,10 @@ template <class R, class OT, int CORE, int TI, int TR, int YL>
 __device__ __forceinline__ void run_core(Frag<R, FragN<CORE, TI, TR>::value>& f, unsigned char* raw,
                                          const LdsLayout& L, const Cx<OT>* Yt, int X, int nsites, int ndc,
                                          int ndir, int RT, int KS, int MT, int NT) {
-  const Cx<R>* Ys = reinterpret_cast<const Cx<R>*>(raw + L.ys);
+  Cx<R>* Ys = reinterpret_cast<Cx<R>*>(raw + L.ys);
   const Cx<R>* Vs = reinterpret_cast<const Cx<R>*>(raw + L.vs);
   if constexpr (CORE == 1)
-    core_mfma<R, OT, YL>(f, Ys, Yt, X, nsites, Vs, ndc, ndir, RT, MT, NT);
+    core_mfma<R, OT, YL>(f, Ys, Yt, X, nsites, Vs, ndc, ndir, RT, MT, NT, KS);
   else
     core_simt<R, OT, TI, TR>(f, Yt, X, nsites, Vs, reinterpret_cast<Cx<R>*>(raw + L.red), ndc, ndir, RT, KS);
 }
@@ -424,7 +450,9 @@ __device__ __forceinline__ LdsLayout lds_layout_dev(int core, int ylds, int RT, 
     o += (bytes + 15) & ~size_t(15);
     return at;
   };
-  L.ys = take(core && ylds ? (size_t)ndir * ndc * ndc * esz : 0);
+  const size_t ysz = core && ylds ? (size_t)ndir * ndc * ndc * esz : 0;
+  const size_t ksz = core && KS > 1 ? (size_t)(KS - 1) * MT * (RT / 16) * 256 * esz : 0;
+  L.ys = take(ysz > ksz ? ysz : ksz);
   L.vs = take((size_t)ndir * ndc * panel_stride(RT) * esz);
   const int nib = core ? 0 : ndc / TI, nrb = core ? 0 : RT / TR;
   L.red = take(core ? 0 : (size_t)(KS - 1) * nib * nrb * TI * TR * esz);

@@ -78,6 +78,7 @@ _SIGS = {
     "kdmg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(kdmg_solve_info), _P]),
     "kdmg_hierarchy_footprint": (_I, [_P, _I, ctypes.POINTER(_S)]),
     "kdmg_hierarchy_autotune": (_I, [_P, _I, _I, _P]),
+    "kdmg_coarse_apply_candidates": (_I, [_P, _I, _I, _P, _P, _I, _I, _I, ctypes.POINTER(_I), _P]),
     "kdmg_hierarchy_at_mass": (_I, [_P, _D, _P, ctypes.POINTER(_P)]),
     "kdmg_hierarchy_set_mass": (_I, [_P, _P, _D, _P]),
     "kdmg_hierarchy_graphs": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
@@ -279,6 +280,14 @@ class Hierarchy:
 def kdmg_coarse_apply(h, level, inp, out, nrhs, dagger=False, prec=KDMG_FP64, stream=None):
     _check(_lib.kdmg_coarse_apply(h.handle, level, 1 if dagger else 0, _ptr(inp), _ptr(out), nrhs,
                                   prec, _stream(stream)))
+
+
+def kdmg_coarse_apply_candidates(h, level, inp, out, nrhs, dagger=False, prec=KDMG_FP64, stream=None):
+    """Every tuner candidate's stencil apply: out[c] for c < out.shape[0]; returns the candidate count."""
+    nc = _I()
+    _check(_lib.kdmg_coarse_apply_candidates(h.handle, level, 1 if dagger else 0, _ptr(inp), _ptr(out), nrhs, prec,
+                                             out.shape[0], ctypes.byref(nc), _stream(stream)))
+    return nc.value
 
 
 def kdmg_restrict(h, k, inp, out, nrhs, stream=None):

@@ -445,3 +445,32 @@ def test_cgne_graph_replay_matches_eager(K):
     for arrs in outs.values():
         for a in arrs:
             assert np.array_equal(a, ref)
+
+
+@pytest.mark.parametrize("nv,nrhs", [(12, 32), (8, 20), (12, 5)])
+def test_every_tuner_candidate(K, nv, nrhs):
+    """Every launch shape the autotuner may choose (MFMA tiles with and
+    without staged blocks and with 1-4 way k-splits, SIMT tiles) gives the
+    coarse stencil and its adjoint, FP64 and FP32, to the oracle's bar."""
+    dims, beta, m = (32, 32), 6.0, 0.02
+    levels = [((4, 4), nv), ((2, 2), nv)]
+    U = field(dims, beta)
+    oh, _ = oracle_setup(dims, U, m, levels, 25)
+    lat = K.Lattice(dims, U)
+    gh = K.Hierarchy(lat, m, gpu_params(K, levels), oh.nullvecs, relaxed=True)
+    for level in (1, 2):
+        n = gh.ndof(level)
+        v = gaussian_vectors(nrhs, n, 70 + level + nrhs)
+        A = oh.ops[level]
+        for dag, ref in ((False, A), (True, A.conj().T)):
+            r = (ref @ v.T).T
+            for prec, dt, bar in ((K.KDMG_FP64, torch.complex128, 1e-12), (K.KDMG_MIXED, torch.complex64, 1e-5)):
+                out = torch.empty((64, nrhs, n), dtype=dt, device="cuda")
+                nc = K.kdmg_coarse_apply_candidates(gh, level, dev(v, dt), out, nrhs, dagger=dag, prec=prec)
+                assert 1 <= nc <= 64
+                got = out[:nc].cpu().numpy()
+                for c in range(nc):
+                    if prec == K.KDMG_FP64:
+                        assert relerr(got[c], r) < bar, c
+                    else:
+                        assert np.linalg.norm(got[c] - r) / np.linalg.norm(r) < bar, c
