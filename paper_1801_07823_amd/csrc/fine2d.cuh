@@ -226,7 +226,13 @@ __global__ __launch_bounds__(256) void k_dslash_nat(Cx<VT>* __restrict__ out, co
                                                     const Cx<LT>* __restrict__ Ux,
                                                     const Cx<LT>* __restrict__ Ut, int Lx, int Lt,
                                                     long vol, R m, int nrhs) {
-  const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // Workgroups go to the 8 XCDs round-robin (XCD = blockIdx.x % 8), each with
+  // its own L2.  Renumber them so every XCD sweeps one contiguous range of
+  // sites: the rows x1 +- 1 a workgroup needs were then just read by the same
+  // XCD and are still in its L2.
+  const unsigned nb = gridDim.x;
+  const unsigned lb = (nb % 8u == 0) ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+  const long x = (long)lb * blockDim.x + threadIdx.x;
   const int r0 = blockIdx.y * RB;
   if (x >= vol) return;
   const int x1 = (int)(x / Lx), x0 = (int)(x - (long)x1 * Lx);
