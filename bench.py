@@ -144,9 +144,9 @@ SERVE_SETUP_TOL, SERVE_SETUP_MAXIT = 1e-6, 1000
 
 
 def _serve_field(args):
-    L, c, sweeps = args
+    L, c, sweeps, betas = args
     from synth import u1_heatbath, config_seed
-    beta = SERVE_BETAS[c % 3]
+    beta = betas[c % len(betas)]
     U, info = u1_heatbath((L, L), beta, sweeps, config_seed(L, beta, c))
     return L, c, beta, U, info["plaquette"]
 
@@ -155,13 +155,15 @@ def serve_main(a):
     """Served stream of single-rhs mixed-precision solves through kdmg_server:
     lattice sizes uniform in {64,128,256,512}^2, masses log-uniform in
     [1e-3, 1e-1], each request on one of `--serve-configs` resident
-    configurations per size (beta cycling 3, 6, 10).  Reports the closed-loop
+    configurations per size (beta cycling through `--serve-betas`, by default
+    3, 6, 10).  Reports the closed-loop
     capacity, then p50/p99 latency and solves/s for Poisson arrivals at
     fractions of it, and checks a sample of results alone against the mix."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
     from synth import gaussian_vectors, config_seed
-    jobs = [(L, c, a.serve_sweeps) for L in SERVE_SIZES for c in range(a.serve_configs)]
+    betas = tuple(a.serve_betas)
+    jobs = [(L, c, a.serve_sweeps, betas) for L in SERVE_SIZES for c in range(a.serve_configs)]
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=min(16, len(jobs))) as ex:
         fields = list(ex.map(_serve_field, jobs))
@@ -209,6 +211,8 @@ def serve_main(a):
                     st, info, times = r
                     lat_s[i], infos[i] = times[2], info[0]
                     xs[i] = xd
+                    if len(lat_s) % 8 == 0:
+                        print("  %d of %d requests done" % (len(lat_s), len(reqs)), file=sys.stderr, flush=True)
                     if st != kdmg.KDMG_OK:
                         k, m, L, _ = reqs[i]
                         failures.append({"L": L, "config": k, "mass": m, "status": st,
@@ -250,8 +254,9 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
     closed = make_requests(a.serve_closed, 1)
     lat_c, info_c, _, span = run(srv, ids, closed, None)
     cap = len(closed) / span
-    print("closed loop: %d requests in %.2f s -> %.2f solves/s" % (len(closed), span, cap), file=sys.stderr,
-          flush=True)
+    closed_ok = sum(int(info_c[i]["converged"]) for i in range(len(closed)))
+    print("closed loop: %d requests (%d converged) in %.2f s -> %.2f requests/s" % (len(closed), closed_ok, span, cap),
+          file=sys.stderr, flush=True)
     points = []
     for frac in a.serve_fracs:
         qps = frac * cap
@@ -259,17 +264,27 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
         arr = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
         lat_s, infos, xs, span = run(srv, ids, reqs, list(arr))
         v = np.array([lat_s[i] for i in range(len(reqs))])
-        worst = max(infos[i]["true_rel_resid"] for i in range(len(reqs)))
-        by_size = {}
+        ok = [i for i in range(len(reqs)) if infos[i]["converged"]]
+        vok = v[ok] if ok else np.zeros(1)
+        worst = max([infos[i]["true_rel_resid"] for i in ok] or [0.0])
+        by_size, by_beta = {}, {}
         for i, (k, m, L, sd) in enumerate(reqs):
             by_size.setdefault(L, []).append(lat_s[i])
+            nb = by_beta.setdefault(str(cfgs[k][2]), [0, 0])
+            nb[0] += 1
+            nb[1] += int(not infos[i]["converged"])
         points.append({"offered_qps": qps, "fraction_of_capacity": frac, "requests": len(reqs),
-                       "solves_per_s": len(reqs) / span, "p50_s": float(np.percentile(v, 50)),
-                       "p99_s": float(np.percentile(v, 99)), "max_true_rel_resid": worst,
+                       "converged": len(ok), "solves_per_s": len(ok) / span, "requests_per_s": len(reqs) / span,
+                       "p50_s": float(np.percentile(v, 50)), "p99_s": float(np.percentile(v, 99)),
+                       "p50_s_converged": float(np.percentile(vok, 50)),
+                       "p99_s_converged": float(np.percentile(vok, 99)),
+                       "max_true_rel_resid_converged": worst,
+                       "requests_failed_by_beta": {b: "%d of %d" % (n[1], n[0]) for b, n in sorted(by_beta.items())},
                        "p50_s_by_L": {str(L): float(np.percentile(t, 50)) for L, t in sorted(by_size.items())}})
-        print("qps %.2f: p50 %.3f s p99 %.3f s, %.2f solves/s" % (qps, points[-1]["p50_s"], points[-1]["p99_s"],
-                                                                 points[-1]["solves_per_s"]),
-              file=sys.stderr, flush=True)
+        pt = points[-1]
+        print("qps %.2f: p50 %.3f s p99 %.3f s (converged only: %.3f / %.3f), %.2f solves/s, failed by beta %s"
+              % (qps, pt["p50_s"], pt["p99_s"], pt["p50_s_converged"], pt["p99_s_converged"], pt["solves_per_s"],
+                 pt["requests_failed_by_beta"]), file=sys.stderr, flush=True)
         last = (reqs, xs)
     stats = srv.stats()
     srv.close()
@@ -284,9 +299,11 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
         alone.close()
     diffs = [float(torch.linalg.norm(xs[i] - xs1[j]) / torch.linalg.norm(xs1[j])) for j, i in enumerate(sample)]
     res = {"metric": "served KD-MG solves, 2D U(1), L^2 in {64,128,256,512}^2, m log-uniform in [1e-3, 1e-1]",
-           "unit": "solves/s", "closed_loop_solves_per_s": cap, "points": points,
+           "unit": "solves/s", "closed_loop_requests_per_s": cap,
+           "closed_loop_solves_per_s": closed_ok / span, "closed_loop_requests": len(closed),
+           "closed_loop_converged": closed_ok, "points": points,
            "slots": a.serve_slots, "hbm_budget_gb": a.serve_budget_gb, "configs": len(cfgs),
-           "configs_per_size": a.serve_configs, "heatbath_sweeps": a.serve_sweeps,
+           "configs_per_size": a.serve_configs, "betas": list(a.serve_betas), "heatbath_sweeps": a.serve_sweeps,
            "setup_mass": SERVE_M_SETUP, "prec": "mixed", "tol": 1e-10,
            "levels": "4x4 n_vec %d; 2x2 n_vec %d" % SERVE_NV,
            "setup_relaxation": {"tol": SERVE_SETUP_TOL, "maxit": SERVE_SETUP_MAXIT},
@@ -382,6 +399,7 @@ def main():
     ap.add_argument("--su3", action="store_true", help="4D SU(3) 24^4 measurement instead of the bench line")
     ap.add_argument("--serve-configs", type=int, default=8)
     ap.add_argument("--serve-sweeps", type=int, default=200)
+    ap.add_argument("--serve-betas", type=float, nargs="+", default=list(SERVE_BETAS))
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-closed", type=int, default=48)

@@ -82,6 +82,10 @@ struct LdsLayout {
 // stores of the dof-fastest gather off a single bank
 __host__ __device__ __forceinline__ int panel_stride(int RT) { return RT + 1; }
 
+// panel rows (contraction index k = dir * ndc + j) rounded up to the 8 of an
+// MFMA chunk pair; rows [ndir * ndc, kpad8) are zero
+__host__ __device__ __forceinline__ int kpad8(int K) { return (K + 7) & ~7; }
+
 // floor(e / n) through the float reciprocal inv = 1.0f / n: exact whenever
 // 0 <= e and e + n < 2^22 (the relative error of the product, < 2^-23, stays
 // below the distance 0.5 / n of (e + 0.5) / n to the nearest integer).  All
@@ -116,7 +120,7 @@ inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz) {
   // written after the contraction
   L.ys = take(std::max(s.core && s.ylds ? (size_t)ndir * ndc * ndc * esz : 0,
                        s.core && s.KS > 1 ? (size_t)(s.KS - 1) * s.MT * s.NT * 256 * esz : 0));
-  L.vs = take((size_t)ndir * ndc * panel_stride(s.RT) * esz);
+  L.vs = take((size_t)kpad8(ndir * ndc) * panel_stride(s.RT) * esz);
   int nib = s.core ? 0 : ndc / s.TI, nrb = s.core ? 0 : s.RT / s.TR;
   L.red = take(s.core ? 0 : (size_t)(s.KS - 1) * nib * nrb * s.TI * s.TR * esz);
   const int nsl = s.core ? s.MT * 4 : nib;
@@ -195,7 +199,8 @@ constexpr int YU = 4, SU = 8;
 // every load of a pass (stencil blocks, panel, partial sums) is issued before
 // any is consumed, so the common shapes pay a single memory round trip.
 //   Ys[(d*ndc + j)*ndc + i] = Y_dir(X)[i][j]            (when Ys != null)
-//   Vs[(d*ndc + j)*RTP + r] = v[r0 + r][nbr(X, d)][j]    (rhs >= nrhs read as 0)
+//   Vs[(d*ndc + j)*RTP + r] = v[r0 + r][nbr(X, d)][j]    (rhs >= nrhs read as 0;
+//                                                         rows up to kpad8 zero)
 // With P != null ([rhs][site] partial sums of the previous kernel) the lane
 // g of rhs group t (t = tid / GS, g = tid % GS, GS = group_size(RT)) sums
 // P[r0 + t][g + k GS] over k in increasing order; the group's lanes are then
@@ -254,6 +259,9 @@ __device__ __forceinline__ void stage_all(Cx<R>* Ys, Cx<R>* Vs, const Cx<OT>* __
 #pragma unroll
     for (int u = 0; u < SU; ++u) acc += ts[u];
   }
+  // zero panel rows [ndir * ndc, kpad8) for the MFMA core's last chunk pair
+  const int K = ndir * ndc, kz = (kpad8(K) - K) * RTP;
+  for (int e = tid; e < kz; e += nthr) Vs[K * RTP + e] = Cx<R>{0, 0};
   if (P) {
     const double sum = group_sum(acc, GS);
     if (g == 0 && t < RT) tot[t] = sum;
@@ -351,32 +359,40 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, Cx<R>* Ys, const Cx<OT>
                                           int KS) {
   using M = Mfma<R>;
   typedef typename M::v4 v4;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  // the wave index is uniform over the wave: keeping it in a scalar register
+  // makes the tile bookkeeping and the k-loop control scalar
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
   const int ntile = MT * NT, tile = w % ntile, split = w / ntile;
   // k-split factor, limited to the wave groups the workgroup actually has
   const int KSP = max(1, min(KS, (int)(blockDim.x >> 6) / ntile));
   const bool on = split < KSP;
   const int mt = on ? tile % MT : 0, nt = on ? tile / MT : 0;
-  const int K = ndir * ndc, nkc = (K + 3) / 4;
+  const int K = ndir * ndc, K8 = kpad8(K), nkc = K8 / 4;
   // k-split: wave group `split` takes a contiguous range of chunk pairs
-  const int npairs = (nkc + 1) / 2, share = (npairs + KSP - 1) / KSP;
+  const int npairs = nkc / 2, share = (npairs + KSP - 1) / KSP;
   const int pb = on ? split * share : 0, pe = on ? min(npairs, (split + 1) * share) : 0;
   const int ia = mt * 16 + (l & 15);      // A-operand row held by this lane
   const int cb = nt * 16 + (l & 15);      // B-operand column held by this lane
   const int kk = l >> 4;
-  const bool arow = ia < ndc;
   const long per = (long)ndc * ndc;
+  // Operand loads carry no condition, so the compiler can keep the next
+  // chunk pair's loads in flight across the current pair's MFMAs:
+  //  * rows ia >= ndc of the last 16-row tile read row ndc - 1; their outputs
+  //    are dropped;
+  //  * k >= K reads stencil column K - 1 against the panel's zero rows
+  //    [K, K8); prefetches past the end are clamped and never used.
+  const int iac = min(ia, ndc - 1);
   auto loadA = [&](int k) -> Cx<R> {
-    if (k >= K || !arow) return Cx<R>{0, 0};
+    const int kc = min(k, K - 1);
     if constexpr (YL == 1) {
-      return Ys[k * ndc + ia];
+      return Ys[kc * ndc + iac];
     } else {
-      const int d = fdiv(k, 1.0f / (float)ndc), j = k - d * ndc;
-      return ld<R>(Yt[((long)d * nsites + X) * per + (long)j * ndc + ia]);
+      const int d = fdiv(kc, 1.0f / (float)ndc), j = kc - d * ndc;
+      return ld<R>(Yt[((long)d * nsites + X) * per + (long)j * ndc + iac]);
     }
   };
   const int RTP = panel_stride(RT);
-  auto loadB = [&](int k) -> Cx<R> { return k < K ? Vs[k * RTP + cb] : Cx<R>{0, 0}; };
+  auto loadB = [&](int k) -> Cx<R> { return Vs[min(k, K8 - 1) * RTP + cb]; };
   // Three real products per complex one (Gauss): with P1 = Ar Br,
   // P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi):  Re = P1 - P2, Im = P3 - P1 - P2.
   // Two accumulator sets (even / odd k-chunks) keep independent MFMAs in
@@ -453,7 +469,7 @@ __device__ __forceinline__ LdsLayout lds_layout_dev(int core, int ylds, int RT, 
   const size_t ysz = core && ylds ? (size_t)ndir * ndc * ndc * esz : 0;
   const size_t ksz = core && KS > 1 ? (size_t)(KS - 1) * MT * (RT / 16) * 256 * esz : 0;
   L.ys = take(ysz > ksz ? ysz : ksz);
-  L.vs = take((size_t)ndir * ndc * panel_stride(RT) * esz);
+  L.vs = take((size_t)kpad8(ndir * ndc) * panel_stride(RT) * esz);
   const int nib = core ? 0 : ndc / TI, nrb = core ? 0 : RT / TR;
   L.red = take(core ? 0 : (size_t)(KS - 1) * nib * nrb * TI * TR * esz);
   const int nsl = core ? MT * 4 : nib;
@@ -642,10 +658,11 @@ __global__ __launch_bounds__(1024) void k_cgne_A(Cx<R>* x, Cx<R>* r, const Cx<R>
   double* sc = reinterpret_cast<double*>(smem_raw + L.sc);
   int* live = reinterpret_cast<int*>(smem_raw + L.live);
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT, sl = (k & 1) * nrhs;
-  // nothing to do once every rhs of the tile has stopped (the host polls the
-  // flags asynchronously, so a few iterations past convergence are launched)
+  // Nothing to do once every rhs of the tile has stopped (the host polls the
+  // flags asynchronously, so a few iterations past convergence are
+  // launched).  The flags are tested at the barrier after the staging, so
+  // their load overlaps the staging loads (which only read).
   const int mine = threadIdx.x < RT && r0 + (int)threadIdx.x < nrhs ? s.act[sl + r0 + threadIdx.x] : 0;
-  if (!__syncthreads_or(mine)) return;
   const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
   const FirstElem fe = first_elem(X, nsites, ndc, r0, RT, nrhs);
   Cx<R> x0{0, 0}, r0v{0, 0};
@@ -654,7 +671,7 @@ __global__ __launch_bounds__(1024) void k_cgne_A(Cx<R>* x, Cx<R>* r, const Cx<R>
     r0v = r[fe.o];
   }
   cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yt, p, nb, X, nsites, ndc, ndir, r0, RT, nrhs, s.PB, sc + 2 * RT);
-  __syncthreads();
+  if (!__syncthreads_or(mine)) return;
   if (threadIdx.x < RT) {
     const int t = threadIdx.x, rr = r0 + t;
     const double pp = sc[2 * RT + t];
@@ -701,7 +718,13 @@ __global__ __launch_bounds__(1024) void k_cgne_B(Cx<R>* p, const Cx<R>* r, const
   int* live = reinterpret_cast<int*>(smem_raw + L.live);
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT, RT = ta.RT;
   const int sl = (k & 1) * nrhs, sn = ((k + 1) & 1) * nrhs;
+  // flags tested after the staging, as in k_cgne_A
   const int mine = threadIdx.x < RT && r0 + (int)threadIdx.x < nrhs ? s.act[sl + r0 + threadIdx.x] : 0;
+  const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
+  const FirstElem fe = first_elem(X, nsites, ndc, r0, RT, nrhs);
+  Cx<R> p0{0, 0};
+  if (fe.on) p0 = p[fe.o];
+  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nb, X, nsites, ndc, ndir, r0, RT, nrhs, s.PA, sc + 2 * RT);
   if (!__syncthreads_or(mine)) {
     // every rhs of the tile has stopped: carry the state into the next slot
     if (X == 0 && threadIdx.x < RT && r0 + (int)threadIdx.x < nrhs) {
@@ -711,12 +734,6 @@ __global__ __launch_bounds__(1024) void k_cgne_B(Cx<R>* p, const Cx<R>* r, const
     }
     return;
   }
-  const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
-  const FirstElem fe = first_elem(X, nsites, ndc, r0, RT, nrhs);
-  Cx<R> p0{0, 0};
-  if (fe.on) p0 = p[fe.o];
-  cgne_stage<R, OT, CORE, YL>(smem_raw, L, Yd, r, nb, X, nsites, ndc, ndir, r0, RT, nrhs, s.PA, sc + 2 * RT);
-  __syncthreads();
   if (threadIdx.x < RT) {
     const int t = threadIdx.x, rr = r0 + t;
     const double rn = sc[2 * RT + t];
