@@ -382,6 +382,57 @@ def su3_main(a):
     return 0
 
 
+# ------------------------------------------------------------------ transfer operators
+
+XF_DIMS, XF_NV, XF_NRHS = (2048, 2048), 16, 32
+
+
+def transfer_main(a):
+    """Level-0 restriction and prolongation in the mixed form (FP16-stored P,
+    FP32 vectors), 32 rhs per call as in the solve, on a 2048^2 lattice whose P (268 MB) and
+    vectors exceed the Infinity Cache; the hierarchy is built from random
+    vectors taken as relaxed.  Run under `rocprofv3 --kernel-trace --stats`
+    for the k_restrict1 / k_prolong1 kernel times; the API-level times printed
+    here include the lexicographic <-> block-layout permutation and a
+    temporary allocation."""
+    import numpy as np
+    import torch
+    from paper_1801_07823_amd import kdmg
+    from synth import gaussian_vectors
+    kdmg.kdmg_init(0)
+    V = XF_DIMS[0] * XF_DIMS[1]
+    rng = np.random.default_rng(7)
+    U = np.exp(1j * rng.uniform(0, 2 * np.pi, size=(2, V, 1, 1)))
+    lat = kdmg.Lattice(XF_DIMS, U)
+    del U
+    psi = [gaussian_vectors(XF_NV, V, 71, tag=1)]
+    h = kdmg.Hierarchy(lat, MASS, kdmg.make_params([((4, 4), XF_NV)]), psi, relaxed=True)
+    del psi
+    nc = h.ndof(1)
+    v = torch.randn((XF_NRHS, V), dtype=torch.complex64, device="cuda")
+    c = torch.empty((XF_NRHS, nc), dtype=torch.complex64, device="cuda")
+    w = torch.empty_like(v)
+    reps = 20
+    res = {}
+    for name, fn in (("restrict", lambda: kdmg.kdmg_restrict(h, 0, v, c, XF_NRHS, prec=kdmg.KDMG_MIXED)),
+                     ("prolong", lambda: kdmg.kdmg_prolong(h, 0, c, w, XF_NRHS, prec=kdmg.KDMG_MIXED))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name + "_api_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        print("%s: %.3f ms per call (API level)" % (name, res[name + "_api_ms"]), file=sys.stderr, flush=True)
+    # algorithmic bytes per kernel launch (all of P, FP16: 4 B per complex;
+    # FP32 vectors: 8 B per complex)
+    res.update({"lattice": list(XF_DIMS), "nv": XF_NV, "nrhs": XF_NRHS, "coarse_dof": nc,
+                "restrict_bytes": 4 * V * XF_NV + 8 * V * XF_NRHS + 8 * nc * XF_NRHS,
+                "prolong_bytes": 4 * V * XF_NV + 8 * nc * XF_NRHS + 8 * V * XF_NRHS})
+    print(json.dumps(res))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -397,6 +448,8 @@ def main():
     ap.add_argument("--cpu-child", type=int, default=None)
     ap.add_argument("--serve", action="store_true", help="served-stream measurement instead of the bench line")
     ap.add_argument("--su3", action="store_true", help="4D SU(3) 24^4 measurement instead of the bench line")
+    ap.add_argument("--transfer-profile", action="store_true",
+                    help="2048^2 mixed restriction / prolongation calls for a kernel trace; prints no metric")
     ap.add_argument("--serve-configs", type=int, default=8)
     ap.add_argument("--serve-sweeps", type=int, default=200)
     ap.add_argument("--serve-betas", type=float, nargs="+", default=list(SERVE_BETAS))
@@ -419,6 +472,8 @@ def main():
         return serve_main(a)
     if a.su3:
         return su3_main(a)
+    if a.transfer_profile:
+        return transfer_main(a)
     cpu = None if (a.no_cpu or a.kernel_profile) else start_cpu_leg(a.cpu_its)
 
     import numpy as np

@@ -182,11 +182,18 @@ kdmg_status kdmg_hierarchy_get_coarse_op(const kdmg_hierarchy* h, int level, dou
 kdmg_status kdmg_coarse_apply(const kdmg_hierarchy* h, int level, int dagger,
                               const void* in, void* out, int nrhs, kdmg_prec prec,
                               void* stream);
-/* Restriction R_k = P_k^dag from level k to k+1 and prolongation P_k, complex128. */
+/* Restriction R_k = P_k^dag from level k to k+1 (Sec. 3, the restriction of
+   the Galerkin coarse operator) and prolongation P_k, for nrhs vectors
+   [rhs][dof] (level 0: [rhs][site] in lexicographic site order; coarse
+   levels: [rhs][site][2 nv]).  prec KDMG_FP64: complex128 vectors and the
+   FP64 prolongator; KDMG_MIXED: complex64 vectors and the FP16-stored
+   prolongator of the mixed V-cycle, FP32 arithmetic.  Several rhs share one
+   read of P.  in/out: caller-owned device buffers.  Level 0 synchronises
+   `stream` (it uses a temporary); coarse levels are stream-ordered. */
 kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void* in, void* out,
-                          int nrhs, void* stream);
+                          int nrhs, kdmg_prec prec, void* stream);
 kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* out,
-                         int nrhs, void* stream);
+                         int nrhs, kdmg_prec prec, void* stream);
 
 /* Solves D x = b for nrhs right-hand sides sharing the hierarchy (Sec. 4):
    FGCR on the Schur system until ||b - D x|| <= tol ||b|| per rhs, then

@@ -218,6 +218,15 @@ __global__ __launch_bounds__(256) void k_dslash_blk(Cx<VT>* out, long so, const 
   }
 }
 
+// Workgroup index renumbered so that each of the 8 XCDs (which receive
+// workgroups round-robin, XCD = index % 8, each with its own L2) takes one
+// contiguous range of the grid: data shared by neighbouring workgroups (the
+// rows x1 +- 1 of the Dslash, the 128-byte lines split between neighbouring
+// aggregates of the transfers) is then read through the same L2.
+__device__ __forceinline__ int xcd_block(unsigned b, unsigned nb) {
+  return (int)((nb % 8u == 0) ? (b & 7u) * (nb >> 3) + (b >> 3) : b);
+}
+
 // D in natural site order: one thread per site and RB right-hand sides (the
 // site's four links are loaded once for all of them; every vector load of
 // the RB rhs is issued before any is used).  links_nat[mu][site] folded.
@@ -226,13 +235,7 @@ __global__ __launch_bounds__(256) void k_dslash_nat(Cx<VT>* __restrict__ out, co
                                                     const Cx<LT>* __restrict__ Ux,
                                                     const Cx<LT>* __restrict__ Ut, int Lx, int Lt,
                                                     long vol, R m, int nrhs) {
-  // Workgroups go to the 8 XCDs round-robin (XCD = blockIdx.x % 8), each with
-  // its own L2.  Renumber them so every XCD sweeps one contiguous range of
-  // sites: the rows x1 +- 1 a workgroup needs were then just read by the same
-  // XCD and are still in its L2.
-  const unsigned nb = gridDim.x;
-  const unsigned lb = (nb % 8u == 0) ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
-  const long x = (long)lb * blockDim.x + threadIdx.x;
+  const long x = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int r0 = blockIdx.y * RB;
   if (x >= vol) return;
   const int x1 = (int)(x / Lx), x0 = (int)(x - (long)x1 * Lx);
@@ -284,63 +287,133 @@ struct Agg2 {
   int nv;         // null vectors (coarse dofs = 2 nv)
 };
 
-// out[r][Z][c*nv+i] = sum_{x in Z, chir(x)=c} conj(P[x][i]) in[r][x]
-// in: full block-layout vector (even_only: parity-0 half only contributes).
-// Block of 2*nv*NPART threads; grid (nZ, nrhs).
-template <class R, class PT, class VI, class VO>
-__global__ __launch_bounds__(256) void k_restrict1(Cx<VO>* out, const Cx<VI>* in, long si,
-                                                   const Cx<PT>* P, Geo2 g, Agg2 a, int even_only,
-                                                   const int* act) {
-  const int Z = blockIdx.x, r = blockIdx.y;
-  if (!is_active(act, r)) return;
-  const int ndc = 2 * a.nv;
-  const int col = threadIdx.x % ndc, part = threadIdx.x / ndc, nparts = blockDim.x / ndc;
-  const int c = col / a.nv, i = col % a.nv;
-  const int Z0 = Z % a.Ncx, Z1 = Z / a.Ncx;
-  Cx<R> acc{0, 0};
-  const int nblk = a.a0 * a.a1;
-  for (int k = part; k < nblk; k += nparts) {
-    const int X0 = Z0 * a.a0 + k % a.a0, X1 = Z1 * a.a1 + k / a.a0;
-    const int p = (X0 + X1) & 1;
-    if (even_only && p) continue;
-    const int b = blk_index(g, X0, X1);
-    const long base = (long)p * g.half + 4L * b;
-    const int s0 = c ? 1 : 0, s1 = c ? 2 : 3;
-    cfma_conj(acc, ld<R>(P[(base + s0) * a.nv + i]), ld<R>(in[r * si + base + s0]));
-    cfma_conj(acc, ld<R>(P[(base + s1) * a.nv + i]), ld<R>(in[r * si + base + s1]));
-  }
-  __shared__ Cx<R> sh[256];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  if (part == 0) {
-    for (int q = 1; q < nparts; ++q) acc += sh[q * ndc + col];
-    out[((long)r * a.Ncx * a.Nct + Z) * ndc + col] = st<VO>(acc);
+// Shared by the multi-rhs transfers: the fine dof of every aggregate-local
+// index q = 4 k + s (block k of the aggregate in row-major order, site s),
+// -1 where it does not take part (parity >= npar), written to qd[0 .. nd)
+// by the first nd threads.
+__device__ __forceinline__ void aggregate_dofs(int* qd, const Geo2& g, const Agg2& a, int Z, int npar) {
+  const int nd = 4 * a.a0 * a.a1;
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    const int k = q >> 2, Z0 = Z % a.Ncx, Z1 = Z / a.Ncx;
+    const int X0 = Z0 * a.a0 + k % a.a0, X1 = Z1 * a.a1 + k / a.a0, p = (X0 + X1) & 1;
+    qd[q] = p < npar ? (int)((long)p * g.half + 4L * blk_index(g, X0, X1) + (q & 3)) : -1;
   }
 }
 
-// out[r][x] = [add[r][x] +] sum_i P[x][i] in[r][Z(x)][c(x)*nv+i]
-// grid: (blocks of parity, nrhs, nparity); out/add full or half (single parity)
+// Copies n = rows * cols elements src(row, col) -> dst[row * ds + col] with
+// every thread's loads issued before its stores (XU per batch); the row and
+// column come from the float-reciprocal division (exact for these sizes).
+template <class R, int XU, class F>
+__device__ __forceinline__ void stage_rows(Cx<R>* dst, int ds, int rows, int cols, F src) {
+  const int n = rows * cols;
+  const float inv = 1.0f / (float)cols;
+  for (int e0 = threadIdx.x; e0 < n; e0 += XU * blockDim.x) {
+    Cx<R> v[XU];
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int e = e0 + u * blockDim.x, row = (int)(((float)e + 0.5f) * inv), col = e - row * cols;
+      v[u] = e < n ? src(row, col) : Cx<R>{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int e = e0 + u * blockDim.x, row = (int)(((float)e + 0.5f) * inv), col = e - row * cols;
+      if (e < n) dst[row * ds + col] = v[u];
+    }
+  }
+}
+
+// Restriction, several rhs per workgroup:
+//   out[r][Z][c*nv+i] = sum_{x in Z, chir(x)=c} conj(P[x][i]) in[r][x]
+// in: full block-layout vector (even_only: the parity-0 half only
+// contributes).  The workgroup of aggregate Z stages the aggregate's P rows
+// (nd = 4 a0 a1 fine dofs, converted to R) and its tile of RB rhs in LDS,
+// so P is read once per rhs tile; thread o then adds TI consecutive coarse
+// dofs of one (rhs, chirality) over the aggregate's blocks in order.
+// grid (nZ, cdiv(nrhs, RB)); LDS (nd nv + RB nd) Cx<R> + nd int.
+template <class R, class PT, class VI, class VO, int TI>
+__global__ __launch_bounds__(256) void k_restrict1(Cx<VO>* out, const Cx<VI>* in, long si,
+                                                   const Cx<PT>* P, Geo2 g, Agg2 a, int even_only,
+                                                   const int* act, int nrhs, int RB) {
+  extern __shared__ __align__(16) unsigned char xf_raw[];
+  const int Z = xcd_block(blockIdx.x, gridDim.x), r0 = blockIdx.y * RB, nv = a.nv, ndc = 2 * nv;
+  const int nblk = a.a0 * a.a1, nd = 4 * nblk;
+  Cx<R>* Ps = reinterpret_cast<Cx<R>*>(xf_raw);  // [nd][nv]
+  Cx<R>* Vs = Ps + (long)nd * nv;                // [RB][nd]
+  int* qd = reinterpret_cast<int*>(Vs + (long)RB * nd);
+  aggregate_dofs(qd, g, a, Z, even_only ? 1 : 2);
+  __syncthreads();
+  stage_rows<R, 4>(Ps, nv, nd, nv, [&](int q, int i) {
+    const int d = qd[q];
+    return d >= 0 ? ld<R>(P[(long)d * nv + i]) : Cx<R>{0, 0};
+  });
+  stage_rows<R, 4>(Vs, nd, RB, nd, [&](int r, int q) {
+    const int d = qd[q], rr = r0 + r;
+    return d >= 0 && rr < nrhs && is_active(act, rr) ? ld<R>(in[rr * si + d]) : Cx<R>{0, 0};
+  });
+  __syncthreads();
+  const int ng = nv / TI, nout = RB * 2 * ng;
+  const long nc = (long)a.Ncx * a.Nct * ndc;
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    const int r = o / (2 * ng), rem = o - r * 2 * ng, c = rem / ng, i0 = (rem - c * ng) * TI, rr = r0 + r;
+    if (rr >= nrhs || !is_active(act, rr)) continue;
+    Cx<R> acc[TI];
+#pragma unroll
+    for (int u = 0; u < TI; ++u) acc[u] = Cx<R>{0, 0};
+    const int s0 = c ? 1 : 0, s1 = c ? 2 : 3;
+    const Cx<R>* v = Vs + (long)r * nd;
+    for (int k = 0; k < nblk; ++k) {
+      const int q0 = 4 * k + s0, q1 = 4 * k + s1;
+      const Cx<R> v0 = v[q0], v1 = v[q1];
+#pragma unroll
+      for (int u = 0; u < TI; ++u) {
+        cfma_conj(acc[u], Ps[q0 * nv + i0 + u], v0);
+        cfma_conj(acc[u], Ps[q1 * nv + i0 + u], v1);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TI; ++u) out[rr * nc + (long)Z * ndc + c * nv + i0 + u] = st<VO>(acc[u]);
+  }
+}
+
+// Prolongation, several rhs per workgroup:
+//   out[r][x] = [add[r][x] +] sum_i P[x][i] in[r][Z(x)][c(x)*nv+i]
+// The workgroup of aggregate Z stages the aggregate's P rows (row stride
+// nv + 1 against LDS bank conflicts) and the coarse values of its rhs tile in
+// LDS, so P is read once per tile; output o is (rhs o / nd, aggregate-local
+// dof o % nd).  npar = 1: only the parity-0 blocks (out/add are Schur-half
+// vectors), npar = 2: all.  grid (nZ, cdiv(nrhs, RB)); LDS
+// (nd (nv + 1) + RB 2 nv) Cx<R> + nd int.
 template <class R, class PT, class VI, class VO>
 __global__ __launch_bounds__(256) void k_prolong1(Cx<VO>* out, long so, const Cx<VO>* add, long sa,
-                                                  const Cx<VI>* in, const Cx<PT>* P, Geo2 g, Agg2 a,
-                                                  const int* act) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y, p = blockIdx.z;
-  if (b >= g.Nb2 || !is_active(act, r)) return;
-  int X0, X1;
-  blk_coords(g, p, b, X0, X1);
-  const int Z = (X0 / a.a0) + a.Ncx * (X1 / a.a1);
-  const int ndc = 2 * a.nv;
-  const Cx<VI>* e = in + ((long)r * a.Ncx * a.Nct + Z) * ndc;
-  const long base = (long)p * g.half + 4L * b;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int c = chir2(s);
+                                                  const Cx<VI>* in, const Cx<PT>* P, Geo2 g, Agg2 a, int npar,
+                                                  const int* act, int nrhs, int RB) {
+  extern __shared__ __align__(16) unsigned char xf_raw[];
+  const int Z = xcd_block(blockIdx.x, gridDim.x), r0 = blockIdx.y * RB, nv = a.nv, ndc = 2 * nv, RP = nv + 1;
+  const int nd = 4 * a.a0 * a.a1;
+  Cx<R>* Ps = reinterpret_cast<Cx<R>*>(xf_raw);  // [nd][nv + 1]
+  Cx<R>* Es = Ps + (long)nd * RP;                // [RB][2 nv]
+  int* qd = reinterpret_cast<int*>(Es + (long)RB * ndc);
+  aggregate_dofs(qd, g, a, Z, npar);
+  __syncthreads();
+  stage_rows<R, 4>(Ps, RP, nd, nv, [&](int q, int i) {
+    const int d = qd[q];
+    return d >= 0 ? ld<R>(P[(long)d * nv + i]) : Cx<R>{0, 0};
+  });
+  const long nc = (long)a.Ncx * a.Nct * ndc;
+  stage_rows<R, 4>(Es, ndc, RB, ndc, [&](int r, int j) {
+    const int rr = r0 + r;
+    return rr < nrhs ? ld<R>(in[rr * nc + (long)Z * ndc + j]) : Cx<R>{0, 0};
+  });
+  __syncthreads();
+  for (int o = threadIdx.x; o < RB * nd; o += blockDim.x) {
+    const int r = o / nd, q = o - r * nd, rr = r0 + r, x = qd[q];
+    if (x < 0 || rr >= nrhs || !is_active(act, rr)) continue;
+    const Cx<R>* pq = Ps + q * RP;
+    const Cx<R>* er = Es + r * ndc + chir2(q & 3) * nv;
     Cx<R> acc{0, 0};
-    const Cx<PT>* Px = P + (base + s) * a.nv;
-    for (int i = 0; i < a.nv; ++i) cfma(acc, ld<R>(Px[i]), ld<R>(e[c * a.nv + i]));
-    if (add) acc += ld<R>(add[r * sa + base + s]);
-    out[r * so + base + s] = st<VO>(acc);
+    for (int i = 0; i < nv; ++i) cfma(acc, pq[i], er[i]);
+    if (add) acc += ld<R>(add[rr * sa + x]);
+    out[rr * so + x] = st<VO>(acc);
   }
 }
 

@@ -651,47 +651,61 @@ extern "C" kdmg_status kdmg_coarse_apply(const kdmg_hierarchy* h, int level, int
   KDMG_API_END
 }
 
-extern "C" kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void* in, void* out, int nrhs,
-                                     void* stream) {
-  KDMG_API_BEGIN
-  KDMG_CHECK(h && in && out && k >= 0 && k < h->nlevels - 1 && nrhs >= 1, KDMG_EINVAL,
-             "kdmg_restrict: bad argument");
-  hipStream_t st = (hipStream_t)stream;
+// kdmg_restrict / kdmg_prolong in precision R with prolongator storage PT
+// (FP64 / FP64, or FP32 vectors with the FP16-stored P of the mixed V-cycle).
+template <class R, class PT>
+static void restrict_as(const kdmg_hierarchy* h, int k, const void* in, void* out, int nrhs, hipStream_t st) {
   const Transfer& T = h->T[k];
   if (k == 0) {
     const kdmg_lattice& lat = *h->lat;
     const long f = 2 * lat.half, V = lat.ndof;
-    DevBuf a(sizeof(c64) * f * nrhs);
-    launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, V, lat.perm_full.as<int>(), V, 1,
-                                   nrhs, st);
-    transfer_restrict<double, double, double, double>(T, lat, nullptr, (c64*)out, a.as<c64>(), f, 0,
-                                                      nullptr, nrhs, st);
+    DevBuf a(sizeof(Cx<R>) * f * nrhs);
+    launch_permute<R, R>(a.as<Cx<R>>(), f, (const Cx<R>*)in, V, lat.perm_full.as<int>(), V, 1, nrhs, st);
+    transfer_restrict<R, PT, R, R>(T, lat, nullptr, (Cx<R>*)out, a.as<Cx<R>>(), f, 0, nullptr, nrhs, st);
     KDMG_HIP(hipStreamSynchronize(st));
   } else {
-    transfer_restrict<double, double, double, double>(T, *h->lat, &h->L[k], (c64*)out, (const c64*)in,
-                                                      T.nfine, 0, nullptr, nrhs, st);
+    transfer_restrict<R, PT, R, R>(T, *h->lat, &h->L[k], (Cx<R>*)out, (const Cx<R>*)in, T.nfine, 0, nullptr,
+                                   nrhs, st);
   }
+}
+
+template <class R, class PT>
+static void prolong_as(const kdmg_hierarchy* h, int k, const void* in, void* out, int nrhs, hipStream_t st) {
+  const Transfer& T = h->T[k];
+  if (k == 0) {
+    const kdmg_lattice& lat = *h->lat;
+    const long f = 2 * lat.half, V = lat.ndof;
+    DevBuf a(sizeof(Cx<R>) * f * nrhs);
+    transfer_prolong<R, PT, R, R>(T, lat, a.as<Cx<R>>(), f, nullptr, 0, (const Cx<R>*)in, 2, nullptr, nrhs, st);
+    launch_permute<R, R>((Cx<R>*)out, V, a.as<Cx<R>>(), f, lat.perm_full.as<int>(), V, 0, nrhs, st);
+    KDMG_HIP(hipStreamSynchronize(st));
+  } else {
+    transfer_prolong<R, PT, R, R>(T, *h->lat, (Cx<R>*)out, 0, nullptr, 0, (const Cx<R>*)in, 1, nullptr, nrhs, st);
+  }
+}
+
+extern "C" kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void* in, void* out, int nrhs,
+                                     kdmg_prec prec, void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && in && out && k >= 0 && k < h->nlevels - 1 && nrhs >= 1 &&
+                 (prec == KDMG_FP64 || prec == KDMG_MIXED),
+             KDMG_EINVAL, "kdmg_restrict: bad argument");
+  if (prec == KDMG_FP64)
+    restrict_as<double, double>(h, k, in, out, nrhs, (hipStream_t)stream);
+  else
+    restrict_as<float, _Float16>(h, k, in, out, nrhs, (hipStream_t)stream);
   KDMG_API_END
 }
 
 extern "C" kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* out, int nrhs,
-                                    void* stream) {
+                                    kdmg_prec prec, void* stream) {
   KDMG_API_BEGIN
-  KDMG_CHECK(h && in && out && k >= 0 && k < h->nlevels - 1 && nrhs >= 1, KDMG_EINVAL,
-             "kdmg_prolong: bad argument");
-  hipStream_t st = (hipStream_t)stream;
-  const Transfer& T = h->T[k];
-  if (k == 0) {
-    const kdmg_lattice& lat = *h->lat;
-    const long f = 2 * lat.half, V = lat.ndof;
-    DevBuf a(sizeof(c64) * f * nrhs);
-    transfer_prolong<double, double, double, double>(T, lat, a.as<c64>(), f, nullptr, 0, (const c64*)in,
-                                                     2, nullptr, nrhs, st);
-    launch_permute<double, double>((c64*)out, V, a.as<c64>(), f, lat.perm_full.as<int>(), V, 0, nrhs, st);
-    KDMG_HIP(hipStreamSynchronize(st));
-  } else {
-    transfer_prolong<double, double, double, double>(T, *h->lat, (c64*)out, 0, nullptr, 0,
-                                                     (const c64*)in, 1, nullptr, nrhs, st);
-  }
+  KDMG_CHECK(h && in && out && k >= 0 && k < h->nlevels - 1 && nrhs >= 1 &&
+                 (prec == KDMG_FP64 || prec == KDMG_MIXED),
+             KDMG_EINVAL, "kdmg_prolong: bad argument");
+  if (prec == KDMG_FP64)
+    prolong_as<double, double>(h, k, in, out, nrhs, (hipStream_t)stream);
+  else
+    prolong_as<float, _Float16>(h, k, in, out, nrhs, (hipStream_t)stream);
   KDMG_API_END
 }

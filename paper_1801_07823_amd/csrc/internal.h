@@ -473,12 +473,23 @@ void transfer_restrict(const Transfer& T, const kdmg_lattice& lat, const CoarseL
     hipLaunchKernelGGL((k4_restrict<R, PT, VI, VO>), grid, dim3(256), 0, st, out, in, si, P, T.rows4.as<int>(),
                        T.nrows4, T.nv, even_only, lat.half, act, nrhs);
   } else if (T.k == 0) {
-    const int ndc = 2 * T.nv;
-    int parts = 256 / ndc;
-    if (parts < 1) parts = 1;
-    dim3 grid(T.a2.Ncx * T.a2.Nct, nrhs);
-    hipLaunchKernelGGL((k_restrict1<R, PT, VI, VO>), grid, dim3(ndc * parts), 0, st, out, in, si, P,
-                       lat.g, T.a2, even_only, act);
+    // rhs tile: up to 32, with the staged P rows and rhs values within the LDS
+    const int nd = 4 * T.a2.a0 * T.a2.a1;
+    int RB = nrhs < 32 ? nrhs : 32;
+    auto bytes = [&] { return ((size_t)nd * T.nv + (size_t)RB * nd) * sizeof(Cx<R>) + nd * sizeof(int); };
+    while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
+    KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "restriction: aggregate too large for LDS staging");
+    dim3 grid(T.a2.Ncx * T.a2.Nct, cdiv(nrhs, RB));
+    // four coarse dofs per thread only when that still fills the workgroup
+    if (T.nv % 4 == 0 && RB * 2 * T.nv >= 4 * 256) {
+      auto fn = k_restrict1<R, PT, VI, VO, 4>;
+      ensure_smem((const void*)fn, bytes());
+      hipLaunchKernelGGL(fn, grid, dim3(256), bytes(), st, out, in, si, P, lat.g, T.a2, even_only, act, nrhs, RB);
+    } else {
+      auto fn = k_restrict1<R, PT, VI, VO, 1>;
+      ensure_smem((const void*)fn, bytes());
+      hipLaunchKernelGGL(fn, grid, dim3(256), bytes(), st, out, in, si, P, lat.g, T.a2, even_only, act, nrhs, RB);
+    }
   } else {
     const int ndn = 2 * T.nv;
     int parts = 256 / ndn;
@@ -502,9 +513,15 @@ void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, l
     hipLaunchKernelGGL((k4_prolong<R, PT, VI, VO>), grid, dim3(256), 0, st, out, so, add, sa, in, P,
                        T.dgrp4.as<int>(), T.nv, n_out, (long)T.nZ * 2 * T.nv, act);
   } else if (T.k == 0) {
-    dim3 grid(cdiv(lat.g.Nb2, 256), nrhs, npar);
-    hipLaunchKernelGGL((k_prolong1<R, PT, VI, VO>), grid, dim3(256), 0, st, out, so, add, sa, in, P,
-                       lat.g, T.a2, act);
+    const int nd = 4 * T.a2.a0 * T.a2.a1;
+    int RB = nrhs < 32 ? nrhs : 32;
+    auto bytes = [&] { return ((size_t)nd * (T.nv + 1) + (size_t)RB * 2 * T.nv) * sizeof(Cx<R>) + nd * sizeof(int); };
+    while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
+    KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "prolongation: aggregate too large for LDS staging");
+    auto fn = k_prolong1<R, PT, VI, VO>;
+    ensure_smem((const void*)fn, bytes());
+    hipLaunchKernelGGL(fn, dim3(T.a2.Ncx * T.a2.Nct, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, so, add, sa, in,
+                       P, lat.g, T.a2, npar, act, nrhs, RB);
   } else {
     dim3 grid(cdiv((long)T.nsf * T.ndf, 256), nrhs);
     hipLaunchKernelGGL((k_prolong_c<R, PT, VI, VO>), grid, dim3(256), 0, st, out, add, in, P,

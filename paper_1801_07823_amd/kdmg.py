@@ -73,8 +73,8 @@ _SIGS = {
     "kdmg_hierarchy_get_prolongator": (_I, [_P, _I, _P]),
     "kdmg_hierarchy_get_coarse_op": (_I, [_P, _I, _P]),
     "kdmg_coarse_apply": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
-    "kdmg_restrict": (_I, [_P, _I, _P, _P, _I, _P]),
-    "kdmg_prolong": (_I, [_P, _I, _P, _P, _I, _P]),
+    "kdmg_restrict": (_I, [_P, _I, _P, _P, _I, _I, _P]),
+    "kdmg_prolong": (_I, [_P, _I, _P, _P, _I, _I, _P]),
     "kdmg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(kdmg_solve_info), _P]),
     "kdmg_hierarchy_footprint": (_I, [_P, _I, ctypes.POINTER(_S)]),
     "kdmg_hierarchy_autotune": (_I, [_P, _I, _I, _P]),
@@ -290,12 +290,12 @@ def kdmg_coarse_apply_candidates(h, level, inp, out, nrhs, dagger=False, prec=KD
     return nc.value
 
 
-def kdmg_restrict(h, k, inp, out, nrhs, stream=None):
-    _check(_lib.kdmg_restrict(h.handle, k, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+def kdmg_restrict(h, k, inp, out, nrhs, prec=KDMG_FP64, stream=None):
+    _check(_lib.kdmg_restrict(h.handle, k, _ptr(inp), _ptr(out), nrhs, prec, _stream(stream)))
 
 
-def kdmg_prolong(h, k, inp, out, nrhs, stream=None):
-    _check(_lib.kdmg_prolong(h.handle, k, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+def kdmg_prolong(h, k, inp, out, nrhs, prec=KDMG_FP64, stream=None):
+    _check(_lib.kdmg_prolong(h.handle, k, _ptr(inp), _ptr(out), nrhs, prec, _stream(stream)))
 
 
 def kdmg_hierarchy_autotune(h, nrhs, prec=KDMG_FP64, stream=None):

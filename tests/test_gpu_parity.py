@@ -196,21 +196,38 @@ def test_transfer_and_coarse_apply(K, dims, beta, m, levels):
     oh, _ = oracle_setup(dims, U, m, levels, 23)
     lat = K.Lattice(dims, U)
     gh = K.Hierarchy(lat, m, gpu_params(K, levels), oh.nullvecs, relaxed=True)
+    # rhs counts: one, a ragged tail of the 8-rhs prolongation tile and of the
+    # 32-rhs restriction tile.  FP64 to 1e-12; the mixed form (FP16-stored P,
+    # FP32 vectors and arithmetic) to 2e-3 relative 2-norm per rhs (P's
+    # entries carry a relative rounding of at most 2^-11)
     nrhs = 3
     for k in range(len(levels)):
         nf = gh.ndof(k)
         nc = gh.ndof(k + 1)
-        v = gaussian_vectors(nrhs, nf, 30 + k)
-        out = torch.empty((nrhs, nc), dtype=torch.complex128, device="cuda")
-        K.kdmg_restrict(gh, k, dev(v), out, nrhs)
-        torch.cuda.synchronize()
         P = oh.P[k]
-        assert relerr(out.cpu().numpy(), (P.conj().T @ v.T).T) < 1e-12
-        e = gaussian_vectors(nrhs, nc, 40 + k)
-        outp = torch.empty((nrhs, nf), dtype=torch.complex128, device="cuda")
-        K.kdmg_prolong(gh, k, dev(e), outp, nrhs)
-        torch.cuda.synchronize()
-        assert relerr(outp.cpu().numpy(), (P @ e.T).T) < 1e-12
+        for nr in (1, nrhs, 37):
+            v = gaussian_vectors(nr, nf, 30 + k + nr)
+            ref = (P.conj().T @ v.T).T
+            out = torch.empty((nr, nc), dtype=torch.complex128, device="cuda")
+            K.kdmg_restrict(gh, k, dev(v), out, nr)
+            torch.cuda.synchronize()
+            assert relerr(out.cpu().numpy(), ref) < 1e-12
+            out32 = torch.empty((nr, nc), dtype=torch.complex64, device="cuda")
+            K.kdmg_restrict(gh, k, dev(v, torch.complex64), out32, nr, prec=K.KDMG_MIXED)
+            torch.cuda.synchronize()
+            err = np.linalg.norm(out32.cpu().numpy() - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            assert np.all(err < 2e-3)
+            e = gaussian_vectors(nr, nc, 40 + k + nr)
+            ref = (P @ e.T).T
+            outp = torch.empty((nr, nf), dtype=torch.complex128, device="cuda")
+            K.kdmg_prolong(gh, k, dev(e), outp, nr)
+            torch.cuda.synchronize()
+            assert relerr(outp.cpu().numpy(), ref) < 1e-12
+            outp32 = torch.empty((nr, nf), dtype=torch.complex64, device="cuda")
+            K.kdmg_prolong(gh, k, dev(e, torch.complex64), outp32, nr, prec=K.KDMG_MIXED)
+            torch.cuda.synchronize()
+            err = np.linalg.norm(outp32.cpu().numpy() - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            assert np.all(err < 2e-3)
     for level in (1, 2):
         n = gh.ndof(level)
         v = gaussian_vectors(nrhs, n, 50 + level)
