@@ -36,9 +36,9 @@ WORKLOAD = {"workload": "2D U(1) staggered KD-MG solve", "lattice": [256, 256], 
 # and WRITE_SIZE 65536 KiB for a 64 MiB elementwise copy, so FETCH_SIZE is
 # scaled by 2.0 and WRITE_SIZE by 1.0.  Valid only for the kernel source it
 # was measured on (sha256 of coarse_fast.cuh); otherwise reported as null.
-TRAFFIC = {"coarse_fast_sha256": "1242e6f6b6ce2faa674bad0d65b26729eaeefcd747f80f45ff6688223f9b8593",
+TRAFFIC = {"coarse_fast_sha256": "ef7256408755d5ae044f1bb7fa62d08e7c1c28a7ce0478d42ec5b3e42db524ee",
            "n_vec_2": 12,
-           "bytes_per_launch": ((13671.7 + 12258.3) * 2.0 + (6400.0 + 3328.6) * 1.0) / 2 * 1024}
+           "bytes_per_launch": ((13688.1 + 12286.7) * 2.0 + (6400.0 + 3328.6) * 1.0) / 2 * 1024}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
