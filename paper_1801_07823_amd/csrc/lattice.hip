@@ -248,29 +248,30 @@ extern "C" kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const 
     }
     return KDMG_OK;
   }
-  // several rhs per thread (links read once per site) when there are enough
-  // sites to fill the device
-  const int RB = (nrhs >= 4 && V >= 16384) ? 4 : 1;
+  // several rhs per thread (links read once per site, more loads in flight)
+  // when there are enough sites to fill the device
+  const int RB = V < 16384 ? 1 : nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : 1;
   dim3 grid(cdiv(V, 256), cdiv(nrhs, RB));
-  if (prec == KDMG_FP64) {
-    const c64* U = lat->nat64.as<c64>();
-    if (RB == 4)
-      hipLaunchKernelGGL((k_dslash_nat<double, double, double, 4>), grid, dim3(256), 0, st, (c64*)out,
-                         (const c64*)in, U, U + V, lat->dims[0], lat->dims[1], V, mass, nrhs);
+  auto launch = [&](auto r_tag, auto l_tag, const auto* U) {
+    using R = decltype(r_tag);
+    using LT = decltype(l_tag);
+    const Cx<LT>* Ul = (const Cx<LT>*)U;
+    if (RB == 8)
+      hipLaunchKernelGGL((k_dslash_nat<R, LT, R, 8>), grid, dim3(256), 0, st, (Cx<R>*)out, (const Cx<R>*)in, Ul,
+                         Ul + V, lat->dims[0], lat->dims[1], V, (R)mass, nrhs);
+    else if (RB == 4)
+      hipLaunchKernelGGL((k_dslash_nat<R, LT, R, 4>), grid, dim3(256), 0, st, (Cx<R>*)out, (const Cx<R>*)in, Ul,
+                         Ul + V, lat->dims[0], lat->dims[1], V, (R)mass, nrhs);
     else
-      hipLaunchKernelGGL((k_dslash_nat<double, double, double, 1>), grid, dim3(256), 0, st, (c64*)out,
-                         (const c64*)in, U, U + V, lat->dims[0], lat->dims[1], V, mass, nrhs);
-  } else if (prec == KDMG_MIXED) {
-    const c16* U = lat->nat16.as<c16>();
-    if (RB == 4)
-      hipLaunchKernelGGL((k_dslash_nat<float, _Float16, float, 4>), grid, dim3(256), 0, st, (c32*)out,
-                         (const c32*)in, U, U + V, lat->dims[0], lat->dims[1], V, (float)mass, nrhs);
-    else
-      hipLaunchKernelGGL((k_dslash_nat<float, _Float16, float, 1>), grid, dim3(256), 0, st, (c32*)out,
-                         (const c32*)in, U, U + V, lat->dims[0], lat->dims[1], V, (float)mass, nrhs);
-  } else {
+      hipLaunchKernelGGL((k_dslash_nat<R, LT, R, 1>), grid, dim3(256), 0, st, (Cx<R>*)out, (const Cx<R>*)in, Ul,
+                         Ul + V, lat->dims[0], lat->dims[1], V, (R)mass, nrhs);
+  };
+  if (prec == KDMG_FP64)
+    launch(double{}, double{}, lat->nat64.as<c64>());
+  else if (prec == KDMG_MIXED)
+    launch(float{}, _Float16{}, lat->nat16.as<c16>());
+  else
     throw Error(KDMG_EINVAL, "kdmg_apply_D: bad precision");
-  }
   KDMG_LAUNCH_CHECK();
   KDMG_API_END
 }

@@ -75,6 +75,28 @@ def test_apply_D_mixed(K, dims, beta, m):
     assert np.all(err / np.linalg.norm(v, axis=1) < 3e-3)
 
 
+@pytest.mark.parametrize("nrhs", [5, 11])
+def test_apply_D_rhs_tiles(K, nrhs):
+    """128^2 (large enough for several rhs per thread): 5 rhs take the 4-rhs
+    tile with a ragged tail, 11 the 8-rhs tile with a ragged tail; FP64 to
+    1e-12 and mixed to 3e-3 relative 2-norm per rhs."""
+    dims, beta, m = (128, 128), 6.0, 0.01
+    U = field(dims, beta)
+    lat = K.Lattice(dims, U)
+    V = lat.volume
+    v = gaussian_vectors(nrhs, V, 13)
+    ref = (dirac_matrix(OLattice(dims), U, m) @ v.T).T
+    out = torch.empty((nrhs, V), dtype=torch.complex128, device="cuda")
+    K.kdmg_apply_D(lat, m, dev(v), out, nrhs)
+    torch.cuda.synchronize()
+    assert relerr(out.cpu().numpy(), ref) < 1e-12
+    out32 = torch.empty((nrhs, V), dtype=torch.complex64, device="cuda")
+    K.kdmg_apply_D(lat, m, dev(v, torch.complex64), out32, nrhs, prec=K.KDMG_MIXED)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(out32.cpu().numpy().astype(np.complex128) - ref, axis=1)
+    assert np.all(err / np.linalg.norm(v, axis=1) < 3e-3)
+
+
 @pytest.mark.parametrize("dims,beta,m", CASES)
 def test_fine_operators_fp64(K, dims, beta, m):
     U = field(dims, beta)
