@@ -131,7 +131,7 @@ int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r
       op(w, z, (const Cx<T>*)nullptr, k.act);
       if (kk > 0)
         for (int pass = 0; pass < 2; ++pass) {
-          launch_map_reduce<2>(OpMultiDot<T>{Wb, vs, w, n, k}, n, nrhs, kk, c.rs, c.st);
+          launch_multidot<T>(Wb, vs, w, n, kk, nrhs, k, c.rs, c.st);
           launch_map(OpMultiAxpy<T>{w, z, Wb, Zb, vs, kk, n, k}, n, nrhs, c.st);
         }
       launch_map_reduce<3>(OpGCRred<T>{w, r, n, k}, n, nrhs, 1, c.rs, c.st);

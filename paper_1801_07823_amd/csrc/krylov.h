@@ -209,22 +209,76 @@ struct OpMRupd {
   }
 };
 
-// GCR: h_j = <w_j, w>  (z-batch over j)
+// The classical Gram-Schmidt projections h[r][j] = <W_j[r], w[r]>, j < nz, in
+// two kernels.  k_multidot reads w once per batch of MDJ directions (the
+// generic map-reduce re-read it for every direction and paid an atomic and a
+// device-scope fence per workgroup) and writes per-workgroup partial sums;
+// k_multidot_sum adds each (rhs, j)'s partials in workgroup order with a fixed
+// tree, so the result is deterministic without atomics.
+constexpr int MDJ = 8;
+
 template <class T>
-struct OpMultiDot {
-  const Cx<T>* Wb; long vstride; const Cx<T>* w; long n; KrylovState k;
-  __device__ bool active(int rr) const { return k.act[rr] != 0; }
-  __device__ void elem(int rr, int j, long i, Acc<2>& a) const {
-    Cx<double> u = ld<double>(Wb[j * vstride + rr * n + i]), v = ld<double>(w[rr * n + i]);
-    a.v[0] += u.re * v.re + u.im * v.im;
-    a.v[1] += u.re * v.im - u.im * v.re;
+__global__ __launch_bounds__(256) void k_multidot(double* part, const Cx<T>* Wb, long vstride, const Cx<T>* w,
+                                                  long n, int nz, int nrhs, const int* act) {
+  const int r = blockIdx.y, j0 = blockIdx.z * MDJ;
+  if (!act[r]) return;
+  double acc[2 * MDJ];
+#pragma unroll
+  for (int q = 0; q < 2 * MDJ; ++q) acc[q] = 0.0;
+  const Cx<T>* wr = w + (long)r * n;
+  const Cx<T>* W0 = Wb + (long)j0 * vstride + (long)r * n;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const Cx<double> v = ld<double>(wr[i]);
+#pragma unroll
+    for (int q = 0; q < MDJ; ++q)
+      if (j0 + q < nz) {
+        const Cx<double> u = ld<double>(W0[(long)q * vstride + i]);
+        acc[2 * q] += u.re * v.re + u.im * v.im;
+        acc[2 * q + 1] += u.re * v.im - u.im * v.re;
+      }
   }
-  __device__ void finish(int rr, int j, const double* s) const {
-    double* S = k.sc + rr * S_COUNT;
-    S[S_H + 2 * j] = s[0];
-    S[S_H + 2 * j + 1] = s[1];
+  __shared__ double sh[2 * MDJ][RED_THREADS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 2 * MDJ; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) sh[q][wid] = v;
   }
-};
+  __syncthreads();
+  if (threadIdx.x < 2 * MDJ && j0 + (int)threadIdx.x / 2 < nz) {
+    const int q = threadIdx.x, j = j0 + q / 2;
+    double v = 0.0;
+    for (int u = 0; u < RED_THREADS / 64; ++u) v += sh[q][u];
+    part[(((long)j * nrhs + r) * 2 + (q & 1)) * RED_MAX_BLOCKS + blockIdx.x] = v;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_multidot_sum(const double* part, int nb, int nrhs, KrylovState k) {
+  const int j = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  if (!k.act[r]) return;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double* p = part + (((long)j * nrhs + r) * 2 + c) * RED_MAX_BLOCKS;
+    double v = 0.0;
+    for (int b = lane; b < nb; b += 64) v += p[b];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) k.sc[(long)r * S_COUNT + S_H + 2 * j + c] = v;
+  }
+}
+
+template <class T>
+void launch_multidot(const Cx<T>* Wb, long vstride, const Cx<T>* w, long n, int nz, int nrhs,
+                     const KrylovState& k, const RedScratch& rs, hipStream_t st) {
+  KDMG_CHECK(nz * nrhs <= rs.slots && 2 * nz <= S_COUNT - S_H, KDMG_EINVAL, "multi-dot: scratch too small");
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_multidot<T>), dim3(nb, nrhs, cdiv(nz, MDJ)), dim3(RED_THREADS), 0, st, rs.partials, Wb,
+                     vstride, w, n, nz, nrhs, (const int*)k.act);
+  hipLaunchKernelGGL((k_multidot_sum<T>), dim3(nz, nrhs), dim3(64), 0, st, (const double*)rs.partials, nb, nrhs,
+                     k);
+  KDMG_LAUNCH_CHECK();
+}
 
 // w -= sum_j h_j w_j ; z -= sum_j h_j z_j
 template <class T>
