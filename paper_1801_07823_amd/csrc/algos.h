@@ -55,20 +55,17 @@ struct KrylovAlloc {
 };
 
 struct CtxAlloc {
-  DevBuf partials, counters;
+  DevBuf partials;
   int* h_poll = nullptr;
   Ctx c;
   void init(hipStream_t st, int slots, int nrhs_max) {
     partials.alloc(sizeof(double) * (size_t)slots * 3 * RED_MAX_BLOCKS);
-    counters.alloc(sizeof(unsigned) * slots);
-    KDMG_HIP(hipMemset(counters.p, 0, counters.bytes));
     {
       std::lock_guard<std::mutex> g(hip_mem_mutex());
       KDMG_HIP(hipHostMalloc((void**)&h_poll, sizeof(int) * (nrhs_max + 8), hipHostMallocDefault));
     }
     c.st = st;
     c.rs.partials = partials.as<double>();
-    c.rs.counters = counters.as<unsigned>();
     c.rs.slots = slots;
     c.h_poll = h_poll;
   }

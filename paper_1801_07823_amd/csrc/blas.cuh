@@ -3,9 +3,8 @@
 // Every vector holds `nrhs` right-hand sides back to back ([rhs][n] complex).
 // Scalars (dot products, Krylov coefficients, convergence flags) live in device
 // memory, one slot per rhs, so a Krylov iteration never waits for the host.
-// Reductions are deterministic: fixed grid, fixed tree order, and the last
-// block of each rhs sums the per-block partials in index order (no float
-// atomics); the integer arrival counter it uses is reset by that same block.
+// Reductions are deterministic: fixed grid, fixed tree order, and a second
+// kernel adds the per-block partials in block order (no atomics).
 #pragma once
 #include "common.h"
 
@@ -17,7 +16,6 @@ constexpr int RED_MAX_BLOCKS = 240;
 // Per-stream scratch for reductions.
 struct RedScratch {
   double* partials = nullptr;  // [slots][K][RED_MAX_BLOCKS]
-  unsigned* counters = nullptr; // [slots], zero between reductions
   int slots = 0;
 };
 
@@ -64,11 +62,14 @@ __device__ __forceinline__ void block_reduce(Acc<K>& a) {
 //   __device__ bool active(int r) const;
 //   __device__ void elem(int r, int z, long i, Acc<K>& a) const;   (may also write)
 //   __device__ void finish(int r, int z, const double* sums) const; (one thread)
-// Grid: x = blocks over i, y = rhs, z = batch index (e.g. which basis vector).
+// Two kernels: k_map_reduce (grid x = blocks over i, y = rhs, z = batch index,
+// e.g. which basis vector) writes one partial sum per workgroup;
+// k_reduce_finish adds each (rhs, z) slot's partials in workgroup order with a
+// fixed lane tree and calls finish.  No atomics and no device-scope fences
+// (on this part a fence writes back L2, and one per workgroup made the
+// reductions several times slower than their memory traffic).
 template <int K, class Op>
-__global__ __launch_bounds__(RED_THREADS) void k_map_reduce(Op op, long n, int nrhs,
-                                                            double* partials,
-                                                            unsigned* counters) {
+__global__ __launch_bounds__(RED_THREADS) void k_map_reduce(Op op, long n, int nrhs, double* partials) {
   const int r = blockIdx.y, z = blockIdx.z;
   if (!op.active(r)) return;
   Acc<K> a;
@@ -78,40 +79,38 @@ __global__ __launch_bounds__(RED_THREADS) void k_map_reduce(Op op, long n, int n
        i += (long)gridDim.x * blockDim.x)
     op.elem(r, z, i, a);
   block_reduce<K>(a);
-  const int slot = z * nrhs + r;
-  __shared__ bool last;
   if (threadIdx.x == 0) {
-    double* pp = partials + (size_t)slot * K * RED_MAX_BLOCKS;
+    double* pp = partials + (size_t)(z * nrhs + r) * K * RED_MAX_BLOCKS;
 #pragma unroll
     for (int k = 0; k < K; ++k) pp[k * RED_MAX_BLOCKS + blockIdx.x] = a.v[k];
-    __threadfence();
-    unsigned prev = atomicAdd(&counters[slot], 1u);
-    last = (prev == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    const volatile double* pp = partials + (size_t)slot * K * RED_MAX_BLOCKS;
-    double s[K];
+}
+
+template <int K, class Op>
+__global__ __launch_bounds__(64) void k_reduce_finish(Op op, int nb, int nrhs, const double* partials) {
+  const int r = blockIdx.x, z = blockIdx.y, lane = threadIdx.x;
+  if (!op.active(r)) return;
+  const double* pp = partials + (size_t)(z * nrhs + r) * K * RED_MAX_BLOCKS;
+  double s[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double t = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) t += pp[k * RED_MAX_BLOCKS + b];
-      s[k] = t;
-    }
-    op.finish(r, z, s);
-    counters[slot] = 0u;
+  for (int k = 0; k < K; ++k) {
+    double v = 0.0;
+    for (int b = lane; b < nb; b += 64) v += pp[k * RED_MAX_BLOCKS + b];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    s[k] = v;
   }
+  if (lane == 0) op.finish(r, z, s);
 }
 
 template <int K, class Op>
 void launch_map_reduce(const Op& op, long n, int nrhs, int nz, const RedScratch& rs,
                        hipStream_t st) {
   KDMG_CHECK(nz * nrhs <= rs.slots, KDMG_EINVAL, "reduction scratch too small");
-  dim3 grid(red_blocks(n), nrhs, nz);
-  hipLaunchKernelGGL((k_map_reduce<K, Op>), grid, dim3(RED_THREADS), 0, st, op, n, nrhs,
-                     rs.partials, rs.counters);
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_map_reduce<K, Op>), dim3(nb, nrhs, nz), dim3(RED_THREADS), 0, st, op, n, nrhs,
+                     rs.partials);
+  hipLaunchKernelGGL((k_reduce_finish<K, Op>), dim3(nrhs, nz), dim3(64), 0, st, op, nb, nrhs,
+                     (const double*)rs.partials);
   KDMG_LAUNCH_CHECK();
 }
 
