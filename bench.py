@@ -193,6 +193,11 @@ SERVE_NV = (16, 16)
 # the setup mass and reused at every request mass; with the looser setting
 # the rough beta = 3 fields at m < 0.005 stall the outer solve.
 SERVE_SETUP_TOL, SERVE_SETUP_MAXIT = 1e-6, 1000
+# Serving policy, not part of the method: a request whose residual norm has
+# not halved over 16 outer iterations stops with KDMG_ENOCONV (outer_stall),
+# so the near-cutoff fields the method cannot solve release their worker
+# instead of holding it for the full 80 iterations.
+SERVE_STALL = 16
 
 
 def _serve_field(args):
@@ -225,7 +230,7 @@ def serve_main(a):
     kdmg.kdmg_init(0)
     nv1, nv2 = SERVE_NV
     params = kdmg.make_params([((4, 4), nv1), ((2, 2), nv2)], coarse_maxit=COARSE_MAXIT, outer_maxit=80,
-                              setup_tol=SERVE_SETUP_TOL, setup_maxit=SERVE_SETUP_MAXIT)
+                              setup_tol=SERVE_SETUP_TOL, setup_maxit=SERVE_SETUP_MAXIT, outer_stall=SERVE_STALL)
     cfgs = []
     t0 = time.perf_counter()
     for L, c, beta, U, plaq in fields:
@@ -359,6 +364,7 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
            "setup_mass": SERVE_M_SETUP, "prec": "mixed", "tol": 1e-10,
            "levels": "4x4 n_vec %d; 2x2 n_vec %d" % SERVE_NV,
            "setup_relaxation": {"tol": SERVE_SETUP_TOL, "maxit": SERVE_SETUP_MAXIT},
+           "outer_maxit": 80, "outer_stall": SERVE_STALL,
            "server": stats, "failed_requests": failures,
            "alone_vs_mix_max_rel_diff": max(diffs) if diffs else None,
            "alone_vs_mix_identical": sum(d == 0.0 for d in diffs), "alone_checked": len(diffs)}

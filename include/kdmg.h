@@ -89,6 +89,11 @@ typedef struct {
   double inter_tol;           /* intermediate GCR relative tolerance (0.2) */
   double coarse_tol;          /* coarsest CGNE relative tolerance (0.2) */
   int coarse_maxit;           /* coarsest CGNE iteration cap (256) */
+  int outer_stall;            /* 0 (default): off.  n > 0: a rhs whose residual
+                                 norm has not halved over the last n outer
+                                 iterations stops (KDMG_ENOCONV, best iterate
+                                 returned) -- a serving policy, not part of
+                                 the paper's method */
 } kdmg_mg_params;
 
 /* Per right-hand side result of kdmg_solve. */

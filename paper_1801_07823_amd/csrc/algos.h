@@ -110,11 +110,13 @@ void mr_smooth(const Ctx& c, int nrhs, long n, Cx<T>* x, Cx<T>* r, Cx<T>* q, int
 }
 
 // Flexible restarted GCR with classical Gram-Schmidt applied twice.
-// Stops a rhs when ||r||^2 <= tol^2 * (ext ? ext[r] : ||b||^2).
+// Stops a rhs when ||r||^2 <= tol^2 * (ext ? ext[r] : ||b||^2), and with
+// stall > 0 also when ||r|| has not halved over the last `stall` iterations.
 template <class T, class OpF, class PrecF>
 int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* Zb,
               Cx<T>* Wb, int restart, int maxit, double tol, const double* ext,
-              const KrylovState& k, const int* parent, OpF op, PrecF prec, bool trace = false) {
+              const KrylovState& k, const int* parent, OpF op, PrecF prec, bool trace = false,
+              int stall = 0) {
   start_solve(c, k, parent, nrhs);
   launch_map_reduce<1>(OpInit<T>{x, r, nullptr, b, n, k, tol * tol, ext}, n, nrhs, 1, c.rs, c.st);
   const long vs = (long)nrhs * n;
@@ -132,7 +134,7 @@ int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r
           launch_map(OpMultiAxpy<T>{w, z, Wb, Zb, vs, kk, n, k}, n, nrhs, c.st);
         }
       launch_map_reduce<3>(OpGCRred<T>{w, r, n, k}, n, nrhs, 1, c.rs, c.st);
-      launch_map_reduce<1>(OpGCRupd<T>{x, r, w, z, n, k}, n, nrhs, 1, c.rs, c.st);
+      launch_map_reduce<1>(OpGCRupd<T>{x, r, w, z, n, k, stall}, n, nrhs, 1, c.rs, c.st);
       ++its;
       if (trace) trace_residuals(c, k, nrhs, its, tol);
       if (!any_active(c, k.act, nrhs)) return its;

@@ -68,58 +68,76 @@ __host__ __device__ __forceinline__ int chir4(int s) { return __builtin_popcount
 //   mode 3: H = B (intra-block hops + m)
 // eps_in multiplies the source by eps.  Vectors are full-layout ([p][b][s][c],
 // `s*` = per-rhs stride) except that a vector only addressed at p = 0 may be
-// the even half alone.
-template <class R, class LT, class VT>
+// the even half alone.  One thread per site and a tile of RB rhs
+// (blockIdx.y): each link and neighbour index is loaded once per tile.
+template <class R, class LT, class VT, int RB>
 __global__ __launch_bounds__(256) void k4_hop(Cx<VT>* out, long so, const Cx<VT>* in, long si,
                                                const Cx<VT>* add, long sa, const Cx<VT>* add2, long sa2, R c2,
                                                R sgn, const Cx<LT>* __restrict__ lk,
                                                const int* __restrict__ nb4, Geo4 g, int p0, R m, int mode,
-                                               int eps_in, const int* act) {
+                                               int eps_in, const int* act, int nrhs) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y, p = p0 + blockIdx.z;
-  if (i >= 16L * g.Nb2 || !is_active(act, r)) return;
+  const int r0 = blockIdx.y * RB, p = p0 + blockIdx.z;
+  if (i >= 16L * g.Nb2) return;
+  bool on[RB];
+  bool any = false;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    on[b] = r0 + b < nrhs && is_active(act, r0 + b);
+    any = any || on[b];
+  }
+  if (!any) return;
   const long ib = (long)p * g.Nb2 * 16 + i;
   const int s = (int)(i & 15);
-  const Cx<VT>* src = in + r * si;
-  Cx<R> acc[3];
+  Cx<R> acc[RB][3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) acc[c] = mode >= 2 ? m * ld<R>(src[ib * 3 + c]) : Cx<R>{0, 0};
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      acc[b][c] = mode >= 2 && on[b] ? m * ld<R>(in[(r0 + b) * si + ib * 3 + c]) : Cx<R>{0, 0};
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const int bit = (s >> mu) & 1;
-    // forward: intra-block iff x_mu even
-    if (mode == 2 || (mode == 0) == (bit == 1)) {
-      const long j = nb4[ib * 8 + 2 * mu];
-      const Cx<LT>* U = lk + (ib * 4 + mu) * 9;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      // forward (dir 0): intra-block iff x_mu even; backward: iff x_mu odd
+      if (!(mode == 2 || (mode == 0) == (bit == (dir == 0 ? 1 : 0)))) continue;
+      const long j = nb4[ib * 8 + 2 * mu + dir];
+      const Cx<LT>* U = lk + ((dir == 0 ? ib : j) * 4 + mu) * 9;
+      Cx<R> u[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) u[q] = ld<R>(U[q]);
       const R e = (eps_in && chir4((int)(j & 15))) ? R(-1) : R(1);
-      Cx<R> v[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] = e * ld<R>(src[j * 3 + c]);
+      for (int b = 0; b < RB; ++b) {
+        if (!on[b]) continue;
+        const Cx<VT>* src = in + (r0 + b) * si + j * 3;
+        Cx<R> v[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) v[c] = e * ld<R>(src[c]);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) acc[a] += ld<R>(U[a * 3 + b]) * v[b];
-    }
-    // backward: intra-block iff x_mu odd
-    if (mode == 2 || (mode == 0) == (bit == 0)) {
-      const long j = nb4[ib * 8 + 2 * mu + 1];
-      const Cx<LT>* U = lk + (j * 4 + mu) * 9;
-      const R e = (eps_in && chir4((int)(j & 15))) ? R(-1) : R(1);
-      Cx<R> v[3];
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] = e * ld<R>(src[j * 3 + c]);
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) acc[a] -= cmul_conj(ld<R>(U[b * 3 + a]), v[b]);
+          for (int c = 0; c < 3; ++c) {
+            if (dir == 0)
+              acc[b][a] += u[a * 3 + c] * v[c];
+            else
+              acc[b][a] -= cmul_conj(u[c * 3 + a], v[c]);
+          }
+      }
     }
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    Cx<R> o = sgn * acc[c];
-    if (add) o += ld<R>(add[r * sa + ib * 3 + c]);
-    if (add2) o += c2 * ld<R>(add2[r * sa2 + ib * 3 + c]);
-    out[r * so + ib * 3 + c] = st<VT>(o);
+  for (int b = 0; b < RB; ++b) {
+    if (!on[b]) continue;
+    const int r = r0 + b;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Cx<R> o = sgn * acc[b][c];
+      if (add) o += ld<R>(add[r * sa + ib * 3 + c]);
+      if (add2) o += c2 * ld<R>(add2[r * sa2 + ib * 3 + c]);
+      out[r * so + ib * 3 + c] = st<VT>(o);
+    }
   }
 }
 
@@ -225,26 +243,41 @@ __global__ __launch_bounds__(256) void k4_restrict(Cx<VO>* out, const Cx<VI>* in
 }
 
 // Prolongation out[r][dof] = [add +] sum_i P[dof][i] in[r][Z][c nv + i] for
-// dof < n_out, (Z, c) = group of the dof (dgrp[dof] = 2 Z + c).
+// dof < n_out, (Z, c) = group of the dof (dgrp[dof] = 2 Z + c).  One thread
+// per dof and a tile of R4_PB rhs (blockIdx.y): each P[dof][i] is read once
+// per tile; the coarse values are shared by the thousands of dofs of a group
+// and come from cache.
+constexpr int R4_PB = 4;
 template <class R, class PT, class VI, class VO>
 __global__ __launch_bounds__(256) void k4_prolong(Cx<VO>* out, long so, const Cx<VO>* add, long sa, const Cx<VI>* in,
                                                   const Cx<PT>* __restrict__ P, const int* __restrict__ dgrp,
-                                                  int nv, long n_out, long ncoarse, const int* act) {
+                                                  int nv, long n_out, long ncoarse, const int* act, int nrhs) {
   const long dof = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (dof >= n_out || !is_active(act, r)) return;
+  const int r0 = blockIdx.y * R4_PB;
+  if (dof >= n_out) return;
+  bool on[R4_PB];
+#pragma unroll
+  for (int b = 0; b < R4_PB; ++b) on[b] = r0 + b < nrhs && is_active(act, r0 + b);
   const int gidx = dgrp[dof];
-  const Cx<VI>* e = in + (long)r * ncoarse + (long)(gidx >> 1) * 2 * nv + (gidx & 1) * nv;
-  Cx<R> s{0, 0};
-  for (int i = 0; i < nv; ++i) s += ld<R>(P[dof * nv + i]) * ld<R>(e[i]);
-  if (add) s += ld<R>(add[(long)r * sa + dof]);
-  out[(long)r * so + dof] = st<VO>(s);
+  const Cx<VI>* e = in + (long)(gidx >> 1) * 2 * nv + (gidx & 1) * nv;
+  Cx<R> acc[R4_PB];
+#pragma unroll
+  for (int b = 0; b < R4_PB; ++b) acc[b] = Cx<R>{0, 0};
+  for (int i = 0; i < nv; ++i) {
+    const Cx<R> pv = ld<R>(P[dof * nv + i]);
+#pragma unroll
+    for (int b = 0; b < R4_PB; ++b)
+      if (on[b]) acc[b] += pv * ld<R>(e[(long)(r0 + b) * ncoarse + i]);
+  }
+#pragma unroll
+  for (int b = 0; b < R4_PB; ++b) {
+    if (!on[b]) continue;
+    const long r = r0 + b;
+    Cx<R> o = acc[b];
+    if (add) o += ld<R>(add[r * sa + dof]);
+    out[r * so + dof] = st<VO>(o);
+  }
 }
-
-
-
-
-
 
 // ------------------------------------------------------------------ setup kernels (setup4d.hip)
 

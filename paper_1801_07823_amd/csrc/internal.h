@@ -137,8 +137,15 @@ template <class R, class LT>
 void launch4_hop(Cx<R>* out, long so, const Cx<R>* in, long si, const Cx<R>* add, long sa, const Cx<R>* add2,
                  long sa2, double c2, double sgn, const Cx<LT>* lk, const int* nb4, const Geo4& g, int p0, int npar,
                  double m, int mode, int eps_in, const int* act, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k4_hop<R, LT, R>), dim3(cdiv(16L * g.Nb2, 256), nrhs, npar), dim3(256), 0, st, out, so, in, si,
-                     add, sa, add2, sa2, (R)c2, (R)sgn, lk, nb4, g, p0, (R)m, mode, eps_in, act);
+  // a tile of 4 rhs per thread (links and neighbour indices read once per
+  // tile) from 4 rhs on
+  if (nrhs >= 4)
+    hipLaunchKernelGGL((k4_hop<R, LT, R, 4>), dim3(cdiv(16L * g.Nb2, 256), cdiv(nrhs, 4), npar), dim3(256), 0, st,
+                       out, so, in, si, add, sa, add2, sa2, (R)c2, (R)sgn, lk, nb4, g, p0, (R)m, mode, eps_in, act,
+                       nrhs);
+  else
+    hipLaunchKernelGGL((k4_hop<R, LT, R, 1>), dim3(cdiv(16L * g.Nb2, 256), nrhs, npar), dim3(256), 0, st, out, so,
+                       in, si, add, sa, add2, sa2, (R)c2, (R)sgn, lk, nb4, g, p0, (R)m, mode, eps_in, act, nrhs);
   KDMG_LAUNCH_CHECK();
 }
 
@@ -509,9 +516,9 @@ void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, l
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
   if (T.k == 0 && lat.nd == 4) {
     const long n_out = npar == 1 ? lat.half : 2 * lat.half;
-    dim3 grid(cdiv(n_out, 256), nrhs);
+    dim3 grid(cdiv(n_out, 256), cdiv(nrhs, R4_PB));
     hipLaunchKernelGGL((k4_prolong<R, PT, VI, VO>), grid, dim3(256), 0, st, out, so, add, sa, in, P,
-                       T.dgrp4.as<int>(), T.nv, n_out, (long)T.nZ * 2 * T.nv, act);
+                       T.dgrp4.as<int>(), T.nv, n_out, (long)T.nZ * 2 * T.nv, act, nrhs);
   } else if (T.k == 0) {
     const int nd = 4 * T.a2.a0 * T.a2.a1;
     int RB = nrhs < 32 ? nrhs : 32;

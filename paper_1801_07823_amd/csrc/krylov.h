@@ -22,6 +22,7 @@ enum ScalarSlot {
   S_ALPHA_I,
   S_BETA,
   S_INV,         // 1 / ||w||
+  S_REF,         // ||r||^2 at the last stall checkpoint (GCR with a stall rule)
   S_H,           // GCR projections: 2 * max_restart slots from here
   S_COUNT = S_H + 2 * 64
 };
@@ -81,6 +82,7 @@ struct OpInit {
   __device__ void finish(int rr, int, const double* s) const {
     double* S = k.sc + rr * S_COUNT;
     S[S_RR] = s[0];
+    S[S_REF] = s[0];
     S[S_TARGET] = tol2 * (ext ? ext[rr] : s[0]);
     if (!(s[0] > S[S_TARGET]) || s[0] == 0.0) k.act[rr] = 0;
   }
@@ -321,7 +323,7 @@ struct OpGCRred {
 // x += alpha z ; r -= alpha w ; w *= inv ; z *= inv ; ||r||^2 -> convergence
 template <class T>
 struct OpGCRupd {
-  Cx<T>* x; Cx<T>* r; Cx<T>* w; Cx<T>* z; long n; KrylovState k;
+  Cx<T>* x; Cx<T>* r; Cx<T>* w; Cx<T>* z; long n; KrylovState k; int stall;
   __device__ bool active(int rr) const { return k.act[rr] != 0; }
   __device__ void elem(int rr, int, long i, Acc<1>& a) const {
     const double* S = k.sc + rr * S_COUNT;
@@ -341,7 +343,13 @@ struct OpGCRupd {
     k.its[rr] += 1;
     k.tot[rr] += 1;
     S[S_RR] = s[0];
-    if (s[0] <= S[S_TARGET]) k.act[rr] = 0;
+    if (s[0] <= S[S_TARGET]) {
+      k.act[rr] = 0;
+    } else if (stall > 0 && k.its[rr] % stall == 0) {
+      // stall rule: the norm must have halved since the last checkpoint
+      if (s[0] > 0.25 * S[S_REF]) k.act[rr] = 0;
+      else S[S_REF] = s[0];
+    }
   }
 };
 

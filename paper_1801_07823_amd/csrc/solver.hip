@@ -396,7 +396,7 @@ class Runner {
     return gcr_solve<double>(c_, nrhs_, n, ws_.bt.as<c64>(), ws_.ye.as<c64>(), ws_.re.as<c64>(),
                              ws_.Zo.as<c64>(), ws_.Wo.as<c64>(), P.outer_restart, P.outer_maxit, tol,
                              ws_.bnorm2.as<double>(), ws_.kout.k, nullptr, op64, prec,
-                             trace_enabled());
+                             trace_enabled(), P.outer_stall);
   }
 
   int poll_ = 8;

@@ -35,7 +35,7 @@ class kdmg_mg_params(ctypes.Structure):
                 ("mr_its", ctypes.c_int), ("mr_omega", ctypes.c_double),
                 ("inter_restart", ctypes.c_int), ("inter_maxit", ctypes.c_int),
                 ("inter_tol", ctypes.c_double), ("coarse_tol", ctypes.c_double),
-                ("coarse_maxit", ctypes.c_int)]
+                ("coarse_maxit", ctypes.c_int), ("outer_stall", ctypes.c_int)]
 
 
 class kdmg_solve_info(ctypes.Structure):

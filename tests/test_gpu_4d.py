@@ -48,7 +48,7 @@ def relerr(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("nrhs", [1, 3, 5])
 def test_apply_D_4d(K, field, nrhs):
     olat = OLattice(DIMS, ncolor=3)
     m = 0.1
@@ -65,21 +65,22 @@ def test_apply_D_4d(K, field, nrhs):
     assert np.all(err < 3e-3)
 
 
-@pytest.mark.parametrize("m", [0.1, 0.5])
-def test_fine_operators_4d(K, field, m):
+@pytest.mark.parametrize("m,nr", [(0.1, 2), (0.5, 2), (0.1, 5)])
+def test_fine_operators_4d(K, field, m, nr):
+    """nr = 5 takes the hop kernel's 4-rhs tile with a ragged tail."""
     olat = OLattice(DIMS, ncolor=3)
     kd = KDOperator(olat, field, m)
     lat = K.Lattice(DIMS, field)
-    v = gaussian_vectors(2, olat.ndof, 4, tag=0)
-    out = torch.empty((2, olat.ndof), dtype=torch.complex128, device="cuda")
-    for fn, ref in ((lambda o: K.kdmg_apply_A(lat, m, dev(v), o, 2), kd.A),
-                    (lambda o: K.kdmg_apply_A(lat, m, dev(v), o, 2, dagger=True), kd.Adag),
-                    (lambda o: K.kdmg_apply_Binv(lat, m, dev(v), o, 2), kd.Binv)):
+    v = gaussian_vectors(nr, olat.ndof, 4, tag=0)
+    out = torch.empty((nr, olat.ndof), dtype=torch.complex128, device="cuda")
+    for fn, ref in ((lambda o: K.kdmg_apply_A(lat, m, dev(v), o, nr), kd.A),
+                    (lambda o: K.kdmg_apply_A(lat, m, dev(v), o, nr, dagger=True), kd.Adag),
+                    (lambda o: K.kdmg_apply_Binv(lat, m, dev(v), o, nr), kd.Binv)):
         fn(out)
         assert relerr(out.cpu().numpy(), (ref @ v.T).T) < 1e-11
     ve = v[:, :olat.ndof // 2]
-    oute = torch.empty((2, olat.ndof // 2), dtype=torch.complex128, device="cuda")
-    K.kdmg_apply_schur(lat, m, dev(ve), oute, 2)
+    oute = torch.empty((nr, olat.ndof // 2), dtype=torch.complex128, device="cuda")
+    K.kdmg_apply_schur(lat, m, dev(ve), oute, nr)
     assert relerr(oute.cpu().numpy(), (kd.S @ ve.T).T) < 1e-11
 
 
@@ -148,6 +149,24 @@ def test_hierarchy_4d_from_given_vectors(K, field):
     assert dims_c == (2, 2, 2, 2)
     Ag = assemble4(gh.coarse_op(1), dims_c)
     assert relerr(Ag, oh.ops[1].toarray()) < 1e-10
+    # level-0 transfers with 5 rhs (the prolongation's 4-rhs tile and a
+    # ragged tail): FP64 against the oracle's P to 1e-10 (P itself agrees to
+    # that), the FP16-P mixed form to 2e-3 per rhs
+    P = oh.P[0]
+    nf, nc = P.shape
+    v = gaussian_vectors(5, nf, 55, tag=0)
+    e = gaussian_vectors(5, nc, 56, tag=0)
+    for prec, dt, tol in ((K.KDMG_FP64, torch.complex128, None), (K.KDMG_MIXED, torch.complex64, 2e-3)):
+        rc = torch.empty((5, nc), dtype=dt, device="cuda")
+        K.kdmg_restrict(gh, 0, dev(v, dt), rc, 5, prec=prec)
+        pf = torch.empty((5, nf), dtype=dt, device="cuda")
+        K.kdmg_prolong(gh, 0, dev(e, dt), pf, 5, prec=prec)
+        for got, ref in ((rc.cpu().numpy(), (P.conj().T @ v.T).T), (pf.cpu().numpy(), (P @ e.T).T)):
+            if tol is None:
+                assert relerr(got, ref) < 1e-10
+            else:
+                err = np.linalg.norm(got.astype(np.complex128) - ref, axis=1) / np.linalg.norm(ref, axis=1)
+                assert np.all(err < tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

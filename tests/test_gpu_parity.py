@@ -319,6 +319,40 @@ def test_three_level_multi_rhs_solve(K, prec):
     assert np.linalg.norm(x1.cpu().numpy()[0] - xs[2]) / np.linalg.norm(xs[2]) < 1e-12
 
 
+def test_outer_stall_rule(K):
+    """The opt-in stall rule of the outer solve (a serving policy): with a
+    working hierarchy that halves the residual every iteration it never fires
+    and the result is bit-identical to the solve without it; with a crippled
+    preconditioner (one intermediate and one coarsest iteration, no
+    smoothing) and a 2-iteration window it stops every rhs after 2 outer
+    iterations with KDMG_ENOCONV, the returned iterate no worse than x = 0."""
+    dims, beta, m = (32, 32), 6.0, 0.02
+    U = field(dims, beta, seed=102, sweeps=100)
+    levels = [((2, 2), 8), ((2, 2), 8)]
+    _, psi0 = oracle_setup(dims, U, m, levels, 8)
+    lat = K.Lattice(dims, U)
+    b = gaussian_vectors(3, lat.volume, 57)
+    D = dirac_matrix(OLattice(dims), U, m)
+    xs = []
+    for stall in (0, 4):
+        gh = K.Hierarchy(lat, m, K.make_params(levels, outer_stall=stall), psi0)
+        x = torch.empty((3, lat.volume), dtype=torch.complex128, device="cuda")
+        info, _ = K.kdmg_solve(gh, dev(b), x, 3, 1e-10, prec=K.KDMG_FP64)
+        assert all(i["converged"] for i in info)
+        xs.append(x.cpu().numpy())
+    assert np.array_equal(xs[0], xs[1])
+    weak = K.make_params(levels, outer_stall=2, inter_maxit=1, coarse_maxit=1, mr_its=0, outer_maxit=50)
+    gh = K.Hierarchy(lat, 0.001, weak, psi0)
+    x = torch.empty((3, lat.volume), dtype=torch.complex128, device="cuda")
+    info, st = K.kdmg_solve(gh, dev(b), x, 3, 1e-10, prec=K.KDMG_FP64, raise_on_noconv=False)
+    assert st == K.KDMG_ENOCONV
+    D0 = dirac_matrix(OLattice(dims), U, 0.001)
+    xw = x.cpu().numpy()
+    for r in range(3):
+        assert not info[r]["converged"] and info[r]["outer_its"] == 2
+        assert np.linalg.norm(b[r] - D0 @ xw[r]) <= np.linalg.norm(b[r])
+
+
 def test_free_field_solve_matches_fft(K):
     from oracle.exact import free_fft_solve
     dims, m = (32, 32), 0.01
