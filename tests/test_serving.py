@@ -31,16 +31,16 @@ def K():
     return kdmg
 
 
-CONFIGS = [((16, 16), 3.0, 11, [((4, 4), 8)]),
+SERVED = [((16, 16), 3.0, 11, [((4, 4), 8)]),
            ((32, 32), 6.0, 12, [((2, 2), 8), ((2, 2), 8)]),
            ((32, 32), 6.0, 13, [((2, 2), 8), ((2, 2), 8)])]
 M_SETUP = 0.02
 
 
 @pytest.fixture(scope="module")
-def configs(K):
+def served(K):
     out = []
-    for dims, beta, seed, levels in CONFIGS:
+    for dims, beta, seed, levels in SERVED:
         U, _ = u1_heatbath(dims, beta, 30, seed)
         lat = K.Lattice(dims, U)
         psi0 = []
@@ -55,21 +55,21 @@ def configs(K):
     return out
 
 
-def requests(configs, count, seed):
+def requests(served, count, seed):
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(count):
-        c = int(rng.integers(len(configs)))
+        c = int(rng.integers(len(served)))
         m = float(np.exp(rng.uniform(np.log(0.01), np.log(0.1))))
-        V = int(np.prod(configs[c][0]))
+        V = int(np.prod(served[c][0]))
         b = gaussian_vectors(1, V, 900 + seed, tag=i)
         reqs.append((c, m, b))
     return reqs
 
 
-def serve(K, configs, reqs, slots, budget, all_at_once):
+def serve(K, served, reqs, slots, budget, all_at_once):
     srv = K.Server(slots, budget)
-    ids = [srv.add_config(h) for (_, _, _, h) in configs]
+    ids = [srv.add_config(h) for (_, _, _, h) in served]
     xs, infos, stats = [None] * len(reqs), [None] * len(reqs), None
     try:
         tickets = []
@@ -95,17 +95,17 @@ def serve(K, configs, reqs, slots, budget, all_at_once):
     return xs, infos, stats
 
 
-def test_served_alone_equals_mix(K, configs):
-    reqs = requests(configs, 12, 1)
+def test_served_alone_equals_mix(K, served):
+    reqs = requests(served, 12, 1)
     budget = 8 << 30
-    x_alone, _, st_alone = serve(K, configs, reqs, 1, budget, all_at_once=False)
-    x_mix, info_mix, st_mix = serve(K, configs, reqs, 3, budget, all_at_once=True)
+    x_alone, _, st_alone = serve(K, served, reqs, 1, budget, all_at_once=False)
+    x_mix, info_mix, st_mix = serve(K, served, reqs, 3, budget, all_at_once=True)
     assert st_alone["peak_running"] == 1
     assert st_mix["peak_running"] >= 2
     assert st_mix["completed"] == len(reqs)
     exact = 0
     for (c, m, b), xa, xm, inf in zip(reqs, x_alone, x_mix, info_mix):
-        dims, U = configs[c][0], configs[c][1]
+        dims, U = served[c][0], served[c][1]
         D = dirac_matrix(OLattice(dims), U, m)
         assert inf["converged"]
         assert np.linalg.norm(b[0] - D @ xm) / np.linalg.norm(b[0]) <= 1e-10
@@ -114,11 +114,11 @@ def test_served_alone_equals_mix(K, configs):
     print("served results identical alone and in the mix: %d of %d" % (exact, len(reqs)))
 
 
-def test_served_equals_direct_solve(K, configs):
-    reqs = requests(configs, 4, 2)
-    x_srv, _, _ = serve(K, configs, reqs, 2, 8 << 30, all_at_once=True)
+def test_served_equals_direct_solve(K, served):
+    reqs = requests(served, 4, 2)
+    x_srv, _, _ = serve(K, served, reqs, 2, 8 << 30, all_at_once=True)
     for (c, m, b), xs in zip(reqs, x_srv):
-        h = configs[c][3].at_mass(m)
+        h = served[c][3].at_mass(m)
         bd = torch.from_numpy(b).to("cuda")
         xd = torch.zeros_like(bd)
         info, _ = K.kdmg_solve(h, bd, xd, 1, 1e-10, prec=K.KDMG_MIXED)
@@ -126,20 +126,20 @@ def test_served_equals_direct_solve(K, configs):
         assert np.linalg.norm(xs - x) / np.linalg.norm(x) <= 1e-12
 
 
-def test_admission_by_footprint(K, configs):
-    reqs = [r for r in requests(configs, 10, 3) if r[0] != 0][:5]
+def test_admission_by_footprint(K, served):
+    reqs = [r for r in requests(served, 10, 3) if r[0] != 0][:5]
     srv = K.Server(3, 1 << 40)
-    cid = srv.add_config(configs[1][3])
+    cid = srv.add_config(served[1][3])
     one = srv.request_bytes(cid, 1, K.KDMG_MIXED)
     srv.close()
     budget = int(one * 1.5)
-    _, infos, st = serve(K, configs, reqs, 3, budget, all_at_once=True)
+    _, infos, st = serve(K, served, reqs, 3, budget, all_at_once=True)
     assert all(i["converged"] for i in infos)
     assert st["peak_running"] == 1
     assert st["peak_allocated"] <= budget
     small = K.Server(2, one // 2)
     try:
-        c = small.add_config(configs[1][3])
+        c = small.add_config(served[1][3])
         b = torch.zeros((1, 32 * 32), dtype=torch.complex128, device="cuda")
         x = torch.zeros_like(b)
         with pytest.raises(K.KdmgError) as e:
