@@ -51,3 +51,31 @@ def test_benchmark_workload_parity():
         err = np.linalg.norm(xs[r] - xc) / np.linalg.norm(xc)
         print("rhs %d: ||x - x_cg|| / ||x_cg|| = %.2e (outer its %d)" % (r, err, info[r]["outer_its"]))
         assert err <= 2e-7
+
+
+def test_su3_benchmark_workload_residuals():
+    """The 4D SU(3) workload of `bench.py --su3` at its full size (24^4,
+    m = 0.01, 8 rhs, mixed, two levels with n_vec 24): every rhs's true
+    residual recomputed with the oracle's D in FP64 on the CPU is <= 1e-10.
+    (The oracle's CG at this size would take minutes per rhs; the solution
+    error is bounded by kappa(D) * 1e-10 <= (m + 4) / m * 1e-10 = 4e-8.)"""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import bench
+    from paper_1801_07823_amd import kdmg
+    from synth import su3_smooth_random
+    kdmg.kdmg_init(0)
+    U = su3_smooth_random(bench.SU3_DIMS, 0.4, 5, 0.5, 2404)
+    lat = kdmg.Lattice(bench.SU3_DIMS, U)
+    n = lat.volume * 3
+    params = kdmg.make_params([((4, 4, 4, 4), bench.SU3_NV)], coarse_maxit=1024, outer_maxit=300)
+    h = kdmg.Hierarchy(lat, bench.SU3_MASS, params, [gaussian_vectors(bench.SU3_NV, n, 2404, tag=1)])
+    b = gaussian_vectors(bench.SU3_NRHS, n, 2404, tag=0)
+    x = torch.empty((bench.SU3_NRHS, n), dtype=torch.complex128, device="cuda")
+    info, _ = kdmg.kdmg_solve(h, torch.from_numpy(b).to("cuda"), x, bench.SU3_NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
+    xs = x.cpu().numpy()
+    D = dirac_matrix(OLattice(bench.SU3_DIMS, ncolor=3), U, bench.SU3_MASS)
+    res = np.linalg.norm(b.T - D @ xs.T, axis=0) / np.linalg.norm(b, axis=1)
+    print("24^4 SU(3): true residuals %s" % np.array2string(res, precision=2))
+    assert all(i["converged"] for i in info)
+    assert np.all(res <= 1e-10)
