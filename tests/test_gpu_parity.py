@@ -379,6 +379,9 @@ def test_errors_are_reported(K):
     with pytest.raises(K.KdmgError) as e:
         K.Hierarchy(lat, 0.1, bad, [gaussian_vectors(8, 256, 1)])
     assert e.value.status == K.KDMG_EINVAL
+    with pytest.raises(K.KdmgError) as e:
+        K.Hierarchy(lat, 0.1, K.make_params([((4, 4), 8)], outer_stall=-1), [gaussian_vectors(8, 256, 1)])
+    assert e.value.status == K.KDMG_EINVAL
     # iteration cap forced from the host: ENOCONV with the best iterate returned
     levels = [((4, 4), 8)]
     p = K.make_params(levels, outer_maxit=1)
