@@ -94,6 +94,11 @@ typedef struct {
                                  iterations stops (KDMG_ENOCONV, best iterate
                                  returned) -- a serving policy, not part of
                                  the paper's method */
+  int coarse_tail;            /* 16 (default): once this many or fewer rhs of a
+                                 wider batched coarsest CGNE are still active,
+                                 they continue as a narrower problem with the
+                                 launch shape tuned for that width (per-rhs
+                                 arithmetic unchanged); 0: off.  0..64 */
 } kdmg_mg_params;
 
 /* Per right-hand side result of kdmg_solve. */
@@ -257,6 +262,12 @@ kdmg_status kdmg_hierarchy_set_mass(kdmg_hierarchy* h, const kdmg_hierarchy* bas
    `replays` (may be NULL) receives the number of chunk graphs replayed on
    this hierarchy so far. */
 kdmg_status kdmg_hierarchy_graphs(kdmg_hierarchy* h, int enable, long long* replays);
+
+/* Implementation counters of the coarsest solve on this hierarchy so far, not
+   quantities of the method: chunk graphs replayed, and batched coarsest CGNE
+   calls that continued as a narrower tail problem (kdmg_mg_params.coarse_tail).
+   Either pointer may be NULL. */
+kdmg_status kdmg_hierarchy_counters(kdmg_hierarchy* h, long long* graph_replays, long long* tail_entries);
 
 /* Measurement hook (not an operation of the method): HIP-event timing of the
    two fused kernels of each coarsest-level CGNE iteration, on the solve's own

@@ -473,7 +473,8 @@ extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass
   KDMG_CHECK(params->nlevels >= 2 && params->nlevels <= 4, KDMG_EINVAL, "nlevels must be 2..4");
   KDMG_CHECK(mass > 0.0, KDMG_EINVAL, "mass must be positive");
   KDMG_CHECK(params->setup_maxit >= 0 && params->outer_restart >= 1 && params->outer_restart <= 64 &&
-                 params->inter_restart >= 1 && params->inter_restart <= 64 && params->outer_stall >= 0,
+                 params->inter_restart >= 1 && params->inter_restart <= 64 && params->outer_stall >= 0 &&
+                 params->coarse_tail >= 0 && params->coarse_tail <= 64,
              KDMG_EINVAL, "bad solver parameters");
   for (int k = 0; k < params->nlevels - 1; ++k)
     KDMG_CHECK(psi0_host[k] != nullptr, KDMG_EINVAL, "missing starting vectors");

@@ -291,6 +291,7 @@ struct kdmg_hierarchy {
     double ms = 0.0;
     long long launches = 0;
     long long graph_replays = 0;  // captured CGNE chunks replayed (counted whether or not timing is on)
+    long long tail_entries = 0;   // coarsest CGNE calls that continued as the narrower tail problem
   } timer;
   ~kdmg_hierarchy();
   // device bytes owned by this hierarchy (borrowed transfers not included)

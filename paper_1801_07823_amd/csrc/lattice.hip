@@ -398,4 +398,5 @@ extern "C" void kdmg_default_params(kdmg_mg_params* p) {
   p->coarse_tol = 0.2;
   p->coarse_maxit = 256;
   p->outer_stall = 0;
+  p->coarse_tail = 16;
 }

@@ -90,6 +90,11 @@ struct LevelWS {
   DevBuf cg_rr, cg_target, cg_act, PA, PB;  // fused CGNE state (coarsest level)
   std::unique_ptr<AsyncPoll> cg_poll;        // its flag copies and events
   std::unique_ptr<ChunkGraph> cg_graph;      // captured CGNE chunk
+  // the fused CGNE's tail problem of `tail` rhs (0: none; batches of more
+  // rhs than kdmg_mg_params.coarse_tail only)
+  int tail = 0;
+  DevBuf tx, tr, tp, trr, ttarget, tact, tints, tPA, tPB, tidx;
+  std::unique_ptr<ChunkGraph> cg_graph_t;
   KrylovAlloc ks, kmr;
   template <class T> Cx<T>* v(DevBuf& d) const { return d.as<Cx<T>>(); }
 };
@@ -171,6 +176,49 @@ bool capture_chunk(ChunkGraph& G, const TileShape& sh, const CoarseLevel& L, c64
   return true;
 }
 
+// Tail of the fused CGNE.  A batched call runs until its slowest rhs
+// converges; once at most W.tail rhs are still active, their rows (x, r, p,
+// the partial sums of ||p||^2 and the per-rhs scalars of both parity slots)
+// are gathered into a W.tail-rhs problem that continues with the launch
+// shape tuned for that width, and the solution and iteration counts are
+// scattered back at the end.  idx[j] < 0 marks an empty, inactive row.
+template <class T>
+__global__ __launch_bounds__(256) void k_rows_gather(T* dst, const T* src, const int* idx, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, q = idx[j];
+  if (i < n) dst[(long)j * n + i] = q >= 0 ? src[(long)q * n + i] : T{};
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_rows_scatter(T* dst, const T* src, const int* idx, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, q = idx[j];
+  if (i < n && q >= 0) dst[(long)q * n + i] = src[(long)j * n + i];
+}
+
+__global__ __launch_bounds__(64) void k_cgne_state_gather(CgneState t, CgneState s, const int* idx, int nrhs, int nt) {
+  const int j = threadIdx.x;
+  if (j >= nt) return;
+  const int q = idx[j];
+  for (int sl = 0; sl < 2; ++sl) {
+    t.rr[sl * nt + j] = q >= 0 ? s.rr[sl * nrhs + q] : 0.0;
+    t.act[sl * nt + j] = q >= 0 ? s.act[sl * nrhs + q] : 0;
+  }
+  t.target[j] = q >= 0 ? s.target[q] : 0.0;
+  t.its[j] = q >= 0 ? s.its[q] : 0;
+  t.tot[j] = q >= 0 ? s.tot[q] : 0;
+  t.calls[j] = q >= 0 ? s.calls[q] : 0;
+}
+
+__global__ __launch_bounds__(64) void k_cgne_state_scatter(CgneState s, CgneState t, const int* idx, int nt) {
+  const int j = threadIdx.x;
+  if (j >= nt || idx[j] < 0) return;
+  const int q = idx[j];
+  s.its[q] = t.its[j];
+  s.tot[q] = t.tot[j];
+  s.calls[q] = t.calls[j];
+}
+
 int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c64* b, c64* x, c64* r,
                c64* p, double tol, int maxit, const int* parent, int poll, kdmg_hierarchy::KTimer* tm,
                bool graphs) {
@@ -184,7 +232,7 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
   s.parent = parent;
   s.PA = W.PA.as<double>();
   s.PB = W.PB.as<double>();
-  const TileShape sh = cgne_shape(L, nrhs);
+  TileShape sh = cgne_shape(L, nrhs);
   KDMG_CHECK(sh.smem <= LDS_LIMIT, KDMG_EUNSUPPORTED, "coarsest operator too large for the fused CGNE");
   launch_cgne_init(sh, L, x, r, p, b, s, nrhs, tol * tol, c.st);
   // Chunks of `poll` iterations.  After each chunk the active flags are
@@ -192,7 +240,7 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
   // copy is checked while this chunk runs, so the stream never drains;
   // iterations launched past convergence return at once (all flags off).
   AsyncPoll& ap = *W.cg_poll;
-  const bool timed = tm && tm->on;
+  bool timed = tm && tm->on;  // live timing covers the full-width launches only
   bool pending[2] = {false, false};
   int done_its[2] = {0, 0};
   int cs = 0, k = 0;
@@ -205,20 +253,66 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
       tm->launches += done_its[slot] * 2 - 1;
     }
   };
-  ChunkGraph& G = *W.cg_graph;
+  // the problem the loop advances: the full batch, later possibly the tail
+  int nr = nrhs;
+  c64 *xc = x, *rc = r, *pc = p;
+  CgneState sc = s;
+  ChunkGraph* G = W.cg_graph.get();
+  const int nt = W.tail;  // <= 64, the state kernels' block
+  const bool can_tail = nt > 0 && W.cg_graph_t && nrhs > nt;
+  bool tail = false;
+  const long nv = (long)L.nsites * L.ndc;
+  auto enter_tail = [&](const int* flags) -> bool {
+    // flags: the active flags of iteration k (this chunk's copy, synchronised)
+    int* idx_h = ap.host;  // both pinned slots are free here
+    int na = 0;
+    for (int q = 0; q < nrhs; ++q)
+      if (flags[q]) idx_h[na++] = q;
+    if (na == 0) return false;
+    for (int j = na; j < nt; ++j) idx_h[j] = -1;
+    int* idx = W.tidx.as<int>();
+    KDMG_HIP(hipMemcpyAsync(idx, idx_h, sizeof(int) * nt, hipMemcpyHostToDevice, c.st));
+    CgneState t;
+    t.rr = W.trr.as<double>();
+    t.target = W.ttarget.as<double>();
+    t.act = W.tact.as<int>();
+    t.its = W.tints.as<int>();
+    t.tot = t.its + nt;
+    t.calls = t.tot + nt;
+    t.parent = nullptr;
+    t.PA = W.tPA.as<double>();
+    t.PB = W.tPB.as<double>();
+    const dim3 gv(cdiv(nv, 256), nt), gs(cdiv(L.nsites, 256), nt);
+    hipLaunchKernelGGL(k_rows_gather<c64>, gv, dim3(256), 0, c.st, W.tx.as<c64>(), x, idx, nv);
+    hipLaunchKernelGGL(k_rows_gather<c64>, gv, dim3(256), 0, c.st, W.tr.as<c64>(), r, idx, nv);
+    hipLaunchKernelGGL(k_rows_gather<c64>, gv, dim3(256), 0, c.st, W.tp.as<c64>(), p, idx, nv);
+    hipLaunchKernelGGL(k_rows_gather<double>, gs, dim3(256), 0, c.st, t.PB, s.PB, idx, (long)L.nsites);
+    hipLaunchKernelGGL(k_cgne_state_gather, dim3(1), dim3(64), 0, c.st, t, s, idx, nrhs, nt);
+    KDMG_LAUNCH_CHECK();
+    xc = W.tx.as<c64>();
+    rc = W.tr.as<c64>();
+    pc = W.tp.as<c64>();
+    sc = t;
+    nr = nt;
+    sh = cgne_shape(L, nt);
+    G = W.cg_graph_t.get();
+    tail = true;
+    if (tm) ++tm->tail_entries;
+    return true;
+  };
   while (k < maxit && !stop) {
     const int kend = std::min(k + poll, maxit);
     // the first chunk of a call runs eagerly (it also sets the kernels' LDS
     // limits and takes the timing start); later full chunks replay a graph
     bool replayed = false;
-    if (graphs && k > 0 && kend - k == poll && k % 2 == 0 && !G.failed) {
-      if (!G.matches(sh, poll, nrhs) && !capture_chunk(G, sh, L, x, r, p, s, nrhs, poll)) {
+    if (graphs && k > 0 && kend - k == poll && k % 2 == 0 && !G->failed) {
+      if (!G->matches(sh, poll, nr) && !capture_chunk(*G, sh, L, xc, rc, pc, sc, nr, poll)) {
         (void)hipGetLastError();
-        G.failed = true;  // capture unavailable: stay eager on this workspace
+        G->failed = true;  // capture unavailable: stay eager on this workspace
       }
-      if (!G.failed) {
-        KDMG_HIP(hipGraphLaunch(G.exec, c.st));
-        ++G.replays;
+      if (!G->failed) {
+        KDMG_HIP(hipGraphLaunch(G->exec, c.st));
+        ++G->replays;
         if (tm) ++tm->graph_replays;
         k = kend;
         replayed = true;
@@ -226,8 +320,8 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
     }
     if (!replayed)
       for (; k < kend; ++k)
-        launch_cgne_iter(sh, L, x, r, p, s, nrhs, k, c.st, timed && k == 0 ? tm->e0 : nullptr);
-    KDMG_HIP(hipMemcpyAsync(ap.host + cs * nrhs, s.act + (k & 1) * nrhs, sizeof(int) * nrhs,
+        launch_cgne_iter(sh, L, xc, rc, pc, sc, nr, k, c.st, timed && k == 0 ? tm->e0 : nullptr);
+    KDMG_HIP(hipMemcpyAsync(ap.host + cs * nrhs, sc.act + (k & 1) * nr, sizeof(int) * nr,
                             hipMemcpyDeviceToHost, c.st));
     KDMG_HIP(hipEventRecord(ap.ev[cs], c.st));
     pending[cs] = true;
@@ -236,11 +330,24 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
     if (pending[ps]) {
       KDMG_HIP(hipEventSynchronize(ap.ev[ps]));
       pending[ps] = false;
-      bool any = false;
-      for (int q = 0; q < nrhs; ++q) any = any || ap.host[ps * nrhs + q] != 0;
-      if (!any) {
+      int active = 0;
+      for (int q = 0; q < nr; ++q) active += ap.host[ps * nrhs + q] != 0;
+      if (active == 0) {
         account(ps);
         stop = true;
+      } else if (can_tail && !tail && active <= nt && k < maxit) {
+        // drain to this chunk's end and take its (newer) flags as the set
+        KDMG_HIP(hipEventSynchronize(ap.ev[cs]));
+        pending[cs] = false;
+        account(cs);
+        timed = false;
+        std::vector<int> flags(ap.host + cs * nrhs, ap.host + cs * nrhs + nrhs);
+        if (!enter_tail(flags.data())) {
+          stop = true;  // nothing left active
+        } else {
+          cs = 0;
+          continue;
+        }
       }
     }
     cs = ps;
@@ -249,6 +356,13 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
     const int last = cs ^ 1;
     KDMG_HIP(hipEventSynchronize(ap.ev[last]));
     account(last);
+  }
+  if (tail) {
+    const int* idx = W.tidx.as<int>();
+    const dim3 gv(cdiv(nv, 256), nt);
+    hipLaunchKernelGGL(k_rows_scatter<c64>, gv, dim3(256), 0, c.st, x, xc, idx, nv);
+    hipLaunchKernelGGL(k_cgne_state_scatter, dim3(1), dim3(64), 0, c.st, s, sc, idx, nt);
+    KDMG_LAUNCH_CHECK();
   }
   return k;
 }
@@ -477,6 +591,21 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
         L.cg_graph = std::make_unique<ChunkGraph>();
         L.cg_poll = std::make_unique<AsyncPoll>();
         L.cg_poll->init(nrhs);
+        if (P.coarse_tail > 0 && nrhs > P.coarse_tail) {
+          const int nt = L.tail = P.coarse_tail;
+          const size_t vt = sizeof(c64) * (size_t)nt * h.L[l].nsites * h.L[l].ndc;
+          A(L.tx, vt);
+          A(L.tr, vt);
+          A(L.tp, vt);
+          A(L.trr, sizeof(double) * 2 * nt);
+          A(L.ttarget, sizeof(double) * nt);
+          A(L.tact, sizeof(int) * 2 * nt);
+          A(L.tints, sizeof(int) * 3 * nt);
+          A(L.tPA, sizeof(double) * (size_t)nt * h.L[l].nsites);
+          A(L.tPB, sizeof(double) * (size_t)nt * h.L[l].nsites);
+          A(L.tidx, sizeof(int) * nt);
+          L.cg_graph_t = std::make_unique<ChunkGraph>();
+        }
       } else {
         A(L.Z, v * P.inter_restart);
         A(L.W, v * P.inter_restart);
@@ -552,6 +681,8 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
     for (int l = 1; l < h->nlevels; ++l)
       autotune_level(h->L[l], nrhs, prec == KDMG_MIXED && l < h->nlevels - 1, st);
     autotune_cgne(h->L[h->nlevels - 1], nrhs, st);
+    const int tw = h->params.coarse_tail;
+    if (tw > 0 && nrhs > tw) autotune_cgne(h->L[h->nlevels - 1], tw, st);
   }
   SolveWS& ws = *h->ws;
   int expect = 0;
@@ -678,5 +809,14 @@ extern "C" kdmg_status kdmg_hierarchy_graphs(kdmg_hierarchy* h, int enable, long
   KDMG_CHECK(h && enable >= -1 && enable <= 1, KDMG_EINVAL, "kdmg_hierarchy_graphs: bad argument");
   if (enable >= 0) h->use_graphs = enable != 0;
   if (replays) *replays = h->timer.graph_replays;
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_counters(kdmg_hierarchy* h, long long* graph_replays,
+                                               long long* tail_entries) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h, KDMG_EINVAL, "kdmg_hierarchy_counters: null hierarchy");
+  if (graph_replays) *graph_replays = h->timer.graph_replays;
+  if (tail_entries) *tail_entries = h->timer.tail_entries;
   KDMG_API_END
 }

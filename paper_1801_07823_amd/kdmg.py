@@ -35,7 +35,8 @@ class kdmg_mg_params(ctypes.Structure):
                 ("mr_its", ctypes.c_int), ("mr_omega", ctypes.c_double),
                 ("inter_restart", ctypes.c_int), ("inter_maxit", ctypes.c_int),
                 ("inter_tol", ctypes.c_double), ("coarse_tol", ctypes.c_double),
-                ("coarse_maxit", ctypes.c_int), ("outer_stall", ctypes.c_int)]
+                ("coarse_maxit", ctypes.c_int), ("outer_stall", ctypes.c_int),
+                ("coarse_tail", ctypes.c_int)]
 
 
 class kdmg_solve_info(ctypes.Structure):
@@ -82,6 +83,7 @@ _SIGS = {
     "kdmg_hierarchy_at_mass": (_I, [_P, _D, _P, ctypes.POINTER(_P)]),
     "kdmg_hierarchy_set_mass": (_I, [_P, _P, _D, _P]),
     "kdmg_hierarchy_graphs": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "kdmg_hierarchy_counters": (_I, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_hierarchy_kernel_timing": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_server_create": (_I, [_I, _S, ctypes.POINTER(_P)]),
     "kdmg_server_add_config": (_I, [_P, _P, ctypes.POINTER(_I)]),
@@ -265,6 +267,12 @@ class Hierarchy:
         _check(_lib.kdmg_hierarchy_graphs(self.handle, -1 if enable is None else (1 if enable else 0),
                                           ctypes.byref(n)))
         return n.value
+
+    def counters(self):
+        """kdmg_hierarchy_counters: {"graph_replays": ..., "tail_entries": ...} so far."""
+        g, t = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(_lib.kdmg_hierarchy_counters(self.handle, ctypes.byref(g), ctypes.byref(t)))
+        return {"graph_replays": g.value, "tail_entries": t.value}
 
     def footprint(self, nrhs=1):
         b = _S()

@@ -135,8 +135,8 @@ def oracle_setup(dims, U, m, levels, seed):
     return OHierarchy(olat, U, m, params, psi0), psi0
 
 
-def gpu_params(K, levels):
-    return K.make_params(levels)
+def gpu_params(K, levels, **kw):
+    return K.make_params(levels, **kw)
 
 
 def assemble(op, dims):
@@ -381,6 +381,9 @@ def test_errors_are_reported(K):
     assert e.value.status == K.KDMG_EINVAL
     with pytest.raises(K.KdmgError) as e:
         K.Hierarchy(lat, 0.1, K.make_params([((4, 4), 8)], outer_stall=-1), [gaussian_vectors(8, 256, 1)])
+    for bad in (-1, 65):
+        with pytest.raises(K.KdmgError):
+            K.Hierarchy(lat, 0.1, K.make_params([((4, 4), 8)], coarse_tail=bad), [gaussian_vectors(8, 256, 1)])
     assert e.value.status == K.KDMG_EINVAL
     # iteration cap forced from the host: ENOCONV with the best iterate returned
     levels = [((4, 4), 8)]
@@ -425,7 +428,11 @@ def test_coarse_apply_all_shapes(K, nv, nrhs):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batched_solve_mfma_path(K, prec):
     """20 rhs (MFMA stencil tiles and fused CGNE) on 32^2, three levels with
-    n_vec 8 then 12: every rhs reaches 1e-10 and matches dense LU to 1e-8."""
+    n_vec 8 then 12: every rhs reaches 1e-10 and matches dense LU to 1e-8.
+    The coarsest CGNE calls continue as a 16-rhs tail problem once 16 or
+    fewer rhs remain active (the default coarse_tail); with the tail off the
+    same solve gives outer iteration counts within one and agrees to 1e-9 (the
+    tail runs its own launch shape, so rounding may differ)."""
     dims, beta, m = (32, 32), 6.0, 0.02
     U = field(dims, beta, seed=103, sweeps=100)
     levels = [((2, 2), 8), ((2, 2), 12)]
@@ -444,6 +451,16 @@ def test_batched_solve_mfma_path(K, prec):
         assert info[r]["converged"]
         assert np.linalg.norm(b[r] - D @ xs[r]) / np.linalg.norm(b[r]) <= 1e-10
         assert np.linalg.norm(xs[r] - xd[r]) / np.linalg.norm(xd[r]) < 1e-8
+    assert gh.counters()["tail_entries"] > 0
+    g0 = K.Hierarchy(lat, m, gpu_params(K, levels, coarse_tail=0), psi0)
+    x0 = torch.empty_like(x)
+    info0, _ = K.kdmg_solve(g0, dev(b), x0, nrhs, 1e-10, prec=p)
+    assert g0.counters()["tail_entries"] == 0
+    x0 = x0.cpu().numpy()
+    for r in range(nrhs):
+        assert info0[r]["converged"]
+        assert abs(info0[r]["outer_its"] - info[r]["outer_its"]) <= 1
+        assert np.linalg.norm(x0[r] - xs[r]) / np.linalg.norm(xs[r]) < 1e-9
 
 
 def test_hierarchy_at_mass_and_rebind(K):
