@@ -33,11 +33,12 @@ inline void trace_residuals(const Ctx& c, const KrylovState& k, int nrhs, int it
 
 // Device allocations for one Krylov state of `nrhs` right-hand sides.
 struct KrylovAlloc {
-  DevBuf sc, ints;
+  DevBuf sc, ints, rec;
   KrylovState k;
-  void init(int nrhs) {
+  // gcr_restart > 0: also the GCR cycle records for that restart length
+  void init(int nrhs, int gcr_restart = 0) {
     sc.alloc(sizeof(double) * S_COUNT * nrhs);
-    ints.alloc(sizeof(int) * 4 * nrhs);
+    ints.alloc(sizeof(int) * 7 * nrhs);
     KDMG_HIP(hipMemset(sc.p, 0, sc.bytes));
     KDMG_HIP(hipMemset(ints.p, 0, ints.bytes));
     k.sc = sc.as<double>();
@@ -45,6 +46,15 @@ struct KrylovAlloc {
     k.its = k.act + nrhs;
     k.calls = k.its + nrhs;
     k.tot = k.calls + nrhs;
+    k.m = k.tot + nrhs;
+    k.re = k.m + nrhs;
+    k.xu = k.re + nrhs;
+    if (gcr_restart > 0) {
+      rec.alloc(sizeof(double) * gcr_record_doubles(gcr_restart) * nrhs);
+      KDMG_HIP(hipMemset(rec.p, 0, rec.bytes));
+      k.R = gcr_restart;
+      k.rec = rec.as<double>();
+    }
   }
   // a state sharing another's flags (smoothers run under their caller's mask)
   KrylovState under(const int* act) const {
@@ -109,7 +119,14 @@ void mr_smooth(const Ctx& c, int nrhs, long n, Cx<T>* x, Cx<T>* r, Cx<T>* q, int
   }
 }
 
-// Flexible restarted GCR with classical Gram-Schmidt applied twice.
+// Flexible restarted GCR.  Each new direction w = op(M r) is orthogonalised
+// against the cycle's normalised directions by classical Gram-Schmidt, with a
+// second pass where the first one lost more than half the norm (OpOrtho).
+// Only w is projected: the preconditioned vectors z = M r stay as computed,
+// and x receives each cycle's correction at the cycle's end from the
+// triangular record of the projections (k_gcr_backsolve, OpXUpdate).  This
+// is the same iteration as projecting z alongside w and updating x every
+// step, with a third of the vector traffic.
 // Stops a rhs when ||r||^2 <= tol^2 * (ext ? ext[r] : ||b||^2), and with
 // stall > 0 also when ||r|| has not halved over the last `stall` iterations.
 template <class T, class OpF, class PrecF>
@@ -120,25 +137,41 @@ int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r
   start_solve(c, k, parent, nrhs);
   launch_map_reduce<1>(OpInit<T>{x, r, nullptr, b, n, k, tol * tol, ext}, n, nrhs, 1, c.rs, c.st);
   const long vs = (long)nrhs * n;
+  KDMG_CHECK(k.R >= restart && k.rec, KDMG_EINVAL, "GCR: cycle record too small");
   int its = 0;
   if (!any_active(c, k.act, nrhs)) return 0;
+  int ncol = 0;  // columns of the current cycle
+  auto end_cycle = [&]() {
+    if (ncol == 0) return;
+    hipLaunchKernelGGL(k_gcr_backsolve<T>, dim3(cdiv(nrhs, 64)), dim3(64), 0, c.st, k, nrhs);
+    KDMG_LAUNCH_CHECK();
+    launch_map(OpXUpdate<T>{x, Zb, vs, ncol, n, k}, n, nrhs, c.st);
+    ncol = 0;
+  };
   while (its < maxit) {
     for (int kk = 0; kk < restart && its < maxit; ++kk) {
       Cx<T>* z = Zb + kk * vs;
       Cx<T>* w = Wb + kk * vs;
       prec(z, r, k.act);
       op(w, z, (const Cx<T>*)nullptr, k.act);
-      if (kk > 0)
+      if (kk > 0) {
         for (int pass = 0; pass < 2; ++pass) {
-          launch_multidot<T>(Wb, vs, w, n, kk, nrhs, k, c.rs, c.st);
-          launch_map(OpMultiAxpy<T>{w, z, Wb, Zb, vs, kk, n, k}, n, nrhs, c.st);
+          launch_multidot<T>(Wb, vs, w, n, kk, nrhs, k, pass ? k.re : nullptr, c.rs, c.st);
+          launch_map_reduce<3>(OpOrtho<T>{w, Wb, r, vs, kk, n, k, pass}, n, nrhs, 1, c.rs, c.st);
         }
-      launch_map_reduce<3>(OpGCRred<T>{w, r, n, k}, n, nrhs, 1, c.rs, c.st);
-      launch_map_reduce<1>(OpGCRupd<T>{x, r, w, z, n, k, stall}, n, nrhs, 1, c.rs, c.st);
+      } else {
+        launch_map_reduce<3>(OpGCRred<T>{w, r, n, k}, n, nrhs, 1, c.rs, c.st);
+      }
+      launch_map_reduce<1>(OpGCRstep<T>{r, w, n, k, stall, kk}, n, nrhs, 1, c.rs, c.st);
+      ncol = kk + 1;
       ++its;
       if (trace) trace_residuals(c, k, nrhs, its, tol);
-      if (!any_active(c, k.act, nrhs)) return its;
+      if (!any_active(c, k.act, nrhs)) {
+        end_cycle();
+        return its;
+      }
     }
+    end_cycle();
     if (its >= maxit) break;
     op(r, x, b, k.act);  // r = b - op x (true residual at restart)
     launch_map_reduce<1>(OpResNorm<T>{r, n, k}, n, nrhs, 1, c.rs, c.st);

@@ -556,7 +556,7 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
   A(ws->Wo, c64s * half * P.outer_restart);
   A(ws->bnorm2, sizeof(double) * nrhs);
   A(ws->rnorm2, sizeof(double) * nrhs);
-  ws->kout.init(nrhs);
+  ws->kout.init(nrhs, P.outer_restart);
   ws->lv.resize(h.nlevels);
   for (int l = 0; l < h.nlevels; ++l) {
     LevelWS& L = ws->lv[l];
@@ -579,7 +579,7 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
       A(L.b, v);
       A(L.xs, v);
       A(L.rs, v);
-      L.ks.init(nrhs);
+      L.ks.init(nrhs, coarsest ? 0 : P.inter_restart);
       if (coarsest) {
         A(L.p, v);
         A(L.q, v);
