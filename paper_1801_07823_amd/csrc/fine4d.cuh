@@ -89,56 +89,73 @@ __global__ __launch_bounds__(256) void k4_hop(Cx<VT>* out, long so, const Cx<VT>
   if (!any) return;
   const long ib = (long)p * g.Nb2 * 16 + i;
   const int s = (int)(i & 15);
+  // Loads carry no branch (a load under a divergent branch is waited for at
+  // the branch's end, which serialises them): inactive rhs of the tile read
+  // row r0 and are never stored, and the hop direction a site takes is
+  // selected arithmetically.
+  long rr[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) rr[b] = on[b] ? r0 + b : r0;
   Cx<R> acc[RB][3];
 #pragma unroll
   for (int b = 0; b < RB; ++b)
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      acc[b][c] = mode >= 2 && on[b] ? m * ld<R>(in[(r0 + b) * si + ib * 3 + c]) : Cx<R>{0, 0};
+    for (int c = 0; c < 3; ++c) acc[b][c] = Cx<R>{0, 0};
+  // the mass term reads the site itself; mode is uniform over the launch, and
+  // in mode 0 the source may hold only the other parity
+  if (mode >= 2)
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[b][c] = m * ld<R>(in[rr[b] * si + ib * 3 + c]);
+  // mode 2 takes both directions of every mu; modes 0 and 3 one each:
+  // forward (dir 0) is intra-block iff x_mu is even, so C (mode 0) takes
+  // dir = 1 - bit and B (mode 3) takes dir = bit
+  const int ndir = mode == 2 ? 2 : 1;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const int bit = (s >> mu) & 1;
-#pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-      // forward (dir 0): intra-block iff x_mu even; backward: iff x_mu odd
-      if (!(mode == 2 || (mode == 0) == (bit == (dir == 0 ? 1 : 0)))) continue;
+    for (int t = 0; t < ndir; ++t) {
+      const int dir = mode == 2 ? t : (mode == 0 ? 1 - bit : bit);
       const long j = nb4[ib * 8 + 2 * mu + dir];
       const Cx<LT>* U = lk + ((dir == 0 ? ib : j) * 4 + mu) * 9;
       Cx<R> u[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) u[q] = ld<R>(U[q]);
+      Cx<R> v[RB][3];
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[b][c] = ld<R>(in[rr[b] * si + j * 3 + c]);
+      // forward: + U v ; backward: - U^dag v (U the link from the neighbour)
+      Cx<R> M[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[a * 3 + c] = dir == 0 ? u[a * 3 + c] : -conj(u[c * 3 + a]);
       const R e = (eps_in && chir4((int)(j & 15))) ? R(-1) : R(1);
 #pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        if (!on[b]) continue;
-        const Cx<VT>* src = in + (r0 + b) * si + j * 3;
-        Cx<R> v[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = e * ld<R>(src[c]);
+      for (int b = 0; b < RB; ++b)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            if (dir == 0)
-              acc[b][a] += u[a * 3 + c] * v[c];
-            else
-              acc[b][a] -= cmul_conj(u[c * 3 + a], v[c]);
-          }
-      }
+          for (int c = 0; c < 3; ++c) acc[b][a] += M[a * 3 + c] * (e * v[b][c]);
     }
   }
 #pragma unroll
-  for (int b = 0; b < RB; ++b) {
-    if (!on[b]) continue;
-    const int r = r0 + b;
+  for (int b = 0; b < RB; ++b)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       Cx<R> o = sgn * acc[b][c];
-      if (add) o += ld<R>(add[r * sa + ib * 3 + c]);
-      if (add2) o += c2 * ld<R>(add2[r * sa2 + ib * 3 + c]);
-      out[r * so + ib * 3 + c] = st<VT>(o);
+      if (add) o += ld<R>(add[rr[b] * sa + ib * 3 + c]);
+      if (add2) o += c2 * ld<R>(add2[rr[b] * sa2 + ib * 3 + c]);
+      acc[b][c] = o;
     }
-  }
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+    if (on[b])
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[(long)(r0 + b) * so + ib * 3 + c] = st<VT>(acc[b][c]);
 }
 
 // ------------------------------------------------------------------ block inverse
@@ -155,9 +172,12 @@ __global__ __launch_bounds__(64) void k4_binv(Cx<VT>* out, long so, const Cx<VT>
   __shared__ Cx<R> vin[B4_RB][48];
   const int b = blockIdx.x, p = p0 + blockIdx.z, r0 = blockIdx.y * B4_RB;
   const long blk = (long)p * g.Nb2 + b, base = blk * 48;
+  // loads carry no branch (inactive rhs read row r0, then count as zero)
   for (int e = threadIdx.x; e < B4_RB * 48; e += blockDim.x) {
     const int rb = e / 48, j = e - rb * 48, rr = r0 + rb;
-    vin[rb][j] = (rr < nrhs && is_active(act, rr)) ? ld<R>(in[rr * si + base + j]) : Cx<R>{0, 0};
+    const bool use = rr < nrhs && is_active(act, rr);
+    const Cx<R> x = ld<R>(in[(long)(use ? rr : r0) * si + base + j]);
+    vin[rb][j] = use ? x : Cx<R>{0, 0};
   }
   __syncthreads();
   const int i = threadIdx.x;
@@ -166,34 +186,46 @@ __global__ __launch_bounds__(64) void k4_binv(Cx<VT>* out, long so, const Cx<VT>
 #pragma unroll
   for (int rb = 0; rb < B4_RB; ++rb) acc[rb] = Cx<R>{0, 0};
   const Cx<BT>* col = Bv + blk * 48 * 48 + i;
-  for (int j = 0; j < 48; ++j) {
-    const Cx<R> bij = ld<R>(col[j * 48]);
+  // sixteen entries of the row loaded before any is used, so their loads are
+  // in flight together (one at a time, the row costs 48 memory latencies)
+  for (int j0 = 0; j0 < 48; j0 += 16) {
+    Cx<BT> raw[16];
 #pragma unroll
-    for (int rb = 0; rb < B4_RB; ++rb) acc[rb] += bij * vin[rb][j];
+    for (int u = 0; u < 16; ++u) raw[u] = col[(j0 + u) * 48];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const Cx<R> bij = ld<R>(raw[u]);
+#pragma unroll
+      for (int rb = 0; rb < B4_RB; ++rb) acc[rb] += bij * vin[rb][j0 + u];
+    }
   }
   const bool neg = eps_out && chir4(i / 3);
+  bool use[B4_RB];
 #pragma unroll
   for (int rb = 0; rb < B4_RB; ++rb) {
-    const int rr = r0 + rb;
-    if (rr >= nrhs || !is_active(act, rr)) continue;
-    Cx<R> o = neg ? -acc[rb] : acc[rb];
-    if (add) o += ld<R>(add[rr * sa + base + i]);
-    out[rr * so + base + i] = st<VT>(o);
+    use[rb] = r0 + rb < nrhs && is_active(act, r0 + rb);
+    if (neg) acc[rb] = -acc[rb];
   }
+  if (add)
+#pragma unroll
+    for (int rb = 0; rb < B4_RB; ++rb) acc[rb] += ld<R>(add[(long)(use[rb] ? r0 + rb : r0) * sa + base + i]);
+#pragma unroll
+  for (int rb = 0; rb < B4_RB; ++rb)
+    if (use[rb]) out[(long)(r0 + rb) * so + base + i] = st<VT>(acc[rb]);
 }
 
 
 // ------------------------------------------------------------------ transfers (level 0 <-> 1)
 
 // Restriction out[r][Z][c nv + i] = sum_{dof in (Z, c)} P[dof][i]^* in[r][dof]
-// (rows[(Z 2 + c) nrows + k] lists the group's fine dofs; with even_only the
-// dofs of odd blocks (dof >= half) count as zero).  Grid (2 nZ, nv / RI,
+// (rows[(Z 2 + c) nrows + k] lists the group's fine dofs in increasing order;
+// with even_only the dofs of odd blocks (dof >= half) count as zero).  Grid (2 nZ, nv / RI,
 // nrhs / RR); the workgroup's partial sums are combined in a fixed tree.
 constexpr int R4_RI = 4, R4_RR = 4;
 template <class R, class PT, class VI, class VO>
 __global__ __launch_bounds__(256) void k4_restrict(Cx<VO>* out, const Cx<VI>* in, long si, const Cx<PT>* __restrict__ P,
-                                                   const int* __restrict__ rows, int nrows, int nv, int even_only,
-                                                   long half, const int* act, int nrhs) {
+                                                   const int* __restrict__ rows, const int* __restrict__ neven,
+                                                   int nrows, int nv, int even_only, const int* act, int nrhs) {
   __shared__ Cx<R> red[4][R4_RI * R4_RR];
   const int gid = blockIdx.x, i0 = blockIdx.y * R4_RI, r0 = blockIdx.z * R4_RR;
   Cx<R> acc[R4_RR][R4_RI];
@@ -204,19 +236,33 @@ __global__ __launch_bounds__(256) void k4_restrict(Cx<VO>* out, const Cx<VI>* in
   bool on[R4_RR];
 #pragma unroll
   for (int a = 0; a < R4_RR; ++a) on[a] = r0 + a < nrhs && is_active(act, r0 + a);
-  for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
-    const long dof = rows[(long)gid * nrows + k];
-    if (even_only && dof >= half) continue;
-    Cx<R> pv[R4_RI];
+  // Loads carry no branch (a load under a divergent branch is waited for at
+  // the branch's end, which serialises them): indices are clamped to valid
+  // entries and unused values replaced by zero afterwards.
+  long ra[R4_RR];
 #pragma unroll
-    for (int q = 0; q < R4_RI; ++q) pv[q] = i0 + q < nv ? conj(ld<R>(P[dof * nv + i0 + q])) : Cx<R>{0, 0};
+  for (int a = 0; a < R4_RR; ++a) ra[a] = on[a] ? r0 + a : r0;
+  // The group's dofs are listed in increasing order, so with even_only the
+  // rows that count form a prefix, of length neven[gid] (dofs < half).
+  const int* grow = rows + (long)gid * nrows;
+  const int nuse = even_only ? neven[gid] : nrows;
+  for (int k = threadIdx.x; k < nuse; k += blockDim.x) {
+    const long dof = grow[k];
+    Cx<R> pv[R4_RI], v[R4_RR];
+#pragma unroll
+    for (int q = 0; q < R4_RI; ++q) {
+      const Cx<R> x = conj(ld<R>(P[dof * nv + min(i0 + q, nv - 1)]));
+      pv[q] = i0 + q < nv ? x : Cx<R>{0, 0};
+    }
 #pragma unroll
     for (int a = 0; a < R4_RR; ++a) {
-      if (!on[a]) continue;
-      const Cx<R> v = ld<R>(in[(long)(r0 + a) * si + dof]);
-#pragma unroll
-      for (int q = 0; q < R4_RI; ++q) acc[a][q] += pv[q] * v;
+      const Cx<R> x = ld<R>(in[ra[a] * si + dof]);
+      v[a] = on[a] ? x : Cx<R>{0, 0};
     }
+#pragma unroll
+    for (int a = 0; a < R4_RR; ++a)
+#pragma unroll
+      for (int q = 0; q < R4_RI; ++q) acc[a][q] += pv[q] * v[a];
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -243,39 +289,64 @@ __global__ __launch_bounds__(256) void k4_restrict(Cx<VO>* out, const Cx<VI>* in
 }
 
 // Prolongation out[r][dof] = [add +] sum_i P[dof][i] in[r][Z][c nv + i] for
-// dof < n_out, (Z, c) = group of the dof (dgrp[dof] = 2 Z + c).  One thread
-// per dof and a tile of R4_PB rhs (blockIdx.y): each P[dof][i] is read once
-// per tile; the coarse values are shared by the thousands of dofs of a group
-// and come from cache.
-constexpr int R4_PB = 4;
-template <class R, class PT, class VI, class VO>
-__global__ __launch_bounds__(256) void k4_prolong(Cx<VO>* out, long so, const Cx<VO>* add, long sa, const Cx<VI>* in,
-                                                  const Cx<PT>* __restrict__ P, const int* __restrict__ dgrp,
-                                                  int nv, long n_out, long ncoarse, const int* act, int nrhs) {
-  const long dof = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r0 = blockIdx.y * R4_PB;
-  if (dof >= n_out) return;
-  bool on[R4_PB];
-#pragma unroll
-  for (int b = 0; b < R4_PB; ++b) on[b] = r0 + b < nrhs && is_active(act, r0 + b);
+// dof < n_out, (Z, c) the group of the dof (dgrp[dof] = 2 Z + c).  A
+// workgroup of BS threads stages the P rows of its BS consecutive dofs (one
+// contiguous range of P) in LDS with coalesced loads, at an odd row stride
+// against bank conflicts; each thread then forms its dof for every rhs in
+// tiles of RR, so P is read from memory once.  The coarse values are shared
+// by the thousands of dofs of a group and come from cache.
+template <class R, class PT, class VI, class VO, int BS, int RR>
+__global__ __launch_bounds__(BS) void k4_prolong(Cx<VO>* out, long so, const Cx<VO>* add, long sa, const Cx<VI>* in,
+                                                 const Cx<PT>* __restrict__ P, const int* __restrict__ dgrp,
+                                                 int nv, long n_out, long ncoarse, const int* act, int nrhs) {
+  extern __shared__ __align__(16) unsigned char k4p_smem[];
+  Cx<R>* Ps = reinterpret_cast<Cx<R>*>(k4p_smem);
+  const int ps = nv | 1;
+  const long d0 = (long)blockIdx.x * BS;
+  const int cnt = (int)(n_out - d0 < BS ? n_out - d0 : BS);
+  const Cx<PT>* Pb = P + d0 * nv;
+  for (int e = threadIdx.x; e < cnt * nv; e += BS) {
+    const int rw = e / nv;
+    Ps[rw * ps + (e - rw * nv)] = ld<R>(Pb[e]);
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= cnt) return;
+  const long dof = d0 + t;
   const int gidx = dgrp[dof];
   const Cx<VI>* e = in + (long)(gidx >> 1) * 2 * nv + (gidx & 1) * nv;
-  Cx<R> acc[R4_PB];
+  const Cx<R>* pr = Ps + t * ps;
+  // Loads carry no branch (a load under a divergent branch is waited for at
+  // the branch's end, which serialises them): rows of rhs outside the tile or
+  // inactive read row r0 instead, and their results are never stored.
+  for (int r0 = 0; r0 < nrhs; r0 += RR) {
+    bool on[RR];
+    long rb[RR];
+    Cx<R> acc[RR];
 #pragma unroll
-  for (int b = 0; b < R4_PB; ++b) acc[b] = Cx<R>{0, 0};
-  for (int i = 0; i < nv; ++i) {
-    const Cx<R> pv = ld<R>(P[dof * nv + i]);
+    for (int b = 0; b < RR; ++b) {
+      on[b] = r0 + b < nrhs && is_active(act, r0 + b);
+      rb[b] = on[b] ? r0 + b : r0;
+      acc[b] = Cx<R>{0, 0};
+    }
+    for (int i = 0; i < nv; ++i) {
+      const Cx<R> pv = pr[i];
+      Cx<R> ev[RR];
 #pragma unroll
-    for (int b = 0; b < R4_PB; ++b)
-      if (on[b]) acc[b] += pv * ld<R>(e[(long)(r0 + b) * ncoarse + i]);
-  }
+      for (int b = 0; b < RR; ++b) ev[b] = ld<R>(e[rb[b] * ncoarse + i]);
 #pragma unroll
-  for (int b = 0; b < R4_PB; ++b) {
-    if (!on[b]) continue;
-    const long r = r0 + b;
-    Cx<R> o = acc[b];
-    if (add) o += ld<R>(add[r * sa + dof]);
-    out[r * so + dof] = st<VO>(o);
+      for (int b = 0; b < RR; ++b) acc[b] += pv * ev[b];
+    }
+    if (add) {
+      Cx<R> av[RR];
+#pragma unroll
+      for (int b = 0; b < RR; ++b) av[b] = ld<R>(add[rb[b] * sa + dof]);
+#pragma unroll
+      for (int b = 0; b < RR; ++b) acc[b] += av[b];
+    }
+#pragma unroll
+    for (int b = 0; b < RR; ++b)
+      if (on[b]) out[(long)(r0 + b) * so + dof] = st<VO>(acc[b]);
   }
 }
 

@@ -262,7 +262,7 @@ void build_level1_4d(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int re
   const long f = 2 * g.half, V = lat.volume, nd = lat.ndof;
   T.nfine = f;
   // (aggregate, chirality) groups, dofs in increasing block-layout order
-  std::vector<int> rows((size_t)2 * T.nZ * T.nrows4), dgrp(f), fill(2 * T.nZ, 0);
+  std::vector<int> rows((size_t)2 * T.nZ * T.nrows4), dgrp(f), fill(2 * T.nZ, 0), neven(2 * T.nZ, 0);
   int Lc[4];
   for (int mu = 0; mu < 4; ++mu) Lc[mu] = g.NB[mu] / T.agg4[mu];
   for (int p = 0; p < 2; ++p)
@@ -280,11 +280,14 @@ void build_level1_4d(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int re
           const int gid = 2 * Z + chir4(s);
           rows[(size_t)gid * T.nrows4 + fill[gid]++] = (int)dof;
           dgrp[dof] = gid;
+          if (p == 0) ++neven[gid];  // parity-0 blocks come first: dof < half
         }
     }
   for (int q = 0; q < 2 * T.nZ; ++q) KDMG_CHECK(fill[q] == T.nrows4, KDMG_EINVAL, "aggregate group size mismatch");
   T.rows4.alloc(sizeof(int) * rows.size());
   T.dgrp4.alloc(sizeof(int) * dgrp.size());
+  T.neven4.alloc(sizeof(int) * neven.size());
+  KDMG_HIP(hipMemcpy(T.neven4.p, neven.data(), T.neven4.bytes, hipMemcpyHostToDevice));
   KDMG_HIP(hipMemcpy(T.rows4.p, rows.data(), T.rows4.bytes, hipMemcpyHostToDevice));
   KDMG_HIP(hipMemcpy(T.dgrp4.p, dgrp.data(), T.dgrp4.bytes, hipMemcpyHostToDevice));
   // starting vectors: natural order -> block layout

@@ -6,6 +6,7 @@
 #include <memory>
 #include <mutex>
 #include <utility>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -137,8 +138,18 @@ template <class R, class LT>
 void launch4_hop(Cx<R>* out, long so, const Cx<R>* in, long si, const Cx<R>* add, long sa, const Cx<R>* add2,
                  long sa2, double c2, double sgn, const Cx<LT>* lk, const int* nb4, const Geo4& g, int p0, int npar,
                  double m, int mode, int eps_in, const int* act, int nrhs, hipStream_t st) {
-  // a tile of 4 rhs per thread (links and neighbour indices read once per
-  // tile) from 4 rhs on
+  // a tile of rhs per thread (links and neighbour indices read once per
+  // tile): 8 in FP32 from 8 rhs on, else 4 from 4 rhs on (an FP64 tile of 8
+  // exceeds the register budget)
+  if constexpr (sizeof(R) == 4) {
+    if (nrhs >= 8) {
+      hipLaunchKernelGGL((k4_hop<R, LT, R, 8>), dim3(cdiv(16L * g.Nb2, 256), cdiv(nrhs, 8), npar), dim3(256), 0,
+                         st, out, so, in, si, add, sa, add2, sa2, (R)c2, (R)sgn, lk, nb4, g, p0, (R)m, mode, eps_in,
+                         act, nrhs);
+      KDMG_LAUNCH_CHECK();
+      return;
+    }
+  }
   if (nrhs >= 4)
     hipLaunchKernelGGL((k4_hop<R, LT, R, 4>), dim3(cdiv(16L * g.Nb2, 256), cdiv(nrhs, 4), npar), dim3(256), 0, st,
                        out, so, in, si, add, sa, add2, sa2, (R)c2, (R)sgn, lk, nb4, g, p0, (R)m, mode, eps_in, act,
@@ -245,11 +256,12 @@ struct Transfer {
   int agg4[4] = {1, 1, 1, 1};
   int nrows4 = 0;
   DevBuf rows4, dgrp4;
+  DevBuf neven4;                 // rows of each group with dof < half (a prefix of rows4)
   DevBuf relaxed;                // relaxed null vectors, FP64, internal layout [nv][n_k]
   long nfine = 0;                // entries per null vector (internal layout)
   size_t bytes() const {
     return P64.bytes + P16.bytes + children.bytes + parent.bytes + gdir.bytes + relaxed.bytes + rows4.bytes +
-           dgrp4.bytes;
+           neven4.bytes + dgrp4.bytes;
   }
 };
 
@@ -479,7 +491,7 @@ void transfer_restrict(const Transfer& T, const kdmg_lattice& lat, const CoarseL
   if (T.k == 0 && lat.nd == 4) {
     dim3 grid(2 * T.nZ, cdiv(T.nv, R4_RI), cdiv(nrhs, R4_RR));
     hipLaunchKernelGGL((k4_restrict<R, PT, VI, VO>), grid, dim3(256), 0, st, out, in, si, P, T.rows4.as<int>(),
-                       T.nrows4, T.nv, even_only, lat.half, act, nrhs);
+                       T.neven4.as<int>(), T.nrows4, T.nv, even_only, act, nrhs);
   } else if (T.k == 0) {
     // rhs tile: up to 32, with the staged P rows and rhs values within the LDS
     const int nd = 4 * T.a2.a0 * T.a2.a1;
@@ -517,9 +529,12 @@ void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, l
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
   if (T.k == 0 && lat.nd == 4) {
     const long n_out = npar == 1 ? lat.half : 2 * lat.half;
-    dim3 grid(cdiv(n_out, 256), cdiv(nrhs, R4_PB));
-    hipLaunchKernelGGL((k4_prolong<R, PT, VI, VO>), grid, dim3(256), 0, st, out, so, add, sa, in, P,
-                       T.dgrp4.as<int>(), T.nv, n_out, (long)T.nZ * 2 * T.nv, act, nrhs);
+    constexpr int BS = sizeof(R) == 8 ? 128 : 256;
+    const size_t bytes = (size_t)BS * (T.nv | 1) * sizeof(Cx<R>);
+    auto fn = k4_prolong<R, PT, VI, VO, BS, 8>;
+    ensure_smem((const void*)fn, bytes);
+    hipLaunchKernelGGL(fn, dim3(cdiv(n_out, BS)), dim3(BS), bytes, st, out, so, add, sa, in, P, T.dgrp4.as<int>(),
+                       T.nv, n_out, (long)T.nZ * 2 * T.nv, act, nrhs);
   } else if (T.k == 0) {
     const int nd = 4 * T.a2.a0 * T.a2.a1;
     int RB = nrhs < 32 ? nrhs : 32;

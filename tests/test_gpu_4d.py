@@ -48,7 +48,7 @@ def relerr(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("nrhs", [1, 3, 5])
+@pytest.mark.parametrize("nrhs", [1, 3, 5, 11])
 def test_apply_D_4d(K, field, nrhs):
     olat = OLattice(DIMS, ncolor=3)
     m = 0.1
@@ -65,9 +65,10 @@ def test_apply_D_4d(K, field, nrhs):
     assert np.all(err < 3e-3)
 
 
-@pytest.mark.parametrize("m,nr", [(0.1, 2), (0.5, 2), (0.1, 5)])
+@pytest.mark.parametrize("m,nr", [(0.1, 2), (0.5, 2), (0.1, 5), (0.1, 11)])
 def test_fine_operators_4d(K, field, m, nr):
-    """nr = 5 takes the hop kernel's 4-rhs tile with a ragged tail."""
+    """nr = 5 takes the hop kernel's 4-rhs tile with a ragged tail; nr = 11 the
+    8-rhs tile of the FP32 hop (apply_D mixed) and the 4-rhs FP64 tiles."""
     olat = OLattice(DIMS, ncolor=3)
     kd = KDOperator(olat, field, m)
     lat = K.Lattice(DIMS, field)
@@ -149,18 +150,19 @@ def test_hierarchy_4d_from_given_vectors(K, field):
     assert dims_c == (2, 2, 2, 2)
     Ag = assemble4(gh.coarse_op(1), dims_c)
     assert relerr(Ag, oh.ops[1].toarray()) < 1e-10
-    # level-0 transfers with 5 rhs (the prolongation's 4-rhs tile and a
-    # ragged tail): FP64 against the oracle's P to 1e-10 (P itself agrees to
-    # that), the FP16-P mixed form to 2e-3 per rhs
+    # level-0 transfers with 5 and 11 rhs (rhs tiles of 4 and 8 with ragged
+    # tails): FP64 against the oracle's P to 1e-10 (P itself agrees to that),
+    # the FP16-P mixed form to 2e-3 per rhs
     P = oh.P[0]
     nf, nc = P.shape
-    v = gaussian_vectors(5, nf, 55, tag=0)
-    e = gaussian_vectors(5, nc, 56, tag=0)
-    for prec, dt, tol in ((K.KDMG_FP64, torch.complex128, None), (K.KDMG_MIXED, torch.complex64, 2e-3)):
-        rc = torch.empty((5, nc), dtype=dt, device="cuda")
-        K.kdmg_restrict(gh, 0, dev(v, dt), rc, 5, prec=prec)
-        pf = torch.empty((5, nf), dtype=dt, device="cuda")
-        K.kdmg_prolong(gh, 0, dev(e, dt), pf, 5, prec=prec)
+    for nr, prec, dt, tol in ((5, K.KDMG_FP64, torch.complex128, None), (5, K.KDMG_MIXED, torch.complex64, 2e-3),
+                              (11, K.KDMG_FP64, torch.complex128, None), (11, K.KDMG_MIXED, torch.complex64, 2e-3)):
+        v = gaussian_vectors(nr, nf, 55, tag=0)
+        e = gaussian_vectors(nr, nc, 56, tag=0)
+        rc = torch.empty((nr, nc), dtype=dt, device="cuda")
+        K.kdmg_restrict(gh, 0, dev(v, dt), rc, nr, prec=prec)
+        pf = torch.empty((nr, nf), dtype=dt, device="cuda")
+        K.kdmg_prolong(gh, 0, dev(e, dt), pf, nr, prec=prec)
         for got, ref in ((rc.cpu().numpy(), (P.conj().T @ v.T).T), (pf.cpu().numpy(), (P @ e.T).T)):
             if tol is None:
                 assert relerr(got, ref) < 1e-10
