@@ -112,12 +112,25 @@ __global__ __launch_bounds__(256) void k4_hop(Cx<VT>* out, long so, const Cx<VT>
   // forward (dir 0) is intra-block iff x_mu is even, so C (mode 0) takes
   // dir = 1 - bit and B (mode 3) takes dir = bit
   const int ndir = mode == 2 ? 2 : 1;
+  // all neighbour indices first, so their latency is paid once
+  int jn[4][2];
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const int bit = (s >> mu) & 1;
-    for (int t = 0; t < ndir; ++t) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
       const int dir = mode == 2 ? t : (mode == 0 ? 1 - bit : bit);
-      const long j = nb4[ib * 8 + 2 * mu + dir];
+      jn[mu][t] = t < ndir ? nb4[ib * 8 + 2 * mu + dir] : 0;
+    }
+  }
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const int bit = (s >> mu) & 1;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t >= ndir) break;
+      const int dir = mode == 2 ? t : (mode == 0 ? 1 - bit : bit);
+      const long j = jn[mu][t];
       const Cx<LT>* U = lk + ((dir == 0 ? ib : j) * 4 + mu) * 9;
       Cx<R> u[9];
 #pragma unroll
