@@ -205,6 +205,20 @@ kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void* in, void* 
 kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* out,
                          int nrhs, kdmg_prec prec, void* stream);
 
+/* Conjugate gradient on the site even/odd Schur system, the solver the paper
+   compares KD-MG against (Sec. 1 and 2; Sec. 5): with D = m + H,
+   (m^2 - H_eo H_oe) x_e = m b_e - H_eo b_o (Hermitian positive definite),
+   then x_o = (b_o - H_oe x_e) / m.  A rhs stops when ||b - D x|| <= tol ||b||,
+   which the even CG residual gives exactly (||b - D x|| = ||r_e|| / m), or
+   after maxit iterations.  2D lattices with even extents; FP64.  b, x:
+   complex128 device vectors [nrhs][volume] in natural site order (x is
+   overwritten).  its_host: nrhs iteration counts (may be NULL).  Allocates
+   its work space per call and synchronises `stream`.  Returns KDMG_ENOCONV
+   (x and its_host still written) if a rhs missed tol within maxit;
+   KDMG_EUNSUPPORTED for a 4D lattice, KDMG_EINVAL for bad arguments. */
+kdmg_status kdmg_solve_cg_eo(const kdmg_lattice* lat, double mass, const void* b, void* x, int nrhs,
+                             double tol, int maxit, int* its_host, void* stream);
+
 /* Solves D x = b for nrhs right-hand sides sharing the hierarchy (Sec. 4):
    FGCR on the Schur system until ||b - D x|| <= tol ||b|| per rhs, then
    reconstruction and an FP64 true-residual check.  b, x: complex128 device

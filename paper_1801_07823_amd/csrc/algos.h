@@ -91,12 +91,13 @@ inline void start_solve(const Ctx& c, const KrylovState& k, const int* parent, i
   launch_map(OpStart{k, parent}, 1, nrhs, c.st);
 }
 
-// CG on a Hermitian positive operator (null-vector relaxation).
+// CG on a Hermitian positive operator (null-vector relaxation, the even/odd
+// comparison solver).  Stops a rhs when ||r||^2 <= tol^2 (ext ? ext[r] : ||b||^2).
 template <class T, class NormalF>
 int cg_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* p, Cx<T>* q,
-             double tol, int maxit, const KrylovState& k, NormalF normal, int poll) {
+             double tol, int maxit, const KrylovState& k, NormalF normal, int poll, const double* ext = nullptr) {
   start_solve(c, k, nullptr, nrhs);
-  launch_map_reduce<1>(OpInit<T>{x, r, p, b, n, k, tol * tol, nullptr}, n, nrhs, 1, c.rs, c.st);
+  launch_map_reduce<1>(OpInit<T>{x, r, p, b, n, k, tol * tol, ext}, n, nrhs, 1, c.rs, c.st);
   int it = 0;
   for (; it < maxit; ++it) {
     normal(q, p, k.act);

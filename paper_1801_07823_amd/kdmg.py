@@ -84,6 +84,7 @@ _SIGS = {
     "kdmg_hierarchy_set_mass": (_I, [_P, _P, _D, _P]),
     "kdmg_hierarchy_graphs": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_hierarchy_counters": (_I, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
+    "kdmg_solve_cg_eo": (_I, [_P, _D, _P, _P, _I, _D, _I, ctypes.POINTER(_I), _P]),
     "kdmg_hierarchy_kernel_timing": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_server_create": (_I, [_I, _S, ctypes.POINTER(_P)]),
     "kdmg_server_add_config": (_I, [_P, _P, ctypes.POINTER(_I)]),
@@ -324,6 +325,15 @@ def kdmg_solve(h, b, x, nrhs, tol=1e-10, prec=KDMG_FP64, stream=None, raise_on_n
     if st != KDMG_OK and (st != KDMG_ENOCONV or raise_on_noconv):
         _check(st)
     return [i.as_dict() for i in info], st
+
+
+def kdmg_solve_cg_eo(lat, mass, b, x, nrhs, tol=1e-10, maxit=200000, stream=None, raise_on_noconv=True):
+    """CG on the site even/odd Schur system (2D, FP64); returns the iteration count per rhs."""
+    its = (_I * nrhs)()
+    st = _lib.kdmg_solve_cg_eo(lat.handle, mass, _ptr(b), _ptr(x), nrhs, tol, maxit, its, _stream(stream))
+    if st != KDMG_OK and (st != KDMG_ENOCONV or raise_on_noconv):
+        _check(st)
+    return list(its)
 
 
 class Server:
