@@ -445,6 +445,51 @@ def su3_main(a):
 XF_DIMS, XF_NV, XF_NRHS = (2048, 2048), 16, 32
 
 
+def mass_scan_main(a):
+    """KD-MG (mixed, outer FGCR capped at --scan-outer) and CG on the even/odd
+    system on the benchmark field and rhs at other masses: one line per solver
+    and mass, printed as each finishes; the hierarchy is set up at each mass."""
+    import numpy as np
+    import torch
+    from paper_1801_07823_amd import kdmg
+    from synth import gaussian_vectors
+    kdmg.kdmg_init(0)
+    U, _ = gauge_field()
+    lat = kdmg.Lattice(DIMS, U)
+    V = lat.volume
+    psi0, seed = starts(V)
+    b = torch.from_numpy(gaussian_vectors(NRHS, V, seed, tag=0)).to("cuda")
+    x = torch.empty_like(b)
+    y = torch.empty_like(b)
+
+    def resid(m):
+        kdmg.kdmg_apply_D(lat, m, x, y, NRHS)
+        return float(((b - y).norm(dim=1) / b.norm(dim=1)).max())
+
+    for m in a.mass_scan:
+        p = kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=COARSE_MAXIT, outer_maxit=a.scan_outer)
+        h = kdmg.Hierarchy(lat, m, p, psi0)
+        kdmg.kdmg_solve(h, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)  # tunes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info, st = kdmg.kdmg_solve(h, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        print(json.dumps({"mass": m, "solver": "kd-mg mixed", "seconds": t, "solves_per_s": NRHS / t,
+                          "converged": st == kdmg.KDMG_OK, "outer_max": max(i["outer_its"] for i in info),
+                          "coarsest_avg": float(np.mean([i["level_avg_its"][1] for i in info])),
+                          "max_true_rel_resid": resid(m)}), flush=True)
+        del h
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = kdmg.kdmg_solve_cg_eo(lat, m, b, x, NRHS, 1e-10, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        print(json.dumps({"mass": m, "solver": "cg-eo fp64", "seconds": t, "solves_per_s": NRHS / t,
+                          "iterations_max": max(its), "max_true_rel_resid": resid(m)}), flush=True)
+    return 0
+
+
 def transfer_main(a):
     """Level-0 restriction and prolongation in the mixed form (FP16-stored P,
     FP32 vectors), 32 rhs per call as in the solve, on a 2048^2 lattice whose P (268 MB) and
@@ -506,6 +551,9 @@ def main():
     ap.add_argument("--cpu-child", type=int, default=None)
     ap.add_argument("--serve", action="store_true", help="served-stream measurement instead of the bench line")
     ap.add_argument("--su3", action="store_true", help="4D SU(3) 24^4 measurement instead of the bench line")
+    ap.add_argument("--mass-scan", type=float, nargs="+", default=None,
+                    help="KD-MG and CG-eo on the benchmark field and rhs at these masses (one JSON line each)")
+    ap.add_argument("--scan-outer", type=int, default=60, help="outer FGCR cap of the mass scan")
     ap.add_argument("--transfer-profile", action="store_true",
                     help="2048^2 mixed restriction / prolongation calls for a kernel trace; prints no metric")
     ap.add_argument("--serve-configs", type=int, default=8)
@@ -532,6 +580,8 @@ def main():
         return su3_main(a)
     if a.transfer_profile:
         return transfer_main(a)
+    if a.mass_scan:
+        return mass_scan_main(a)
     cpu = None if (a.no_cpu or a.kernel_profile) else start_cpu_leg(a.cpu_its)
 
     import numpy as np
