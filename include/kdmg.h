@@ -97,8 +97,9 @@ typedef struct {
   int coarse_tail;            /* 16 (default): once this many or fewer rhs of a
                                  wider batched coarsest CGNE are still active,
                                  they continue as a narrower problem with the
-                                 launch shape tuned for that width (per-rhs
-                                 arithmetic unchanged); 0: off.  0..64 */
+                                 launch shape tuned for that width (the same
+                                 iteration per rhs; rounding may differ with
+                                 the shape); 0: off.  0..64 */
 } kdmg_mg_params;
 
 /* Per right-hand side result of kdmg_solve. */
@@ -208,9 +209,12 @@ kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* o
 /* Conjugate gradient on the site even/odd Schur system, the solver the paper
    compares KD-MG against (Sec. 1 and 2; Sec. 5): with D = m + H,
    (m^2 - H_eo H_oe) x_e = m b_e - H_eo b_o (Hermitian positive definite),
-   then x_o = (b_o - H_oe x_e) / m.  A rhs stops when ||b - D x|| <= tol ||b||,
-   which the even CG residual gives exactly (||b - D x|| = ||r_e|| / m), or
-   after maxit iterations.  2D lattices with even extents; FP64.  b, x:
+   then x_o = (b_o - H_oe x_e) / m.  The target is ||b - D x|| <= tol ||b||,
+   i.e. ||r_e|| <= tol m ||b|| for the true even residual r_e.  CG stops a
+   rhs on its recursive residual; the true one is then recomputed, and rhs
+   still above the target run further CG passes on the residual system
+   (at most 8 passes and maxit iterations in all).  2D lattices with even
+   extents; FP64.  b, x:
    complex128 device vectors [nrhs][volume] in natural site order (x is
    overwritten).  its_host: nrhs iteration counts (may be NULL).  Allocates
    its work space per call and synchronises `stream`.  Returns KDMG_ENOCONV
