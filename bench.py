@@ -652,7 +652,7 @@ def main():
     kdmg.kdmg_solve_cg_eo(lat, MASS, b, xcg, NRHS, 1e-10, maxit=16, raise_on_noconv=False)  # loads the kernels
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    its_cg = kdmg.kdmg_solve_cg_eo(lat, MASS, b, xcg, NRHS, 1e-10)
+    its_cg = kdmg.kdmg_solve_cg_eo(lat, MASS, b, xcg, NRHS, 1e-10, raise_on_noconv=False)
     torch.cuda.synchronize()
     t_cg = time.perf_counter() - t0
     ycg = torch.empty_like(b)
@@ -660,7 +660,7 @@ def main():
     res_cg = float(((b - ycg).norm(dim=1) / b.norm(dim=1)).max())
     cg_eo = {"solves_per_s": NRHS / t_cg, "unit": "solves/s", "rhs": NRHS, "seconds": t_cg,
              "iterations_max": max(its_cg), "iterations_mean": float(np.mean(its_cg)),
-             "max_true_rel_resid": res_cg, "kd_mg_over_cg_eo": value * t_cg / NRHS}
+             "max_true_rel_resid": res_cg, "converged": res_cg <= 1e-10, "kd_mg_over_cg_eo": value * t_cg / NRHS}
     print("cg-eo: %.2f s, %d iterations (max), true residual %.2e" % (t_cg, max(its_cg), res_cg),
           file=sys.stderr, flush=True)
 
