@@ -446,7 +446,8 @@ XF_DIMS, XF_NV, XF_NRHS = (2048, 2048), 16, 32
 
 
 def mass_scan_main(a):
-    """KD-MG (mixed, outer FGCR capped at --scan-outer) and CG on the even/odd
+    """KD-MG (mixed, outer FGCR capped at --scan-outer, coarsest CGNE at
+    --scan-cap) and CG on the even/odd
     system on the benchmark field and rhs at other masses: one line per solver
     and mass, printed as each finishes; the hierarchy is set up at each mass."""
     import numpy as np
@@ -467,7 +468,7 @@ def mass_scan_main(a):
         return float(((b - y).norm(dim=1) / b.norm(dim=1)).max())
 
     for m in a.mass_scan:
-        p = kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=COARSE_MAXIT, outer_maxit=a.scan_outer)
+        p = kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=a.scan_cap, outer_maxit=a.scan_outer)
         h = kdmg.Hierarchy(lat, m, p, psi0)
         kdmg.kdmg_solve(h, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)  # tunes
         torch.cuda.synchronize()
@@ -554,6 +555,7 @@ def main():
     ap.add_argument("--mass-scan", type=float, nargs="+", default=None,
                     help="KD-MG and CG-eo on the benchmark field and rhs at these masses (one JSON line each)")
     ap.add_argument("--scan-outer", type=int, default=60, help="outer FGCR cap of the mass scan")
+    ap.add_argument("--scan-cap", type=int, default=COARSE_MAXIT, help="coarsest CGNE cap of the mass scan")
     ap.add_argument("--transfer-profile", action="store_true",
                     help="2048^2 mixed restriction / prolongation calls for a kernel trace; prints no metric")
     ap.add_argument("--serve-configs", type=int, default=8)
