@@ -257,3 +257,25 @@ def test_oracle_4d_su3_hierarchy_and_solve(h4):
     xd = dense_solve(h.lat, U, 0.1, b)
     assert info["converged"] and info["true_rel_resid"] <= 1e-10
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-8
+
+
+def test_outer_iterations_flat_in_mass():
+    """Sec. 5: the KD-MG outer iteration count hardly changes as the mass
+    falls, here tenfold (m = 0.001 -> 0.0001) on a 64^2 beta = 10 field with
+    the three-level Table 1 shape (4x4 then 2x2 aggregates, n_vec 16 then 12,
+    coarsest CGNE capped at 1024).  Both solves reach 1e-10, with counts
+    within 3 of each other and at most 18 (measured: 13 and 15)."""
+    L = 64
+    U, _ = u1_heatbath((L, L), 10.0, 200, 1)
+    lat = Lattice((L, L))
+    psi0 = [gaussian_vectors(16, lat.volume, 2, tag=1),
+            gaussian_vectors(12, (L // 8) ** 2 * 32, 2, tag=2)]
+    b = gaussian_vectors(1, lat.volume, 3, tag=0)[0]
+    counts = []
+    for m in (0.001, 0.0001):
+        params = MGParams(levels=[LevelParams((4, 4), 16), LevelParams((2, 2), 12)], outer_maxit=40,
+                          coarse_maxit=1024)
+        _, info = Solver(Hierarchy(lat, U, m, params, psi0)).solve(b, 1e-10)
+        assert info["converged"], (m, info)
+        counts.append(info["outer_its"])
+    assert max(counts) <= 18 and abs(counts[1] - counts[0]) <= 3, counts
