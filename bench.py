@@ -22,10 +22,15 @@ DIMS = (256, 256)
 BETA, MASS, NRHS, NV = 10.0, 0.001, 32, 16
 NV2 = int(os.environ.get("KDMG_BENCH_NV2", "12"))
 COARSE_MAXIT = 1024
+# coarsest-level solve of the headline: 1 = exact, through the explicit FP64
+# inverse of the coarsest operator (kdmg_mg_params.coarse_solver); the
+# Table 1 form (CGNE tol 0.2, here capped at 1024) is measured beside it
+COARSE_SOLVER = 1
 WORKLOAD = {"workload": "2D U(1) staggered KD-MG solve", "lattice": [256, 256], "beta": 10.0,
             "mass": 0.001, "nrhs": 32, "levels": "3: 2x2 KD blocks; 4x4 aggregates n_vec 16 "
             "(32x32 complex coarse blocks); 2x2 aggregates n_vec %d" % NV2, "tol": 1e-10,
-            "coarsest": "CGNE tol 0.2, at most 1024 iterations",
+            "coarsest": "exact: product with the explicit FP64 inverse of the 6144-dof coarsest operator "
+                        "(option beside Table 1's CGNE tol 0.2, measured in cgne_coarsest)",
             "gauge": "quenched heatbath, 200 sweeps"}
 # HBM traffic of the dominant kernels from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE) over `bench.py --kernel-profile`, in bytes
@@ -57,47 +62,87 @@ def starts(volume):
 
 # ------------------------------------------------------------------ CPU leg
 
-def cpu_baseline_child(budget_its):
-    """Runs in a subprocess that never touches the GPU: the oracle builds its
-    own hierarchy for the same workload, then runs its FGCR on rhs 0 for
-    `budget_its` outer iterations; the rate is extrapolated to a full solve
-    from the residual reduction reached (FGCR converges geometrically)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_CPU = {}
+
+
+def _cpu_task(task):
+    """One oracle task in a forked worker: ("kdmg", q) solves rhs q with the
+    parent's hierarchy; ("cg_eo", q) runs CG on the even/odd system."""
+    from oracle.mg import Solver
+    from oracle.exact import cg_eo
+    kind, q = task
+    b = _CPU["b"][q]
+    t0 = time.perf_counter()
+    if kind == "kdmg":
+        _, info = Solver(_CPU["h"]).solve(b, 1e-10)
+        return kind, q, time.perf_counter() - t0, info["outer_its"], info["true_rel_resid"]
+    x, its = cg_eo(_CPU["olat"], _CPU["U"], MASS, b, tol=1e-13)
+    return kind, q, time.perf_counter() - t0, its, None
+
+
+def cpu_baseline_child(nproc):
+    """Runs in a subprocess that never touches the GPU.  The oracle builds its
+    own hierarchy for the benchmark workload (same field, starts and
+    parameters, with its dense-LU coarsest solve like the GPU headline; setup
+    reported and excluded like the GPU's), then a pool of forked workers, one
+    BLAS thread each, solves rhs 0 .. P-1 to 1e-10 concurrently, plus one
+    oracle CG on the even/odd system for rhs 0.  value = P solves / wall time
+    of the pool: the host's whole throughput on independent rhs."""
+    import multiprocessing as mp
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from synth import gaussian_vectors
     from oracle.staggered import Lattice
-    from oracle.mg import MGParams, LevelParams, Hierarchy, Solver
+    from oracle.mg import MGParams, LevelParams, Hierarchy
+    avail = len(os.sched_getaffinity(0))
+    P = nproc if nproc > 0 else max(1, min(NRHS, avail - 2, 14))
     U, _ = gauge_field()
     lat = Lattice(DIMS)
     psi0, seed = starts(lat.volume)
     t0 = time.perf_counter()
-    h = Hierarchy(lat, U, MASS, MGParams(levels=[LevelParams((4, 4), NV), LevelParams((2, 2), NV2)],
-                                         outer_maxit=budget_its, coarse_maxit=COARSE_MAXIT), psi0)
+    with threadpool_limits(limits=max(1, avail - 1)):
+        h = Hierarchy(lat, U, MASS, MGParams(levels=[LevelParams((4, 4), NV), LevelParams((2, 2), NV2)],
+                                             coarse_maxit=COARSE_MAXIT, coarse_exact=COARSE_SOLVER == 1), psi0)
     t_setup = time.perf_counter() - t0
-    b = gaussian_vectors(NRHS, lat.volume, seed, tag=0)[0]
-    t0 = time.perf_counter()
-    _, info = Solver(h).solve(b, 1e-10)
-    t_solve = time.perf_counter() - t0
-    its = info["outer_its"]
-    res = info["true_rel_resid"]
-    est_its = its if res <= 1e-10 else its * math.log(1e-10) / math.log(res)
-    per_solve = t_solve / its * est_its
-    print(json.dumps({"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                      "sample": "rhs 0 of 32 at 256^2; oracle hierarchy built first (setup %.1f s, "
-                                "excluded like the GPU setup); %d outer FGCR iterations timed "
-                                "(%.1f s, relative residual %.2e), rate extrapolated to 1e-10 "
-                                "assuming geometric FGCR convergence (%.1f iterations)"
-                                % (t_setup, its, t_solve, res, est_its),
-                      "setup_s": t_setup, "seconds_timed": t_solve}))
+    _CPU.update(h=h, b=gaussian_vectors(NRHS, lat.volume, seed, tag=0), olat=lat, U=U)
+    tasks = [("kdmg", q) for q in range(P)] + [("cg_eo", 0)]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(P + 1) as pool:
+            res = pool.map(_cpu_task, tasks, chunksize=1)
+        wall = time.perf_counter() - t0
+    kd = [r for r in res if r[0] == "kdmg"]
+    cg = [r for r in res if r[0] == "cg_eo"][0]
+    print(json.dumps({"value": P / wall, "unit": "solves/s", "cores": P + 1, "kind": "oracle",
+                      "sample": "oracle KD-MG solves of rhs 0..%d of the 32 to 1e-10 on %d worker processes "
+                                "(one BLAS thread each) plus one oracle CG-eo of rhs 0 on another, all at "
+                                "once; value = %d solves / %.1f s wall; oracle hierarchy built first "
+                                "(setup %.1f s, excluded like the GPU setup)" % (P - 1, P, P, wall, t_setup),
+                      "host_cores_available": avail, "cpu_model": cpu_model(), "setup_s": t_setup,
+                      "wall_s": wall, "per_solve_s": [round(r[2], 2) for r in kd],
+                      "outer_its": [r[3] for r in kd], "max_true_rel_resid": max(r[4] for r in kd),
+                      "cg_eo": {"seconds": cg[2], "iterations": cg[3], "rhs": 0}}))
 
 
-def start_cpu_leg(budget_its):
+def start_cpu_leg(nproc):
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        env[k] = "1"
+        env.pop(k, None)
     env["HIP_VISIBLE_DEVICES"] = ""
     env["CUDA_VISIBLE_DEVICES"] = ""
     return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child",
-                             str(budget_its)], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                             str(nproc)], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
                             text=True, env=env, cwd=ROOT)
 
 
@@ -542,13 +587,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-its", type=int, default=3)
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle worker processes of the CPU baseline (0: available cores - 2, at most 14)")
+    ap.add_argument("--cgne-steps", type=int, default=2,
+                    help="timed steps of the Table 1 CGNE-coarsest variant (0: skip)")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="short run for hardware-counter passes: a 64 MiB copy, then one mixed "
                          "32-rhs solve cut off after one outer iteration; prints no metric")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the out-of-cache Dslash sweep")
-    ap.add_argument("--fp64-rhs", type=int, default=1)
+    ap.add_argument("--fp64-rhs", type=int, default=NRHS)
     ap.add_argument("--cpu-child", type=int, default=None)
     ap.add_argument("--serve", action="store_true", help="served-stream measurement instead of the bench line")
     ap.add_argument("--su3", action="store_true", help="4D SU(3) 24^4 measurement instead of the bench line")
@@ -584,7 +632,7 @@ def main():
         return transfer_main(a)
     if a.mass_scan:
         return mass_scan_main(a)
-    cpu = None if (a.no_cpu or a.kernel_profile) else start_cpu_leg(a.cpu_its)
+    cpu = None if (a.no_cpu or a.kernel_profile) else start_cpu_leg(a.cpu_procs)
 
     import numpy as np
     import torch
@@ -595,11 +643,15 @@ def main():
     lat = kdmg.Lattice(DIMS, U)
     V = lat.volume
     psi0, seed = starts(V)
-    params = kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=COARSE_MAXIT,
-                              outer_maxit=200)
+
+    def params(coarse_solver=COARSE_SOLVER, **kw):
+        kw.setdefault("outer_maxit", 200)
+        return kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=COARSE_MAXIT,
+                                coarse_solver=coarse_solver, **kw)
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = kdmg.Hierarchy(lat, MASS, params, psi0)
+    h = kdmg.Hierarchy(lat, MASS, params(), psi0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print("setup %.2f s" % setup_s, file=sys.stderr, flush=True)
@@ -611,12 +663,9 @@ def main():
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        p1 = kdmg.make_params([((4, 4), NV), ((2, 2), NV2)], coarse_maxit=COARSE_MAXIT, outer_maxit=1)
-        h1 = kdmg.Hierarchy(lat, MASS, p1, psi0)
-        info, st = kdmg.kdmg_solve(h1, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)
+        info, st = kdmg.kdmg_solve(h, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)
         torch.cuda.synchronize()
-        print("kernel-profile run done: 1 outer iteration, level-3 avg its %.1f"
-              % info[0]["level_avg_its"][1], flush=True)
+        print("kernel-profile run done: %d outer iterations" % info[0]["outer_its"], flush=True)
         return 0
     for i in range(a.warmup):
         info, _ = kdmg.kdmg_solve(h, b, x, NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
@@ -629,7 +678,7 @@ def main():
         print("step %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    cg_ms, cg_launches = kdmg.kdmg_hierarchy_kernel_timing(h, 0)
+    cs_ms, cs_launches = kdmg.kdmg_hierarchy_kernel_timing(h, 0)
     value = NRHS * a.steps / T
     max_res = max(i["true_rel_resid"] for i in info)
     assert all(i["converged"] for i in info) and max_res <= 1e-10
@@ -645,8 +694,40 @@ def main():
         torch.cuda.synchronize()
         t64.append(time.perf_counter() - t0)
         info64.append(inf[0])
-        print("fp64 rhs %d: %.2f s" % (r, t64[-1]), file=sys.stderr, flush=True)
+    if t64:
+        print("fp64 single rhs: %d rhs in %.2f s" % (len(t64), sum(t64)), file=sys.stderr, flush=True)
     fp64_rate = len(t64) / sum(t64) if t64 else None
+
+    # the Table 1 coarsest solve (CGNE tol 0.2, capped at 1024) on the same
+    # null vectors: a second hierarchy, mixed 32 rhs, with the coarsest
+    # CGNE's fused kernels timed live
+    cgne = None
+    if a.cgne_steps > 0:
+        hc = kdmg.Hierarchy(lat, MASS, params(coarse_solver=0), psi0)
+        xc = torch.empty_like(b)
+        kdmg.kdmg_solve(hc, b, xc, NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
+        torch.cuda.synchronize()
+        kdmg.kdmg_hierarchy_kernel_timing(hc, 1)
+        t0 = time.perf_counter()
+        for i in range(a.cgne_steps):
+            infc, _ = kdmg.kdmg_solve(hc, b, xc, NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
+        torch.cuda.synchronize()
+        Tc = time.perf_counter() - t0
+        cg_ms, cg_launches = kdmg.kdmg_hierarchy_kernel_timing(hc, 0)
+        dims3, nd3 = hc.level_info(2)
+        ns3 = int(np.prod(dims3))
+        ndir = 2 * len(dims3) + 1
+        t_c = cg_ms * 1e-3 / max(cg_launches, 1)
+        bytes_c = 16.0 * ndir * nd3 * nd3 * ns3 + 4.0 * 16.0 * ns3 * nd3 * NRHS
+        cgne = {"value": NRHS * a.cgne_steps / Tc, "unit": "solves/s", "steps": a.cgne_steps,
+                "coarsest": "CGNE tol 0.2, at most %d iterations (Table 1 form)" % COARSE_MAXIT,
+                "outer": [i["outer_its"] for i in infc],
+                "level3_avg": [round(i["level_avg_its"][1], 1) for i in infc],
+                "max_true_rel_resid": max(i["true_rel_resid"] for i in infc),
+                "k_cgne_us_per_launch": t_c * 1e6, "k_cgne_hbm_frac": bytes_c / t_c / 1e9 / HBM_PEAK_GBS,
+                "traffic": traffic_per_launch()}
+        del hc, xc
+        print("cgne coarsest: %.1f solves/s" % cgne["value"], file=sys.stderr, flush=True)
 
     # the paper's comparison solver: CG on the site even/odd Schur system,
     # FP64, the same NRHS rhs batched, to the same true-residual target
@@ -710,32 +791,29 @@ def main():
             torch.cuda.empty_cache()
     dslash["out_of_cache_sweep"] = sweep
 
-    # dominant kernel: the coarsest level's fused CGNE iteration (k_cgne_A then
-    # k_cgne_B, FP64, 32 rhs), timed with HIP events on the solve stream during
-    # the timed steps.  Algorithmic traffic per launch, averaged over the pair:
-    # the stencil Y (ndir blocks of ndc^2 complex per site) once, plus 5 (A:
-    # p, x r/w, r r/w) or 3 (B: r, p r/w) vector passes of nsites*ndc*nrhs.
-    dims3, nd3 = h.level_info(2)
-    ns3 = int(np.prod(dims3))
-    ndir = 2 * len(dims3) + 1
-    t_c = cg_ms * 1e-3 / max(cg_launches, 1)
-    y_bytes = 16.0 * ndir * nd3 * nd3 * ns3
-    vec_bytes = 16.0 * ns3 * nd3 * NRHS
-    bytes_c = y_bytes + 4.0 * vec_bytes
-    flops = 8.0 * ndir * nd3 * nd3 * ns3 * NRHS
+    # dominant kernel of the headline: the product with the coarsest inverse
+    # (k_dn_apply and its in-order k_dn_reduce), timed with HIP events on the
+    # solve stream during the timed steps.  Algorithmic work per launch: the
+    # n x n inverse read once (16 n^2 B), the rhs and the solution once each
+    # (2 * 16 n nrhs B), 8 n^2 nrhs flop (a complex multiply-add is 8 real
+    # flops; the kernel spends 6 in MFMA, Gauss's three real products).
+    n3 = h.ndof(2)
+    t_c = cs_ms * 1e-3 / max(cs_launches, 1)
+    bytes_c = 16.0 * n3 * n3 + 2 * 16.0 * n3 * NRHS
+    flops = 8.0 * n3 * n3 * NRHS
     t_hbm, t_mfma = bytes_c / (HBM_PEAK_GBS * 1e9), flops / (FP64_PEAK_TFLOPS * 1e12)
-    achieved_gbs = bytes_c / t_c / 1e9
-    roofline = {"kernel": "k_cgne_A / k_cgne_B (coarsest CGNE iteration on A_hat_hat, %dx%d sites x %d "
-                          "dofs, FP64, 32 rhs; MFMA f64 16x16x4)" % (dims3[0], dims3[1], nd3),
-                "bound": "hbm" if t_hbm >= t_mfma else "mfma",
-                "achieved": achieved_gbs if t_hbm >= t_mfma else flops / t_c / 1e12,
-                "peak": HBM_PEAK_GBS if t_hbm >= t_mfma else FP64_PEAK_TFLOPS,
-                "unit": "GB/s" if t_hbm >= t_mfma else "TFLOP/s",
-                "frac": (t_hbm if t_hbm >= t_mfma else t_mfma) / t_c,
-                "traffic": traffic_per_launch(),
-                "us_per_launch": t_c * 1e6, "launches_timed": cg_launches,
+    mfma_bound = t_mfma >= t_hbm
+    roofline = {"kernel": "k_dn_apply + k_dn_reduce (coarsest solve: product with the explicit inverse, "
+                          "%d x %d complex FP64, %d rhs; MFMA f64 16x16x4)" % (n3, n3, NRHS),
+                "bound": "mfma" if mfma_bound else "hbm",
+                "achieved": flops / t_c / 1e12 if mfma_bound else bytes_c / t_c / 1e9,
+                "peak": FP64_PEAK_TFLOPS if mfma_bound else HBM_PEAK_GBS,
+                "unit": "TFLOP/s" if mfma_bound else "GB/s",
+                "frac": (t_mfma if mfma_bound else t_hbm) / t_c,
+                "traffic": None,
+                "us_per_launch": t_c * 1e6, "launches_timed": cs_launches,
                 "algorithmic_bytes_per_launch": bytes_c, "flops_per_launch": flops,
-                "fp64_mfma_tflops": flops / t_c / 1e12}
+                "hbm_gbs": bytes_c / t_c / 1e9}
 
     cpu_res = None
     if cpu is not None:
@@ -758,6 +836,7 @@ def main():
         "fp64_single_rhs": {"value": fp64_rate, "unit": "solves/s", "rhs_timed": len(t64),
                             "outer_its": [i["outer_its"] for i in info64],
                             "mixed_over_fp64": value / fp64_rate if fp64_rate else None},
+        "cgne_coarsest": cgne,
         "cg_eo": cg_eo,
         "dslash": dslash,
         "roofline": roofline,

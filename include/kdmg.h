@@ -100,6 +100,14 @@ typedef struct {
                                  launch shape tuned for that width (the same
                                  iteration per rhs; rounding may differ with
                                  the shape); 0: off.  0..64 */
+  int coarse_solver;          /* coarsest-level solve: 0 (default) CGNE with
+                                 coarse_tol / coarse_maxit as in Table 1;
+                                 1 exact, through an explicit FP64 inverse of
+                                 the coarsest operator built with the
+                                 hierarchy and on every mass change (not the
+                                 paper's choice: a stronger preconditioner;
+                                 at most 32768 coarsest dofs, 32 n^2 bytes of
+                                 device memory for n dofs) */
 } kdmg_mg_params;
 
 /* Per right-hand side result of kdmg_solve. */
@@ -120,12 +128,19 @@ void kdmg_default_params(kdmg_mg_params* p);
    other call; idempotent). */
 kdmg_status kdmg_init(int device);
 
-/* Uploads a gauge field.  links_host: complex128 [nd][volume][ncolor][ncolor]
-   (copied; the caller keeps ownership).  antiperiodic_time != 0 applies the
-   antiperiodic sign to hops that cross the last axis' boundary. */
-kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
-                                const double* links_host, int antiperiodic_time,
-                                kdmg_lattice** out);
+/* Uploads a gauge field for the staggered operator of eq. "staggeredD"
+   (Sec. 1; U(1) links in 2D, SU(3) in 4D, Sec. 2).
+   dims: nd extents, x_1 first.  links_host: complex128 [nd][volume][ncolor][ncolor],
+   U_mu(x) the link from x to x+mu (copied; the caller keeps ownership).
+   bc_sign: nd entries of +1 (periodic) or -1 (antiperiodic); a hop that
+   crosses the boundary of direction mu carries bc_sign[mu].  NULL selects
+   periodic space directions and an antiperiodic last (time) direction -- the
+   paper states no boundary condition.  The upload runs on `stream`, which is
+   synchronised before return.  KDMG_EINVAL for extents that are not positive
+   multiples of 4 or signs other than +-1; KDMG_EUNSUPPORTED for geometries
+   other than (nd 2, ncolor 1) and (nd 4, ncolor 3). */
+kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor, const int* bc_sign,
+                                const double* links_host, void* stream, kdmg_lattice** out);
 void kdmg_lattice_destroy(kdmg_lattice* lat);
 /* Device bytes held by the lattice. */
 kdmg_status kdmg_lattice_footprint(const kdmg_lattice* lat, size_t* bytes);
@@ -138,12 +153,20 @@ kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const void* in,
                          void* out, int nrhs, kdmg_prec prec, void* stream);
 
 /* out = A in with A = D B^-1 (Sec. 2.1 eq. "defA"), or out = A^dag in when
-   dagger != 0, using A^dag = eps B^-1 D eps (eq. "gamma5L").  complex128, FP64.
-   B^-1 is the exact inverse of each 2^d Kahler-Dirac block (mass included). */
+   dagger != 0, using A^dag = eps B^-1 D eps (eq. "gamma5L").  B^-1 is the
+   exact inverse of each 2^d Kahler-Dirac block (mass included).
+   prec = KDMG_FP64: complex128 vectors, FP64 links and arithmetic.
+   prec = KDMG_MIXED: complex64 vectors, FP16-stored links, FP32 arithmetic
+   (4D: FP32 copies of the B^-1 blocks) -- the level-0 operator of the mixed
+   V-cycle.  in, out: [nrhs][volume*ncolor] natural order, must not overlap.
+   Allocates its work space per call and synchronises `stream`. */
 kdmg_status kdmg_apply_A(const kdmg_lattice* lat, double mass, const void* in,
-                         void* out, int nrhs, int dagger, void* stream);
+                         void* out, int nrhs, int dagger, kdmg_prec prec, void* stream);
 
-/* out = B^-1 in (block-local inverse of the Kahler-Dirac blocks), complex128. */
+/* out = B^-1 in: the inverse of the 2^d Kahler-Dirac blocks B, the
+   block-local part of D (Sec. 2.1, the printed 2D block eq. "localblock";
+   mass included).  complex128, FP64, natural order [nrhs][volume*ncolor].
+   Allocates its work space per call and synchronises `stream`. */
 kdmg_status kdmg_apply_Binv(const kdmg_lattice* lat, double mass, const void* in,
                             void* out, int nrhs, void* stream);
 
@@ -187,9 +210,12 @@ kdmg_status kdmg_hierarchy_get_prolongator(const kdmg_hierarchy* h, int k, doubl
    block [dir][Z][i][j] couples dof i of Z to dof j of that neighbour. */
 kdmg_status kdmg_hierarchy_get_coarse_op(const kdmg_hierarchy* h, int level, double* host_out);
 
-/* out = A_level in (dagger = 0) or A_level^dag in on coarse level >= 1.
+/* out = A_level in (dagger = 0) or A_level^dag in on coarse level >= 1: the
+   Galerkin coarse operator A_hat = P^dag A P of Sec. 3 (Sec. 3.3 for the
+   Kahler-Dirac form), a nearest-neighbour block stencil with 2 n_vec dofs
+   per coarse site; in and out are [nrhs][sites][dofs] coarse vectors.
    prec KDMG_FP64: complex128 and FP64 operator; KDMG_MIXED: complex64 and the
-   FP32 operator. */
+   FP32 operator.  Stream-ordered. */
 kdmg_status kdmg_coarse_apply(const kdmg_hierarchy* h, int level, int dagger,
                               const void* in, void* out, int nrhs, kdmg_prec prec,
                               void* stream);
@@ -206,8 +232,19 @@ kdmg_status kdmg_restrict(const kdmg_hierarchy* h, int k, const void* in, void* 
 kdmg_status kdmg_prolong(const kdmg_hierarchy* h, int k, const void* in, void* out,
                          int nrhs, kdmg_prec prec, void* stream);
 
+/* The exact coarsest solve of a hierarchy built with coarse_solver = 1:
+   out = A_c^-1 in on the coarsest level c = nlevels - 1 (A_c the Galerkin
+   operator of Sec. 3 at the hierarchy's mass), for nrhs complex128 coarse
+   vectors [nrhs][sites][dofs].  The inverse is formed at build time as
+   A_c^dag (A_c A_c^dag)^-1 (FP64 Gauss-Jordan on the positive definite
+   normal matrix); each call is one product with it.  KDMG_EINVAL if the
+   hierarchy has no such inverse.  Allocates its work space per call and
+   synchronises `stream`. */
+kdmg_status kdmg_coarsest_solve(kdmg_hierarchy* h, const void* in, void* out, int nrhs, void* stream);
+
 /* Conjugate gradient on the site even/odd Schur system, the solver the paper
-   compares KD-MG against (Sec. 1 and 2; Sec. 5): with D = m + H,
+   compares KD-MG against (Sec. 2, the even/odd normal equations; Sec. 4,
+   Figs. "resid" and "iterworst"): with D = m + H,
    (m^2 - H_eo H_oe) x_e = m b_e - H_eo b_o (Hermitian positive definite),
    then x_o = (b_o - H_oe x_e) / m.  The target is ||b - D x|| <= tol ||b||,
    i.e. ||r_e|| <= tol m ||b|| for the true even residual r_e.  CG stops a
@@ -287,9 +324,11 @@ kdmg_status kdmg_hierarchy_graphs(kdmg_hierarchy* h, int enable, long long* repl
    Either pointer may be NULL. */
 kdmg_status kdmg_hierarchy_counters(kdmg_hierarchy* h, long long* graph_replays, long long* tail_entries);
 
-/* Measurement hook (not an operation of the method): HIP-event timing of the
-   two fused kernels of each coarsest-level CGNE iteration, on the solve's own
-   stream, during later kdmg_solve calls.  enable = 1 starts (and zeroes) the
+/* Measurement hook (not an operation of the method): HIP-event timing, on
+   the solve's own stream during later kdmg_solve calls, of the coarsest
+   solve's kernels -- the two fused kernels of each CGNE iteration, or with
+   coarse_solver = 1 the product with the inverse (one launch counted per
+   call, the partial-product kernel and its in-order reduction together).  enable = 1 starts (and zeroes) the
    counters, 0 stops, -1 leaves the state as it is.  `ms` (may be NULL)
    receives the summed kernel time and `launches` (may be NULL) the number of
    kernel launches it covers: within every run of launches between two host
@@ -325,10 +364,16 @@ kdmg_status kdmg_server_request_bytes(kdmg_server* s, int config_id, int nrhs, k
 
 /* Queue a solve of D(U_config, mass) x = b for nrhs right-hand sides, layout
    as kdmg_solve.  b and x are caller-owned device buffers that must stay
-   valid and untouched until the request is collected by kdmg_server_poll.
-   KDMG_ENOMEM if the request alone exceeds the budget. */
+   valid until the request is collected by kdmg_server_poll.  Ordering: an
+   event is recorded on `stream` (the caller's stream; NULL = default stream)
+   at submit, and the request's device work waits for it, so work the caller
+   queued on `stream` before the submit (producing b, clearing x) completes
+   first.  Work queued on other streams must be ordered by the caller.  The
+   caller must not touch b or x after the submit until poll reports done;
+   then the solve's device work is complete and x can be read on any
+   stream.  KDMG_ENOMEM if the request alone exceeds the budget. */
 kdmg_status kdmg_server_submit(kdmg_server* s, int config_id, double mass, const void* b, void* x,
-                               int nrhs, double tol, kdmg_prec prec, long long* ticket);
+                               int nrhs, double tol, kdmg_prec prec, void* stream, long long* ticket);
 
 /* done = 1 once the request has finished (wait != 0 blocks until then).
    When done: *solve_status is kdmg_solve's status (kdmg_last_error() has its

@@ -6,10 +6,11 @@ TEST INFRASTRUCTURE ONLY (see oracle/staggered.py).
   matrix; small lattices only.
 * ``cg_eo``: CG on the site-parity normal equations of Sec. 2 (eq. "normal"):
   (m^2 - D_eo D_oe) x_e = m b_e - D_eo b_o, then x_o = (b_o - D_oe x_e)/m.
+  ``cg_eo_multi`` runs the same CG on several right-hand sides at once.
 * ``free_fft_solve``: for unit links, D^dag D = m^2 + sum_mu sin^2 p_mu is
   diagonal in momentum space (the corner terms cancel, Sec. 2), so
-  x = D^dag F^-1[F(b) / (m^2 + sum sin^2 p)].  The antiperiodic time direction
-  is handled by the twist exp(i pi t / L_t), which makes the field periodic.
+  x = D^dag F^-1[F(b) / (m^2 + sum sin^2 p)].  Each antiperiodic direction mu
+  is handled by the twist exp(i pi x_mu / L_mu), which makes the field periodic.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -39,22 +40,62 @@ def cg_eo(lat, U, m, b, tol=1e-13, maxit=200000):
     return x, its
 
 
+def cg_eo_multi(lat, U, m, B, tol=1e-13, maxit=200000):
+    """``cg_eo`` for the columns of B [nrhs][ndof] at once: the same CG,
+    with its own scalars and its own stop per column, run over a block of
+    columns so the sparse products are shared.  Returns (X, iterations)."""
+    D = dirac_matrix(lat, U, m)
+    par = np.repeat(np.where(epsilon(lat) > 0, 0, 1), lat.ncolor)
+    e = np.flatnonzero(par == 0)
+    o = np.flatnonzero(par == 1)
+    D_eo = D[e][:, o].tocsr()
+    D_oe = D[o][:, e].tocsr()
+    B = np.asarray(B)
+    rhs = (m * B[:, e] - (D_eo @ B[:, o].T).T).T          # [n_e][nrhs]
+    x = np.zeros_like(rhs)
+    r = rhs.copy()
+    p = r.copy()
+    rr = np.einsum("ij,ij->j", r.conj(), r).real
+    bnorm = np.sqrt(rr)
+    active = bnorm > 0
+    its = np.zeros(B.shape[0], dtype=int)
+    while active.any() and its.max() < maxit:
+        a = np.flatnonzero(active)
+        q = m * m * p[:, a] - D_eo @ (D_oe @ p[:, a])
+        alpha = rr[a] / np.einsum("ij,ij->j", p[:, a].conj(), q).real
+        x[:, a] += alpha * p[:, a]
+        r[:, a] -= alpha * q
+        its[a] += 1
+        rr_new = np.einsum("ij,ij->j", r[:, a].conj(), r[:, a]).real
+        done = np.sqrt(rr_new) <= tol * bnorm[a]
+        beta = rr_new / rr[a]
+        p[:, a] = r[:, a] + beta * p[:, a]
+        rr[a] = rr_new
+        active[a[done]] = False
+    X = np.zeros_like(B)
+    X[:, e] = x.T
+    X[:, o] = (B[:, o].T - D_oe @ x).T / m
+    return X, its
+
+
 def free_fft_solve(lat, m, b):
     """Closed-form solve for U = 1 (ncolor 1 or more, colours decouple)."""
     nc = lat.ncolor
     shape = tuple(reversed(lat.dims))
     nd = lat.nd
     bb = b.reshape(shape + (nc,))
-    t = lat.coords[:, nd - 1].reshape(shape)
-    twist = np.exp(1j * np.pi * t / lat.dims[-1]) if lat.antiperiodic_time \
-        else np.ones(shape)
+    twist = np.ones(shape, dtype=np.complex128)
+    for mu in range(nd):
+        if lat.bc[mu] == -1:
+            xm = lat.coords[:, mu].reshape(shape)
+            twist = twist * np.exp(1j * np.pi * xm / lat.dims[mu])
     g = bb / twist[..., None]
     ghat = np.fft.fftn(g, axes=tuple(range(nd)))
     denom = np.full(shape, m * m, dtype=np.float64)
     for mu in range(nd):
         L = lat.dims[mu]
         p = 2 * np.pi * np.fft.fftfreq(L) * 1.0
-        if lat.antiperiodic_time and mu == nd - 1:
+        if lat.bc[mu] == -1:
             p = p + np.pi / L
         sh = [1] * nd
         sh[nd - 1 - mu] = L

@@ -25,6 +25,9 @@ solve (Sec. 4 and Table 1 "solver" rows):
   * intermediate levels: GCR(8) on A_hat, at most 16 iterations, tolerance 0.2,
     itself preconditioned by the next K-cycle;
   * coarsest level: CGNE (CG on A A^dag, x = A^dag y), tolerance 0.2, at most 256.
+    Option beyond the paper (``MGParams.coarse_exact``): the coarsest system
+    is solved exactly, by a dense LU factorisation of the coarsest operator
+    made once per hierarchy, instead of CGNE(0.2).
 
 Null vectors are random by construction, so their values are parity unpinned
 against the paper; everything downstream of them (P, A_hat, the solve) is
@@ -32,6 +35,7 @@ pinned given them.
 """
 from dataclasses import dataclass, field
 import numpy as np
+import scipy.linalg
 import scipy.sparse as sp
 
 from .kd import KDOperator
@@ -61,6 +65,7 @@ class MGParams:
     inter_tol: float = 0.2
     coarse_tol: float = 0.2
     coarse_maxit: int = 256
+    coarse_exact: bool = False   # dense LU solve on the coarsest level (not the paper's CGNE)
 
 
 def vdot(a, b):
@@ -253,6 +258,9 @@ class Hierarchy:
             nvec_prev = lp.nvec
         self.coarse_dims = dims
         self.P_even = self.P[0][self.kd.even].tocsr()
+        self.coarse_lu = None
+        if params.coarse_exact:
+            self.coarse_lu = scipy.linalg.lu_factor(self.ops[-1].toarray())
 
     @property
     def nlevels(self):
@@ -369,7 +377,9 @@ class Solver:
     def coarse_solve(self, level, r):
         p = self.p
         self.stats.calls[level] += 1
-        if level == self.h.nlevels - 1:
+        if level == self.h.nlevels - 1 and self.h.coarse_lu is not None:
+            x, its = scipy.linalg.lu_solve(self.h.coarse_lu, r), 1
+        elif level == self.h.nlevels - 1:
             x, its = cgne(self.h.ops[level], r, p.coarse_tol, p.coarse_maxit)
         else:
             x, its, _ = gcr(self._op(level), r, lambda v: self.kcycle(level, v),

@@ -11,8 +11,10 @@ Definitions follow the paper's Sec. 1 (eq. "staggeredD") and Sec. 2:
 
 with eta_mu(x) = (-1)^{sum_{nu<mu} x_nu} (Sec. 1) and the chirality
 epsilon(x) = (-1)^{sum_mu x_mu} (Sec. 2, eq. "epsilon").  Lattice spacing a = 1.
-Boundary conditions are periodic in every direction except the last (time),
-which is antiperiodic; the paper is silent on this, the workloads fix it.
+Boundary conditions: the paper is silent.  The default is periodic in every
+direction except the last (time), which is antiperiodic, as the workloads
+fix it; ``Lattice(bc=...)`` sets a sign per direction (+1 periodic, -1
+antiperiodic), carried by every hop that crosses that direction's boundary.
 
 Index conventions: site index x_1 + L_1*(x_2 + L_2*(...)) (x_1 fastest),
 dof index site*ncolor + colour.  Gauge fields are complex128 [mu, site, a, b].
@@ -22,14 +24,18 @@ import scipy.sparse as sp
 
 
 class Lattice:
-    """Geometry of a periodic hypercubic lattice."""
+    """Geometry of a hypercubic torus with a boundary sign per direction."""
 
-    def __init__(self, dims, ncolor=1, antiperiodic_time=True):
+    def __init__(self, dims, ncolor=1, antiperiodic_time=True, bc=None):
         self.dims = tuple(int(L) for L in dims)
         self.nd = len(self.dims)
         self.ncolor = int(ncolor)
         self.volume = int(np.prod(self.dims))
-        self.antiperiodic_time = bool(antiperiodic_time)
+        if bc is None:
+            bc = [1] * (self.nd - 1) + [-1 if antiperiodic_time else 1]
+        self.bc = tuple(int(b) for b in bc)
+        assert len(self.bc) == self.nd and all(b in (1, -1) for b in self.bc)
+        self.antiperiodic_time = self.bc[-1] == -1
         idx = np.arange(self.volume)
         coords = np.empty((self.volume, self.nd), dtype=np.int64)
         rem = idx.copy()
@@ -53,8 +59,7 @@ class Lattice:
         c[:, mu] += step
         crosses = (c[:, mu] < 0) | (c[:, mu] >= self.dims[mu])
         sign = np.ones(self.volume)
-        if self.antiperiodic_time and mu == self.nd - 1:
-            sign[crosses] = -1.0
+        sign[crosses] = float(self.bc[mu])
         return self.index(c), sign
 
 
@@ -131,7 +136,7 @@ def free_spectrum(lat, m):
     """Closed-form free eigenvalues m +- i sqrt(sum_mu sin^2 p_mu) (Sec. 2).
 
     Enumerates the full Brillouin zone: p_mu = 2 pi n / L_mu in periodic
-    directions and (2n + 1) pi / L_mu in the antiperiodic time direction.
+    directions and (2n + 1) pi / L_mu in antiperiodic ones.
     The full-zone multiset of sum sin^2 p_mu equals the paper's reduced zone
     n in [-L/4+1, L/4] with multiplicity 2^d.  Returns the multiset of
     (Im lambda)^2 values (each appearing once per momentum) for a single colour.
@@ -139,7 +144,7 @@ def free_spectrum(lat, m):
     ps = []
     for mu, L in enumerate(lat.dims):
         n = np.arange(L)
-        if lat.antiperiodic_time and mu == lat.nd - 1:
+        if lat.bc[mu] == -1:
             ps.append((2 * n + 1) * np.pi / L)
         else:
             ps.append(2 * n * np.pi / L)

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkdmg.so")
 SOURCES = ["lattice.hip", "coarse_kernels.hip", "hierarchy.hip", "solver.hip", "autotune.hip", "cg_eo.hip",
-           "server.hip", "setup4d.hip"]
+           "server.hip", "setup4d.hip", "coarsest_dense.hip"]
 ARCH = os.environ.get("KDMG_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
          # no packed FP32 instructions in device code

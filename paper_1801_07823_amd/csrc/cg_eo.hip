@@ -1,6 +1,7 @@
 // Conjugate gradient on the site even/odd (red/black) Schur system of the 2D
 // staggered operator: the solver the paper compares KD-MG against (Sec. 1 and
-// Sec. 2 state the system; Sec. 5 compares iteration counts).
+// Sec. 2 state the system; Sec. 4, Figs. "resid" and "iterworst", compares
+// iteration counts).
 //
 // With D = m + H (H the hopping term, anti-Hermitian, connecting opposite
 // site parities only), D x = b splits into

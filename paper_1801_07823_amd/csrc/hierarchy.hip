@@ -464,6 +464,10 @@ kdmg_hierarchy::~kdmg_hierarchy() {
   if (ws) kdmg::destroy_ws(ws);
   if (timer.e0) (void)hipEventDestroy(timer.e0);
   if (timer.e1) (void)hipEventDestroy(timer.e1);
+  for (auto& e : timer.dn_ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
 }
 
 extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass,
@@ -477,7 +481,8 @@ extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass
   KDMG_CHECK(mass > 0.0, KDMG_EINVAL, "mass must be positive");
   KDMG_CHECK(params->setup_maxit >= 0 && params->outer_restart >= 1 && params->outer_restart <= 64 &&
                  params->inter_restart >= 1 && params->inter_restart <= 64 && params->outer_stall >= 0 &&
-                 params->coarse_tail >= 0 && params->coarse_tail <= 64,
+                 params->coarse_tail >= 0 && params->coarse_tail <= 64 &&
+                 (params->coarse_solver == 0 || params->coarse_solver == 1),
              KDMG_EINVAL, "bad solver parameters");
   for (int k = 0; k < params->nlevels - 1; ++k)
     KDMG_CHECK(psi0_host[k] != nullptr, KDMG_EINVAL, "missing starting vectors");
@@ -497,6 +502,7 @@ extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass
   else
     build_level1(*h, ca.c, psi0_host[0], relaxed);
   for (int k = 1; k < h->nlevels - 1; ++k) build_coarse(*h, k, ca.c, psi0_host[k], relaxed);
+  if (params->coarse_solver == 1) build_dense_inverse(h->dinv, h->L[h->nlevels - 1], (hipStream_t)stream);
   KDMG_HIP(hipStreamSynchronize((hipStream_t)stream));
   *out = h.release();
   KDMG_API_END
@@ -522,6 +528,7 @@ void rebuild_coarse_ops(kdmg_hierarchy& h, hipStream_t st) {
   c.st = st;
   galerkin_level1(h, c);
   for (int k = 1; k < h.nlevels - 1; ++k) galerkin_coarse(h, k, c);
+  if (h.params.coarse_solver == 1) build_dense_inverse(h.dinv, h.L[h.nlevels - 1], st);
   KDMG_HIP(hipStreamSynchronize(st));
 }
 

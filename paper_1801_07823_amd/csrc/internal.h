@@ -15,6 +15,7 @@
 #include "fine4d.cuh"
 #include "coarse.cuh"
 #include "coarse_fast.cuh"
+#include "dense.h"
 
 namespace kdmg {
 
@@ -27,7 +28,7 @@ struct kdmg_lattice {
   int nd = 0, nc = 0;
   int dims[4] = {1, 1, 1, 1};
   long volume = 0;
-  int antiperiodic = 1;
+  int bc[4] = {1, 1, 1, -1};  // boundary sign per direction (+1 periodic, -1 antiperiodic)
   kdmg::Geo2 g{};
   long ndof = 0;   // complex entries of a fine vector (volume * nc)
   long half = 0;   // complex entries of one KD-block parity half (the Schur space)
@@ -111,25 +112,22 @@ void schur_apply(Cx<R>* out, const Cx<R>* v, const Cx<R>* resid, Cx<R>* t, Cx<R>
 }
 
 // Full-lattice A = 1 + C B^-1:  t = B^-1 v ; out = v + C t
-template <class LT>
-void fullA_apply(c64* out, const c64* v, c64* t, const Cx<LT>* links, const Geo2& g, double m,
+template <class LT, class R = double>
+void fullA_apply(Cx<R>* out, const Cx<R>* v, Cx<R>* t, const Cx<LT>* links, const Geo2& g, double m,
                  const int* act, int nrhs, hipStream_t st) {
   const long f = 2 * g.half;
-  launch_binv<double, LT, double>(t, f, nullptr, 0, v, f, nullptr, 0, links, g, 0, 2, m, 0, act,
-                                  nrhs, st);
-  launch_hop<double, LT, double>(out, f, t, f, v, f, nullptr, 0, 0.0, 1.0, links, g, 0, 2, m, 0, 0,
-                                 act, nrhs, st);
+  launch_binv<R, LT, R>(t, f, nullptr, 0, v, f, nullptr, 0, links, g, 0, 2, m, 0, act, nrhs, st);
+  launch_hop<R, LT, R>(out, f, t, f, v, f, nullptr, 0, 0.0, 1.0, links, g, 0, 2, m, 0, 0, act, nrhs, st);
 }
 
 // Full-lattice A^dag = 1 + eps B^-1 C eps:  t = C (eps v) ; out = v + eps B^-1 t
 // (optionally out2 = B^-1 out, the first half of the next A apply)
-template <class LT>
-void fullAdag_apply(c64* out, c64* out2, const c64* v, c64* t, const Cx<LT>* links, const Geo2& g,
+template <class LT, class R = double>
+void fullAdag_apply(Cx<R>* out, Cx<R>* out2, const Cx<R>* v, Cx<R>* t, const Cx<LT>* links, const Geo2& g,
                     double m, const int* act, int nrhs, hipStream_t st) {
   const long f = 2 * g.half;
-  launch_hop<double, LT, double>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, links, g, 0, 2, m, 0,
-                                 1, act, nrhs, st);
-  launch_binv<double, LT, double>(out, f, out2, f, t, f, v, f, links, g, 0, 2, m, 1, act, nrhs, st);
+  launch_hop<R, LT, R>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, links, g, 0, 2, m, 0, 1, act, nrhs, st);
+  launch_binv<R, LT, R>(out, f, out2, f, t, f, v, f, links, g, 0, 2, m, 1, act, nrhs, st);
 }
 
 // ------------------------------------------------------------ 4D fine operators
@@ -196,21 +194,21 @@ void schur_apply4(Cx<R>* out, const Cx<R>* v, const Cx<R>* resid, Cx<R>* t, Cx<R
 }
 
 // A = 1 + C B^-1 on full vectors:  t = B^-1 v ; out = v + C t
-template <class LT, class BT>
-void fullA_apply4(c64* out, const c64* v, c64* t, const Fine4<LT, BT>& F, const int* act, int nrhs, hipStream_t st) {
+template <class LT, class BT, class R = double>
+void fullA_apply4(Cx<R>* out, const Cx<R>* v, Cx<R>* t, const Fine4<LT, BT>& F, const int* act, int nrhs,
+                  hipStream_t st) {
   const long f = 2 * F.g.half;
-  launch4_binv<double, BT>(t, f, v, f, nullptr, 0, F.Bv, F.g, 0, 2, 0, act, nrhs, st);
-  launch4_hop<double, LT>(out, f, t, f, v, f, nullptr, 0, 0.0, 1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 0, 0, act, nrhs, st);
+  launch4_binv<R, BT>(t, f, v, f, nullptr, 0, F.Bv, F.g, 0, 2, 0, act, nrhs, st);
+  launch4_hop<R, LT>(out, f, t, f, v, f, nullptr, 0, 0.0, 1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 0, 0, act, nrhs, st);
 }
 
 // A^dag = 1 + eps B^-1 C eps:  t = C (eps v) ; out = v + eps B^-1 t
-template <class LT, class BT>
-void fullAdag_apply4(c64* out, const c64* v, c64* t, const Fine4<LT, BT>& F, const int* act, int nrhs,
+template <class LT, class BT, class R = double>
+void fullAdag_apply4(Cx<R>* out, const Cx<R>* v, Cx<R>* t, const Fine4<LT, BT>& F, const int* act, int nrhs,
                      hipStream_t st) {
   const long f = 2 * F.g.half;
-  launch4_hop<double, LT>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 0, 1, act, nrhs,
-                          st);
-  launch4_binv<double, BT>(out, f, t, f, v, f, F.Bv, F.g, 0, 2, 1, act, nrhs, st);
+  launch4_hop<R, LT>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 0, 1, act, nrhs, st);
+  launch4_binv<R, BT>(out, f, t, f, v, f, F.Bv, F.g, 0, 2, 1, act, nrhs, st);
 }
 
 // Dense B^-1 blocks of a 4D lattice at mass m (FP64 and an FP32 copy).
@@ -294,6 +292,7 @@ struct kdmg_hierarchy {
   std::vector<kdmg::CoarseLevel> L;   // index by level; L[0] unused
   kdmg::DevBuf gal_w;                 // Galerkin scratch W = B^-1 P (level 1), kept for rebuilds
   kdmg::DevBuf binv64, binv32;        // 4D: dense B^-1 blocks at this mass (FP64, FP32)
+  kdmg::DenseInverse dinv;            // coarsest inverse (params.coarse_solver == 1)
   bool use_graphs = true;             // replay captured chunks of the coarsest CGNE
   kdmg::SolveWS* ws = nullptr;
   // event timing of the coarsest CGNE kernels (kdmg_hierarchy_kernel_timing)
@@ -304,11 +303,15 @@ struct kdmg_hierarchy {
     long long launches = 0;
     long long graph_replays = 0;  // captured CGNE chunks replayed (counted whether or not timing is on)
     long long tail_entries = 0;   // coarsest CGNE calls that continued as the narrower tail problem
+    // exact coarsest solve: event pairs around each product launch, summed
+    // when the solve ends
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> dn_ev;
+    size_t dn_used = 0;
   } timer;
   ~kdmg_hierarchy();
   // device bytes owned by this hierarchy (borrowed transfers not included)
   size_t bytes() const {
-    size_t b = gal_w.bytes + binv64.bytes + binv32.bytes;
+    size_t b = gal_w.bytes + binv64.bytes + binv32.bytes + dinv.bytes();
     if (!derived)
       for (size_t k = 0; k < T.size(); ++k) b += T[k].bytes();
     for (auto& l : L) b += l.bytes();

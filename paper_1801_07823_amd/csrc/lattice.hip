@@ -19,7 +19,8 @@ const char* last_error() { return g_last_error.c_str(); }
 
 namespace {
 
-// Fold 1/2 eta_mu(x) bc_mu(x) into the links (2D, U(1)).
+// Fold 1/2 eta_mu(x) bc_mu(x) into the links (2D, U(1)): the boundary sign
+// of direction mu sits on the links that leave the last slice in mu.
 void fold_links_2d(const kdmg_lattice& lat, const double* links, std::vector<c64>& nat) {
   const int Lx = lat.dims[0], Lt = lat.dims[1];
   const long V = lat.volume;
@@ -27,16 +28,17 @@ void fold_links_2d(const kdmg_lattice& lat, const double* links, std::vector<c64
   for (long x = 0; x < V; ++x) {
     const int x0 = (int)(x % Lx), x1 = (int)(x / Lx);
     const double eta1 = (x0 & 1) ? -1.0 : 1.0;
-    const double bc = (lat.antiperiodic && x1 == Lt - 1) ? -1.0 : 1.0;
+    const double bc0 = x0 == Lx - 1 ? (double)lat.bc[0] : 1.0;
+    const double bc1 = x1 == Lt - 1 ? (double)lat.bc[1] : 1.0;
     const double* u0 = links + 2 * (0 * V + x);
     const double* u1 = links + 2 * (1 * V + x);
-    nat[x] = c64{0.5 * u0[0], 0.5 * u0[1]};
-    nat[V + x] = c64{0.5 * eta1 * bc * u1[0], 0.5 * eta1 * bc * u1[1]};
+    nat[x] = c64{0.5 * bc0 * u0[0], 0.5 * bc0 * u0[1]};
+    nat[V + x] = c64{0.5 * eta1 * bc1 * u1[0], 0.5 * eta1 * bc1 * u1[1]};
   }
 }
 
 // 4D SU(3): geometry, folded links, neighbour table and permutations.
-void create_4d(kdmg_lattice& lat, const double* links) {
+void create_4d(kdmg_lattice& lat, const double* links, hipStream_t st) {
   Geo4& g = lat.g4;
   for (int mu = 0; mu < 4; ++mu) {
     g.L[mu] = lat.dims[mu];
@@ -73,7 +75,7 @@ void create_4d(kdmg_lattice& lat, const double* links) {
     for (int mu = 0; mu < 4; ++mu) {
       const double eta = (parity & 1) ? -1.0 : 1.0;
       parity += x[mu];
-      const double bc = (mu == 3 && lat.antiperiodic && x[3] == L[3] - 1) ? -1.0 : 1.0;
+      const double bc = x[mu] == L[mu] - 1 ? (double)lat.bc[mu] : 1.0;
       const double* u = links + 2 * (((long)mu * V + n) * 9);
       for (int e = 0; e < 9; ++e)
         lk[((size_t)ib * 4 + mu) * 9 + e] = c64{0.5 * eta * bc * u[2 * e], 0.5 * eta * bc * u[2 * e + 1]};
@@ -98,13 +100,13 @@ void create_4d(kdmg_lattice& lat, const double* links) {
   lat.nb4.alloc(nb.size() * sizeof(int));
   lat.perm_full.alloc(lat.h_perm_full.size() * sizeof(int));
   lat.perm_even.alloc(lat.h_perm_even.size() * sizeof(int));
-  KDMG_HIP(hipMemcpy(lat.lk64.p, lk.data(), lat.lk64.bytes, hipMemcpyHostToDevice));
-  KDMG_HIP(hipMemcpy(lat.nb4.p, nb.data(), lat.nb4.bytes, hipMemcpyHostToDevice));
-  KDMG_HIP(hipMemcpy(lat.perm_full.p, lat.h_perm_full.data(), lat.perm_full.bytes, hipMemcpyHostToDevice));
-  KDMG_HIP(hipMemcpy(lat.perm_even.p, lat.h_perm_even.data(), lat.perm_even.bytes, hipMemcpyHostToDevice));
-  convert<_Float16, double>(lat.lk16.as<c16>(), lat.lk64.as<c64>(), (long)lk.size(), 1, nullptr, 0);
-  convert<float, double>(lat.lk32.as<c32>(), lat.lk64.as<c64>(), (long)lk.size(), 1, nullptr, 0);
-  KDMG_HIP(hipStreamSynchronize(0));
+  KDMG_HIP(hipMemcpyAsync(lat.lk64.p, lk.data(), lat.lk64.bytes, hipMemcpyHostToDevice, st));
+  KDMG_HIP(hipMemcpyAsync(lat.nb4.p, nb.data(), lat.nb4.bytes, hipMemcpyHostToDevice, st));
+  KDMG_HIP(hipMemcpyAsync(lat.perm_full.p, lat.h_perm_full.data(), lat.perm_full.bytes, hipMemcpyHostToDevice, st));
+  KDMG_HIP(hipMemcpyAsync(lat.perm_even.p, lat.h_perm_even.data(), lat.perm_even.bytes, hipMemcpyHostToDevice, st));
+  convert<_Float16, double>(lat.lk16.as<c16>(), lat.lk64.as<c64>(), (long)lk.size(), 1, nullptr, st);
+  convert<float, double>(lat.lk32.as<c32>(), lat.lk64.as<c64>(), (long)lk.size(), 1, nullptr, st);
+  KDMG_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace
@@ -118,12 +120,15 @@ extern "C" kdmg_status kdmg_init(int device) {
   KDMG_API_END
 }
 
-extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
-                                           const double* links_host, int antiperiodic_time,
-                                           kdmg_lattice** out) {
+extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor, const int* bc_sign,
+                                           const double* links_host, void* stream, kdmg_lattice** out) {
   KDMG_API_BEGIN
   KDMG_CHECK(out && dims && links_host, KDMG_EINVAL, "kdmg_lattice_create: null argument");
   *out = nullptr;
+  if (bc_sign)
+    for (int mu = 0; mu < nd && mu < 4; ++mu)
+      KDMG_CHECK(bc_sign[mu] == 1 || bc_sign[mu] == -1, KDMG_EINVAL,
+                 "kdmg_lattice_create: boundary signs must be +1 or -1");
   if (!((nd == 2 && ncolor == 1) || (nd == 4 && ncolor == 3)))
     throw Error(KDMG_EUNSUPPORTED, "kdmg_lattice_create: built for nd=2 with ncolor=1 and nd=4 with ncolor=3");
   for (int mu = 0; mu < nd; ++mu)
@@ -137,10 +142,11 @@ extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
     lat->dims[mu] = dims[mu];
     lat->volume *= dims[mu];
   }
-  lat->antiperiodic = antiperiodic_time ? 1 : 0;
+  for (int mu = 0; mu < nd; ++mu) lat->bc[mu] = bc_sign ? bc_sign[mu] : (mu == nd - 1 ? -1 : 1);
+  hipStream_t st = (hipStream_t)stream;
   if (nd == 4) {
     KDMG_CHECK(lat->volume <= (1L << 26), KDMG_EINVAL, "kdmg_lattice_create: 4D volume too large");
-    create_4d(*lat, links_host);
+    create_4d(*lat, links_host, st);
     *out = lat.release();
     return KDMG_OK;
   }
@@ -194,14 +200,16 @@ extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor,
   lat->nat16.alloc(nat.size() * sizeof(c16));
   lat->perm_full.alloc(V * sizeof(int));
   lat->perm_even.alloc(V / 2 * sizeof(int));
-  KDMG_HIP(hipMemcpy(lat->links64.p, blk.data(), lat->links64.bytes, hipMemcpyHostToDevice));
-  KDMG_HIP(hipMemcpy(lat->nat64.p, nat.data(), lat->nat64.bytes, hipMemcpyHostToDevice));
-  KDMG_HIP(hipMemcpy(lat->perm_full.p, lat->h_perm_full.data(), lat->perm_full.bytes, hipMemcpyHostToDevice));
-  KDMG_HIP(hipMemcpy(lat->perm_even.p, lat->h_perm_even.data(), lat->perm_even.bytes, hipMemcpyHostToDevice));
-  convert<_Float16, double>(lat->links16.as<c16>(), lat->links64.as<c64>(), (long)blk.size(), 1, nullptr, 0);
-  convert<float, double>(lat->links32.as<c32>(), lat->links64.as<c64>(), (long)blk.size(), 1, nullptr, 0);
-  convert<_Float16, double>(lat->nat16.as<c16>(), lat->nat64.as<c64>(), (long)nat.size(), 1, nullptr, 0);
-  KDMG_HIP(hipStreamSynchronize(0));
+  KDMG_HIP(hipMemcpyAsync(lat->links64.p, blk.data(), lat->links64.bytes, hipMemcpyHostToDevice, st));
+  KDMG_HIP(hipMemcpyAsync(lat->nat64.p, nat.data(), lat->nat64.bytes, hipMemcpyHostToDevice, st));
+  KDMG_HIP(hipMemcpyAsync(lat->perm_full.p, lat->h_perm_full.data(), lat->perm_full.bytes, hipMemcpyHostToDevice,
+                          st));
+  KDMG_HIP(hipMemcpyAsync(lat->perm_even.p, lat->h_perm_even.data(), lat->perm_even.bytes, hipMemcpyHostToDevice,
+                          st));
+  convert<_Float16, double>(lat->links16.as<c16>(), lat->links64.as<c64>(), (long)blk.size(), 1, nullptr, st);
+  convert<float, double>(lat->links32.as<c32>(), lat->links64.as<c64>(), (long)blk.size(), 1, nullptr, st);
+  convert<_Float16, double>(lat->nat16.as<c16>(), lat->nat64.as<c64>(), (long)nat.size(), 1, nullptr, st);
+  KDMG_HIP(hipStreamSynchronize(st));
   *out = lat.release();
   KDMG_API_END
 }
@@ -280,85 +288,111 @@ namespace {
 
 enum FineOp { OP_A, OP_ADAG, OP_BINV, OP_SCHUR };
 
-void fine_op_natural(const kdmg_lattice* lat, double mass, const void* in, void* out, int nrhs,
-                     FineOp op, hipStream_t st) {
+// Complex entries of work space a fine-operator call needs per rhs: gathered
+// input a, output b, and the temporaries t and w (the Schur operator's input
+// and output are even-block halves).
+long fine_op_scratch_entries(const kdmg_lattice& lat, FineOp op) {
+  const long h = lat.half, f = 2 * h;
+  return op == OP_SCHUR ? 2 * h + 2 * f : 4 * f;
+}
+
+// One fine operator on natural-order vectors: gather into the block layout,
+// apply, scatter back.  R = double: complex128 vectors and FP64 links;
+// R = float: complex64 vectors, FP16-stored links (FP32 B^-1 blocks in 4D).
+// `work`: caller-provided space of fine_op_scratch_entries * nrhs entries, or
+// null to allocate it for the call.
+template <class R>
+void fine_op_natural(const kdmg_lattice* lat, double mass, const void* in, void* out, int nrhs, FineOp op,
+                     hipStream_t st, Cx<R>* work) {
   KDMG_CHECK(lat && in && out, KDMG_EINVAL, "null argument");
   KDMG_CHECK(nrhs >= 1 && nrhs <= 65535, KDMG_EINVAL, "bad nrhs");
+  KDMG_CHECK(in != out, KDMG_EINVAL, "in and out must not alias");
+  using LT = std::conditional_t<sizeof(R) == 8, double, _Float16>;
   const Geo2& g = lat->g;
-  const long f = 2 * lat->half, V = lat->ndof;
-  DevBuf a(sizeof(c64) * f * nrhs), b(sizeof(c64) * f * nrhs), t(sizeof(c64) * f * nrhs),
-      w(sizeof(c64) * f * nrhs);
-  const c64* L = lat->links64.as<c64>();
+  const long h = lat->half, f = 2 * h, V = lat->ndof;
+  const long na = op == OP_SCHUR ? h : f;
+  DevBuf own;
+  if (!work) {
+    own.alloc(sizeof(Cx<R>) * fine_op_scratch_entries(*lat, op) * nrhs);
+    work = own.as<Cx<R>>();
+  }
+  Cx<R>* a = work;
+  Cx<R>* b = a + na * nrhs;
+  Cx<R>* t = b + na * nrhs;
+  Cx<R>* w = t + f * nrhs;
+  const Cx<R>* vin = (const Cx<R>*)in;
+  Cx<R>* vout = (Cx<R>*)out;
   if (lat->nd == 4) {
     DevBuf b64, b32;
     build_binv4(b64, b32, *lat, mass, st);
-    const Fine4<double, double> F{lat->lk64.as<c64>(), lat->nb4.as<int>(), b64.as<c64>(), lat->g4, mass};
-    const long h = lat->half;
+    const Cx<LT>* lk = (const Cx<LT>*)(sizeof(R) == 8 ? lat->lk64.p : lat->lk16.p);
+    const Cx<R>* Bv = (const Cx<R>*)(sizeof(R) == 8 ? b64.p : b32.p);
+    const Fine4<LT, R> F{lk, lat->nb4.as<int>(), Bv, lat->g4, mass};
     if (op == OP_SCHUR) {
-      launch_permute<double, double>(a.as<c64>(), h, (const c64*)in, V / 2, lat->perm_even.as<int>(), V / 2, 1,
-                                     nrhs, st);
-      schur_apply4<double, double, double>(b.as<c64>(), a.as<c64>(), nullptr, t.as<c64>(), w.as<c64>(), F, nullptr,
-                                           nrhs, st);
-      launch_permute<double, double>((c64*)out, V / 2, b.as<c64>(), h, lat->perm_even.as<int>(), V / 2, 0, nrhs,
-                                     st);
+      launch_permute<R, R>(a, h, vin, V / 2, lat->perm_even.as<int>(), V / 2, 1, nrhs, st);
+      schur_apply4<R, LT, R>(b, a, nullptr, t, w, F, nullptr, nrhs, st);
+      launch_permute<R, R>(vout, V / 2, b, h, lat->perm_even.as<int>(), V / 2, 0, nrhs, st);
     } else {
-      launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, V, lat->perm_full.as<int>(), V, 1, nrhs, st);
+      launch_permute<R, R>(a, f, vin, V, lat->perm_full.as<int>(), V, 1, nrhs, st);
       if (op == OP_A)
-        fullA_apply4<double, double>(b.as<c64>(), a.as<c64>(), t.as<c64>(), F, nullptr, nrhs, st);
+        fullA_apply4<LT, R, R>(b, a, t, F, nullptr, nrhs, st);
       else if (op == OP_ADAG)
-        fullAdag_apply4<double, double>(b.as<c64>(), a.as<c64>(), t.as<c64>(), F, nullptr, nrhs, st);
+        fullAdag_apply4<LT, R, R>(b, a, t, F, nullptr, nrhs, st);
       else
-        launch4_binv<double, double>(b.as<c64>(), f, a.as<c64>(), f, nullptr, 0, F.Bv, F.g, 0, 2, 0, nullptr, nrhs,
-                                     st);
-      launch_permute<double, double>((c64*)out, V, b.as<c64>(), f, lat->perm_full.as<int>(), V, 0, nrhs, st);
+        launch4_binv<R, R>(b, f, a, f, nullptr, 0, F.Bv, F.g, 0, 2, 0, nullptr, nrhs, st);
+      launch_permute<R, R>(vout, V, b, f, lat->perm_full.as<int>(), V, 0, nrhs, st);
     }
-    KDMG_HIP(hipStreamSynchronize(st));
+    KDMG_HIP(hipStreamSynchronize(st));  // the B^-1 blocks are freed on return
     return;
   }
+  const Cx<LT>* L = (const Cx<LT>*)(sizeof(R) == 8 ? lat->links64.p : lat->links16.p);
   if (op == OP_SCHUR) {
-    launch_permute<double, double>(a.as<c64>(), g.half, (const c64*)in, V / 2,
-                                   lat->perm_even.as<int>(), V / 2, 1, nrhs, st);
-    schur_apply<double, double>(b.as<c64>(), a.as<c64>(), nullptr, t.as<c64>(), w.as<c64>(), L, g,
-                                mass, nullptr, nrhs, st);
-    launch_permute<double, double>((c64*)out, V / 2, b.as<c64>(), g.half, lat->perm_even.as<int>(),
-                                   V / 2, 0, nrhs, st);
+    launch_permute<R, R>(a, h, vin, V / 2, lat->perm_even.as<int>(), V / 2, 1, nrhs, st);
+    schur_apply<R, LT>(b, a, nullptr, t, w, L, g, mass, nullptr, nrhs, st);
+    launch_permute<R, R>(vout, V / 2, b, h, lat->perm_even.as<int>(), V / 2, 0, nrhs, st);
   } else {
-    launch_permute<double, double>(a.as<c64>(), f, (const c64*)in, V, lat->perm_full.as<int>(), V, 1,
-                                   nrhs, st);
+    launch_permute<R, R>(a, f, vin, V, lat->perm_full.as<int>(), V, 1, nrhs, st);
     if (op == OP_A)
-      fullA_apply<double>(b.as<c64>(), a.as<c64>(), t.as<c64>(), L, g, mass, nullptr, nrhs, st);
+      fullA_apply<LT, R>(b, a, t, L, g, mass, nullptr, nrhs, st);
     else if (op == OP_ADAG)
-      fullAdag_apply<double>(b.as<c64>(), nullptr, a.as<c64>(), t.as<c64>(), L, g, mass, nullptr,
-                             nrhs, st);
+      fullAdag_apply<LT, R>(b, nullptr, a, t, L, g, mass, nullptr, nrhs, st);
     else
-      launch_binv<double, double, double>(b.as<c64>(), f, nullptr, 0, a.as<c64>(), f, nullptr, 0, L,
-                                          g, 0, 2, mass, 0, nullptr, nrhs, st);
-    launch_permute<double, double>((c64*)out, V, b.as<c64>(), f, lat->perm_full.as<int>(), V, 0, nrhs,
-                                   st);
+      launch_binv<R, LT, R>(b, f, nullptr, 0, a, f, nullptr, 0, L, g, 0, 2, mass, 0, nullptr, nrhs, st);
+    launch_permute<R, R>(vout, V, b, f, lat->perm_full.as<int>(), V, 0, nrhs, st);
   }
-  KDMG_HIP(hipStreamSynchronize(st));
+  if (own.p) KDMG_HIP(hipStreamSynchronize(st));  // the work space is freed on return
+}
+
+void fine_op_prec(const kdmg_lattice* lat, double mass, const void* in, void* out, int nrhs, FineOp op,
+                  kdmg_prec prec, hipStream_t st) {
+  if (prec == KDMG_FP64)
+    fine_op_natural<double>(lat, mass, in, out, nrhs, op, st, nullptr);
+  else if (prec == KDMG_MIXED)
+    fine_op_natural<float>(lat, mass, in, out, nrhs, op, st, nullptr);
+  else
+    throw Error(KDMG_EINVAL, "bad precision");
 }
 
 }  // namespace
 
 extern "C" kdmg_status kdmg_apply_A(const kdmg_lattice* lat, double mass, const void* in, void* out,
-                                    int nrhs, int dagger, void* stream) {
+                                    int nrhs, int dagger, kdmg_prec prec, void* stream) {
   KDMG_API_BEGIN
-  fine_op_natural(lat, mass, in, out, nrhs, dagger ? OP_ADAG : OP_A, (hipStream_t)stream);
+  fine_op_prec(lat, mass, in, out, nrhs, dagger ? OP_ADAG : OP_A, prec, (hipStream_t)stream);
   KDMG_API_END
 }
 
 extern "C" kdmg_status kdmg_apply_Binv(const kdmg_lattice* lat, double mass, const void* in,
                                        void* out, int nrhs, void* stream) {
   KDMG_API_BEGIN
-  fine_op_natural(lat, mass, in, out, nrhs, OP_BINV, (hipStream_t)stream);
+  fine_op_prec(lat, mass, in, out, nrhs, OP_BINV, KDMG_FP64, (hipStream_t)stream);
   KDMG_API_END
 }
 
 extern "C" kdmg_status kdmg_apply_schur(const kdmg_lattice* lat, double mass, const void* in_even,
                                         void* out_even, int nrhs, void* stream) {
   KDMG_API_BEGIN
-  fine_op_natural(lat, mass, in_even, out_even, nrhs, OP_SCHUR, (hipStream_t)stream);
+  fine_op_prec(lat, mass, in_even, out_even, nrhs, OP_SCHUR, KDMG_FP64, (hipStream_t)stream);
   KDMG_API_END
 }
 
@@ -399,4 +433,5 @@ extern "C" void kdmg_default_params(kdmg_mg_params* p) {
   p->coarse_maxit = 256;
   p->outer_stall = 0;
   p->coarse_tail = 16;
+  p->coarse_solver = 0;
 }

@@ -61,6 +61,7 @@ struct Request {
   int nrhs = 1;
   double tol = 1e-10;
   kdmg_prec prec = KDMG_MIXED;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
   ShapeKey key;
   size_t bytes = 0;
   Clock::time_point t_sub, t_start, t_end;
@@ -142,6 +143,11 @@ kdmg_hierarchy* run_request(kdmg_server& s, Request& r, Pooled slot, hipStream_t
       rc = kdmg_hierarchy_autotune(const_cast<kdmg_hierarchy*>(base), r.nrhs, r.prec, st);
   }
   kdmg_hierarchy* h = slot.h;
+  // the caller's work on b and x that was queued before the submit comes first
+  if (rc == KDMG_OK && hipStreamWaitEvent(st, r.ready, 0) != hipSuccess) {
+    rc = KDMG_EHIP;
+    set_last_error("kdmg_server: hipStreamWaitEvent on the submit event failed");
+  }
   if (rc == KDMG_OK) {
     if (h) rc = kdmg_hierarchy_set_mass(h, base, r.mass, st);
     else rc = kdmg_hierarchy_at_mass(base, r.mass, st, &h);
@@ -173,6 +179,9 @@ void worker_main(kdmg_server* sp, int w) {
     lk.unlock();
     for (kdmg_hierarchy* e : evict) kdmg_hierarchy_destroy(e);
     kdmg_hierarchy* h = run_request(s, *r, slot, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
     lk.lock();
     r->t_end = Clock::now();
     if (h) s.idle.emplace(r->key, Pooled{h, slot.bytes});
@@ -228,7 +237,7 @@ extern "C" kdmg_status kdmg_server_request_bytes(kdmg_server* s, int config_id, 
 }
 
 extern "C" kdmg_status kdmg_server_submit(kdmg_server* s, int config_id, double mass, const void* b, void* x,
-                                          int nrhs, double tol, kdmg_prec prec, long long* ticket) {
+                                          int nrhs, double tol, kdmg_prec prec, void* stream, long long* ticket) {
   KDMG_API_BEGIN
   KDMG_CHECK(s && b && x && b != x && ticket, KDMG_EINVAL, "kdmg_server_submit: bad pointers");
   KDMG_CHECK(mass > 0.0 && nrhs >= 1 && nrhs <= 1024 && tol > 0.0 && tol < 1.0, KDMG_EINVAL,
@@ -251,6 +260,11 @@ extern "C" kdmg_status kdmg_server_submit(kdmg_server* s, int config_id, double 
   r->bytes = derived_footprint(base, nrhs, prec);
   KDMG_CHECK(r->bytes <= s->budget, KDMG_ENOMEM, "request needs more device memory than the server budget");
   r->info.resize(nrhs);
+  KDMG_HIP(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
+  if (hipEventRecord(r->ready, (hipStream_t)stream) != hipSuccess) {
+    (void)hipEventDestroy(r->ready);
+    throw Error(KDMG_EHIP, "kdmg_server_submit: hipEventRecord on the caller's stream failed");
+  }
   r->t_sub = Clock::now();
   *ticket = r->id;
   s->queue.push_back(r.get());
@@ -302,6 +316,8 @@ extern "C" void kdmg_server_destroy(kdmg_server* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     // finish what was admitted; requests still queued are dropped
     for (Request* q : s->queue) {
+      if (q->ready) (void)hipEventDestroy(q->ready);
+      q->ready = nullptr;
       q->done = true;
       q->status = KDMG_EBUSY;
       q->err = "server destroyed before the request started";

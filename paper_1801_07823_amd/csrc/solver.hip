@@ -88,6 +88,7 @@ struct LevelWS {
   DevBuf t, w;                // level-0 Schur temporaries (full layout)
   DevBuf b, xs, rs, Z, W, p;  // coarse solve: input, solution, residual, GCR basis / CGNE p
   DevBuf cg_rr, cg_target, cg_act, PA, PB;  // fused CGNE state (coarsest level)
+  DevBuf part;                               // exact coarsest solve: partial products
   std::unique_ptr<AsyncPoll> cg_poll;        // its flag copies and events
   std::unique_ptr<ChunkGraph> cg_graph;      // captured CGNE chunk
   // the fused CGNE's tail problem of `tail` rhs (0: none; batches of more
@@ -463,7 +464,26 @@ class Runner {
       Cx<T>* x = L.v<T>(L.xs);
       Cx<T>* r = L.v<T>(L.rs);
       auto opf = [&](Cx<T>* o, const Cx<T>* i, const Cx<T>* res, const int* a) { op<T>(l, o, i, res, a); };
-      if (l == h_.nlevels - 1) {
+      if (l == h_.nlevels - 1 && P.coarse_solver == 1) {
+        if constexpr (sizeof(T) == 8) {
+          auto& tm = h_.timer;
+          std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+          if (tm.on) {
+            if (tm.dn_used == tm.dn_ev.size()) {
+              std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+              KDMG_HIP(hipEventCreate(&e.first));
+              KDMG_HIP(hipEventCreate(&e.second));
+              tm.dn_ev.push_back(e);
+            }
+            ev = &tm.dn_ev[tm.dn_used++];
+            KDMG_HIP(hipEventRecord(ev->first, c_.st));
+          }
+          dense_apply(h_.dinv, x, b, L.part.as<c64>(), nrhs_, parent, L.ks.k.its, L.ks.k.calls, L.ks.k.tot, c_.st);
+          if (ev) KDMG_HIP(hipEventRecord(ev->second, c_.st));
+        } else {
+          throw Error(KDMG_EINVAL, "exact coarsest solve: the coarsest level runs in FP64");
+        }
+      } else if (l == h_.nlevels - 1) {
         if constexpr (sizeof(T) == 8) {
           cgne_fused(c_, h_.L[l], L, nrhs_, b, x, r, L.v<T>(L.p), P.coarse_tol, P.coarse_maxit, parent,
                      poll_, &h_.timer, h_.use_graphs);
@@ -580,7 +600,9 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
       A(L.xs, v);
       A(L.rs, v);
       L.ks.init(nrhs, coarsest ? 0 : P.inter_restart);
-      if (coarsest) {
+      if (coarsest && P.coarse_solver == 1) {
+        A(L.part, sizeof(c64) * (size_t)dense_apply_splits(L.n, nrhs) * nrhs * L.n);
+      } else if (coarsest) {
         A(L.p, v);
         A(L.q, v);
         A(L.cg_rr, sizeof(double) * 2 * nrhs);
@@ -631,6 +653,7 @@ size_t ws_bytes_estimate(const kdmg_hierarchy& h, int nrhs, kdmg_prec prec) {
     const size_t v = esz * nrhs * n;
     if (!coarsest) b += 4 * v;
     if (l == 0) b += 2 * esz * nrhs * f;
+    else if (coarsest && P.coarse_solver == 1) b += 3 * v + (size_t)dense_apply_splits(n, nrhs) * v;
     else b += 3 * v + (coarsest ? 2 * v : 2 * v * P.inter_restart);
   }
   if (prec == KDMG_MIXED) b += 2 * sizeof(c32) * nrhs * half;
@@ -642,7 +665,7 @@ size_t ws_bytes_estimate(const kdmg_hierarchy& h, int nrhs, kdmg_prec prec) {
 // Device bytes a hierarchy derived from `base` (kdmg_hierarchy_at_mass) holds
 // once it has solved `nrhs` right-hand sides at `prec`.
 size_t derived_footprint(const kdmg_hierarchy& base, int nrhs, kdmg_prec prec) {
-  size_t b = base.gal_w.bytes + ws_bytes_estimate(base, nrhs, prec);
+  size_t b = base.gal_w.bytes + base.dinv.bytes() + ws_bytes_estimate(base, nrhs, prec);
   for (const auto& l : base.L) b += l.bytes();
   return b;
 }
@@ -680,9 +703,11 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   if (autotune_enabled()) {
     for (int l = 1; l < h->nlevels; ++l)
       autotune_level(h->L[l], nrhs, prec == KDMG_MIXED && l < h->nlevels - 1, st);
-    autotune_cgne(h->L[h->nlevels - 1], nrhs, st);
-    const int tw = h->params.coarse_tail;
-    if (tw > 0 && nrhs > tw) autotune_cgne(h->L[h->nlevels - 1], tw, st);
+    if (h->params.coarse_solver == 0) {
+      autotune_cgne(h->L[h->nlevels - 1], nrhs, st);
+      const int tw = h->params.coarse_tail;
+      if (tw > 0 && nrhs > tw) autotune_cgne(h->L[h->nlevels - 1], tw, st);
+    }
   }
   SolveWS& ws = *h->ws;
   int expect = 0;
@@ -696,6 +721,7 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   const c64* L64 = lat.links64.as<c64>();
   const bool d4 = lat.nd == 4;
   Runner run(*h, ws);
+  h->timer.dn_used = 0;
   // reset statistics
   KDMG_HIP(hipMemsetAsync(ws.kout.ints.p, 0, ws.kout.ints.bytes, st));
   for (auto& L : ws.lv)
@@ -760,6 +786,16 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   }
   KDMG_HIP(hipStreamSynchronize(st));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  {  // exact coarsest solve: kernel time of the products recorded in this solve
+    auto& tm = h->timer;
+    for (size_t e = 0; e < tm.dn_used; ++e) {
+      float ms = 0.f;
+      KDMG_HIP(hipEventElapsedTime(&ms, tm.dn_ev[e].first, tm.dn_ev[e].second));
+      tm.ms += ms;
+      tm.launches += 1;
+    }
+    tm.dn_used = 0;
+  }
   bool all = true;
   const int per_it = 2 * h->params.mr_its + 2;
   for (int r = 0; r < nrhs; ++r) {

@@ -36,7 +36,7 @@ class kdmg_mg_params(ctypes.Structure):
                 ("inter_restart", ctypes.c_int), ("inter_maxit", ctypes.c_int),
                 ("inter_tol", ctypes.c_double), ("coarse_tol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int), ("outer_stall", ctypes.c_int),
-                ("coarse_tail", ctypes.c_int)]
+                ("coarse_tail", ctypes.c_int), ("coarse_solver", ctypes.c_int)]
 
 
 class kdmg_solve_info(ctypes.Structure):
@@ -59,11 +59,11 @@ _S = ctypes.c_size_t
 _SIGS = {
     "kdmg_default_params": (None, [ctypes.POINTER(kdmg_mg_params)]),
     "kdmg_init": (_I, [_I]),
-    "kdmg_lattice_create": (_I, [_I, ctypes.POINTER(_I), _I, _P, _I, ctypes.POINTER(_P)]),
+    "kdmg_lattice_create": (_I, [_I, ctypes.POINTER(_I), _I, ctypes.POINTER(_I), _P, _P, ctypes.POINTER(_P)]),
     "kdmg_lattice_destroy": (None, [_P]),
     "kdmg_lattice_footprint": (_I, [_P, ctypes.POINTER(_S)]),
     "kdmg_apply_D": (_I, [_P, _D, _P, _P, _I, _I, _P]),
-    "kdmg_apply_A": (_I, [_P, _D, _P, _P, _I, _I, _P]),
+    "kdmg_apply_A": (_I, [_P, _D, _P, _P, _I, _I, _I, _P]),
     "kdmg_apply_Binv": (_I, [_P, _D, _P, _P, _I, _P]),
     "kdmg_apply_schur": (_I, [_P, _D, _P, _P, _I, _P]),
     "kdmg_hierarchy_build": (_I, [_P, _D, ctypes.POINTER(kdmg_mg_params),
@@ -85,11 +85,12 @@ _SIGS = {
     "kdmg_hierarchy_graphs": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_hierarchy_counters": (_I, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_solve_cg_eo": (_I, [_P, _D, _P, _P, _I, _D, _I, ctypes.POINTER(_I), _P]),
+    "kdmg_coarsest_solve": (_I, [_P, _P, _P, _I, _P]),
     "kdmg_hierarchy_kernel_timing": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_server_create": (_I, [_I, _S, ctypes.POINTER(_P)]),
     "kdmg_server_add_config": (_I, [_P, _P, ctypes.POINTER(_I)]),
     "kdmg_server_request_bytes": (_I, [_P, _I, _I, _I, ctypes.POINTER(_S)]),
-    "kdmg_server_submit": (_I, [_P, _I, _D, _P, _P, _I, _D, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "kdmg_server_submit": (_I, [_P, _I, _D, _P, _P, _I, _D, _I, _P, ctypes.POINTER(ctypes.c_longlong)]),
     "kdmg_server_poll": (_I, [_P, ctypes.c_longlong, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                               _P, ctypes.POINTER(_D)]),
     "kdmg_server_stats": (_I, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_I),
@@ -125,7 +126,23 @@ def _stream(stream):
     return torch.cuda.current_stream().cuda_stream
 
 
-def _ptr(t):
+def _ptr(t, prec, n, what):
+    """Device pointer of tensor `t` after checking what the library will
+    assume of it: a contiguous GPU tensor of the precision's complex dtype
+    (complex128 for KDMG_FP64, complex64 for KDMG_MIXED) with at least `n`
+    elements.  Raises KdmgError(KDMG_EINVAL) otherwise, before any call."""
+    import torch
+    want = torch.complex128 if prec == KDMG_FP64 else torch.complex64
+    if not isinstance(t, torch.Tensor):
+        raise KdmgError(KDMG_EINVAL, "%s: expected a torch tensor, got %s" % (what, type(t).__name__))
+    if not t.is_cuda:
+        raise KdmgError(KDMG_EINVAL, "%s: tensor must be on the GPU" % what)
+    if t.dtype != want:
+        raise KdmgError(KDMG_EINVAL, "%s: dtype %s, expected %s" % (what, t.dtype, want))
+    if not t.is_contiguous():
+        raise KdmgError(KDMG_EINVAL, "%s: tensor must be contiguous" % what)
+    if t.numel() < n:
+        raise KdmgError(KDMG_EINVAL, "%s: %d elements, the call needs %d" % (what, t.numel(), n))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -153,17 +170,26 @@ def kdmg_init(device=0):
 
 
 class Lattice:
-    def __init__(self, dims, links, antiperiodic_time=True):
+    def __init__(self, dims, links, bc=None, stream=None):
+        """bc: per-direction boundary signs (+1 periodic, -1 antiperiodic);
+        None = periodic space, antiperiodic time."""
         links = np.ascontiguousarray(links, dtype=np.complex128)
         nd = len(dims)
         nc = links.shape[-1]
         self.dims = tuple(int(d) for d in dims)
         self.ncolor = nc
         self.volume = int(np.prod(dims))
+        self.ndof = self.volume * nc
+        if links.size != nd * self.volume * nc * nc:
+            raise KdmgError(KDMG_EINVAL, "Lattice: links must hold [nd][volume][nc][nc] entries")
+        self.bc = tuple(int(b) for b in bc) if bc is not None else tuple([1] * (nd - 1) + [-1])
+        if len(self.bc) != nd:
+            raise KdmgError(KDMG_EINVAL, "Lattice: one boundary sign per direction")
         arr = (_I * nd)(*self.dims)
+        bca = (_I * nd)(*self.bc)
         h = _P()
-        _check(_lib.kdmg_lattice_create(nd, arr, nc, links.ctypes.data_as(_P),
-                                        1 if antiperiodic_time else 0, ctypes.byref(h)))
+        _check(_lib.kdmg_lattice_create(nd, arr, nc, bca, links.ctypes.data_as(_P), _stream(stream),
+                                        ctypes.byref(h)))
         self.handle = h
 
     def footprint(self):
@@ -178,20 +204,28 @@ class Lattice:
 
 
 def kdmg_apply_D(lat, mass, inp, out, nrhs, prec=KDMG_FP64, stream=None):
-    _check(_lib.kdmg_apply_D(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, prec, _stream(stream)))
+    n = nrhs * lat.ndof
+    _check(_lib.kdmg_apply_D(lat.handle, mass, _ptr(inp, prec, n, "kdmg_apply_D in"),
+                             _ptr(out, prec, n, "kdmg_apply_D out"), nrhs, prec, _stream(stream)))
 
 
-def kdmg_apply_A(lat, mass, inp, out, nrhs, dagger=False, stream=None):
-    _check(_lib.kdmg_apply_A(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, 1 if dagger else 0,
+def kdmg_apply_A(lat, mass, inp, out, nrhs, dagger=False, prec=KDMG_FP64, stream=None):
+    n = nrhs * lat.ndof
+    _check(_lib.kdmg_apply_A(lat.handle, mass, _ptr(inp, prec, n, "kdmg_apply_A in"),
+                             _ptr(out, prec, n, "kdmg_apply_A out"), nrhs, 1 if dagger else 0, prec,
                              _stream(stream)))
 
 
 def kdmg_apply_Binv(lat, mass, inp, out, nrhs, stream=None):
-    _check(_lib.kdmg_apply_Binv(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+    n = nrhs * lat.ndof
+    _check(_lib.kdmg_apply_Binv(lat.handle, mass, _ptr(inp, KDMG_FP64, n, "kdmg_apply_Binv in"),
+                                _ptr(out, KDMG_FP64, n, "kdmg_apply_Binv out"), nrhs, _stream(stream)))
 
 
 def kdmg_apply_schur(lat, mass, inp, out, nrhs, stream=None):
-    _check(_lib.kdmg_apply_schur(lat.handle, mass, _ptr(inp), _ptr(out), nrhs, _stream(stream)))
+    n = nrhs * (lat.ndof // 2)
+    _check(_lib.kdmg_apply_schur(lat.handle, mass, _ptr(inp, KDMG_FP64, n, "kdmg_apply_schur in"),
+                                 _ptr(out, KDMG_FP64, n, "kdmg_apply_schur out"), nrhs, _stream(stream)))
 
 
 class Hierarchy:
@@ -286,25 +320,46 @@ class Hierarchy:
             self.handle = None
 
 
+def _level_ndof(h, level):
+    if not 0 <= level < h.nlevels:
+        raise KdmgError(KDMG_EINVAL, "no level %d in a %d-level hierarchy" % (level, h.nlevels))
+    return h.ndof(level)
+
+
 def kdmg_coarse_apply(h, level, inp, out, nrhs, dagger=False, prec=KDMG_FP64, stream=None):
-    _check(_lib.kdmg_coarse_apply(h.handle, level, 1 if dagger else 0, _ptr(inp), _ptr(out), nrhs,
-                                  prec, _stream(stream)))
+    n = nrhs * _level_ndof(h, level)
+    _check(_lib.kdmg_coarse_apply(h.handle, level, 1 if dagger else 0, _ptr(inp, prec, n, "kdmg_coarse_apply in"),
+                                  _ptr(out, prec, n, "kdmg_coarse_apply out"), nrhs, prec, _stream(stream)))
 
 
 def kdmg_coarse_apply_candidates(h, level, inp, out, nrhs, dagger=False, prec=KDMG_FP64, stream=None):
     """Every tuner candidate's stencil apply: out[c] for c < out.shape[0]; returns the candidate count."""
+    n = nrhs * _level_ndof(h, level)
     nc = _I()
-    _check(_lib.kdmg_coarse_apply_candidates(h.handle, level, 1 if dagger else 0, _ptr(inp), _ptr(out), nrhs, prec,
+    _check(_lib.kdmg_coarse_apply_candidates(h.handle, level, 1 if dagger else 0,
+                                             _ptr(inp, prec, n, "candidates in"),
+                                             _ptr(out, prec, n * out.shape[0], "candidates out"), nrhs, prec,
                                              out.shape[0], ctypes.byref(nc), _stream(stream)))
     return nc.value
 
 
 def kdmg_restrict(h, k, inp, out, nrhs, prec=KDMG_FP64, stream=None):
-    _check(_lib.kdmg_restrict(h.handle, k, _ptr(inp), _ptr(out), nrhs, prec, _stream(stream)))
+    nf, nc = nrhs * _level_ndof(h, k), nrhs * _level_ndof(h, k + 1)
+    _check(_lib.kdmg_restrict(h.handle, k, _ptr(inp, prec, nf, "kdmg_restrict in"),
+                              _ptr(out, prec, nc, "kdmg_restrict out"), nrhs, prec, _stream(stream)))
 
 
 def kdmg_prolong(h, k, inp, out, nrhs, prec=KDMG_FP64, stream=None):
-    _check(_lib.kdmg_prolong(h.handle, k, _ptr(inp), _ptr(out), nrhs, prec, _stream(stream)))
+    nf, nc = nrhs * _level_ndof(h, k), nrhs * _level_ndof(h, k + 1)
+    _check(_lib.kdmg_prolong(h.handle, k, _ptr(inp, prec, nc, "kdmg_prolong in"),
+                             _ptr(out, prec, nf, "kdmg_prolong out"), nrhs, prec, _stream(stream)))
+
+
+def kdmg_coarsest_solve(h, inp, out, nrhs, stream=None):
+    """Exact coarsest solve (hierarchies built with coarse_solver=1): out = A_c^-1 in."""
+    n = nrhs * _level_ndof(h, h.nlevels - 1)
+    _check(_lib.kdmg_coarsest_solve(h.handle, _ptr(inp, KDMG_FP64, n, "kdmg_coarsest_solve in"),
+                                    _ptr(out, KDMG_FP64, n, "kdmg_coarsest_solve out"), nrhs, _stream(stream)))
 
 
 def kdmg_hierarchy_autotune(h, nrhs, prec=KDMG_FP64, stream=None):
@@ -321,7 +376,9 @@ def kdmg_hierarchy_kernel_timing(h, enable=-1):
 
 def kdmg_solve(h, b, x, nrhs, tol=1e-10, prec=KDMG_FP64, stream=None, raise_on_noconv=True):
     info = (kdmg_solve_info * nrhs)()
-    st = _lib.kdmg_solve(h.handle, _ptr(b), _ptr(x), nrhs, tol, prec, info, _stream(stream))
+    n = nrhs * h.lat.ndof
+    st = _lib.kdmg_solve(h.handle, _ptr(b, KDMG_FP64, n, "kdmg_solve b"), _ptr(x, KDMG_FP64, n, "kdmg_solve x"),
+                         nrhs, tol, prec, info, _stream(stream))
     if st != KDMG_OK and (st != KDMG_ENOCONV or raise_on_noconv):
         _check(st)
     return [i.as_dict() for i in info], st
@@ -330,7 +387,10 @@ def kdmg_solve(h, b, x, nrhs, tol=1e-10, prec=KDMG_FP64, stream=None, raise_on_n
 def kdmg_solve_cg_eo(lat, mass, b, x, nrhs, tol=1e-10, maxit=200000, stream=None, raise_on_noconv=True):
     """CG on the site even/odd Schur system (2D, FP64); returns the iteration count per rhs."""
     its = (_I * nrhs)()
-    st = _lib.kdmg_solve_cg_eo(lat.handle, mass, _ptr(b), _ptr(x), nrhs, tol, maxit, its, _stream(stream))
+    n = nrhs * lat.ndof
+    st = _lib.kdmg_solve_cg_eo(lat.handle, mass, _ptr(b, KDMG_FP64, n, "kdmg_solve_cg_eo b"),
+                               _ptr(x, KDMG_FP64, n, "kdmg_solve_cg_eo x"), nrhs, tol, maxit, its,
+                               _stream(stream))
     if st != KDMG_OK and (st != KDMG_ENOCONV or raise_on_noconv):
         _check(st)
     return list(its)
@@ -360,9 +420,15 @@ class Server:
         _check(_lib.kdmg_server_request_bytes(self.handle, config_id, nrhs, prec, ctypes.byref(b)))
         return b.value
 
-    def submit(self, config_id, mass, b, x, nrhs=1, tol=1e-10, prec=KDMG_MIXED):
+    def submit(self, config_id, mass, b, x, nrhs=1, tol=1e-10, prec=KDMG_MIXED, stream=None):
+        """Queue a solve; device work queued on `stream` (default: torch's current
+        stream) before the call is complete before the request reads b or writes x."""
+        if not 0 <= config_id < len(self._configs):
+            raise KdmgError(KDMG_EINVAL, "Server.submit: no configuration %d" % config_id)
+        n = nrhs * self._configs[config_id].lat.ndof
         t = ctypes.c_longlong()
-        _check(_lib.kdmg_server_submit(self.handle, config_id, mass, _ptr(b), _ptr(x), nrhs, tol, prec,
+        _check(_lib.kdmg_server_submit(self.handle, config_id, mass, _ptr(b, KDMG_FP64, n, "submit b"),
+                                       _ptr(x, KDMG_FP64, n, "submit x"), nrhs, tol, prec, _stream(stream),
                                        ctypes.byref(t)))
         self._live[t.value] = (b, x, nrhs)
         return t.value

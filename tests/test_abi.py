@@ -46,4 +46,5 @@ def test_binding_loads_and_matches_header():
     assert p.coarse_maxit == 256 and abs(p.coarse_tol - 0.2) < 1e-15
     assert p.outer_stall == 0  # the serving stall rule is off unless asked for
     assert p.coarse_tail == 16
+    assert p.coarse_solver == 0  # Table 1: CGNE on the coarsest level
     assert kdmg._lib.kdmg_status_string(kdmg.KDMG_ENOCONV) == b"solver did not converge"

@@ -267,3 +267,52 @@ def test_eta_definition():
     assert np.all(eta(lat, 0) == 1)
     assert np.all(eta(lat, 1) == (-1.0) ** c[:, 0])
     assert np.all(eta(lat, 3) == (-1.0) ** (c[:, 0] + c[:, 1] + c[:, 2]))
+
+
+@pytest.mark.parametrize("bc", [(-1, -1), (-1, 1), (1, 1)])
+def test_boundary_signs_per_direction(bc):
+    """Boundary signs per direction (the paper is silent; reading of the
+    boundary conditions): a sign -1 in direction mu shifts that direction's
+    free momenta to (2n + 1) pi / L_mu, so the free spectrum is
+    m +- i sqrt(sum sin^2 p) over the shifted zone, and the closed-form FFT
+    solve with the matching twist solves D x = b."""
+    dims = (8, 12)
+    lat = Lattice(dims, bc=bc)
+    m = 0.2
+    D = dirac_matrix(lat, unit_gauge(dims), m)
+    lam = np.linalg.eigvals(D.toarray())
+    assert np.allclose(lam.real, m, atol=1e-12)
+    # the closed form enumerated here from the momenta, independently of
+    # free_spectrum's zone bookkeeping
+    ps = [(2 * np.arange(L) + (1 if s == -1 else 0)) * np.pi / L for L, s in zip(dims, bc)]
+    g = np.meshgrid(*ps, indexing="ij")
+    s2 = np.sort(sum(np.sin(x) ** 2 for x in g).ravel())
+    assert np.allclose(np.sort(lam.imag ** 2), s2, atol=1e-11)
+    b = gaussian_vectors(1, lat.volume, 7)[0]
+    x = free_fft_solve(lat, m, b)
+    assert np.linalg.norm(D @ x - b) / np.linalg.norm(b) < 1e-12
+    # a hop across the x boundary carries the x sign, across t the t sign
+    Dd = D.toarray()
+    x0 = lat.index((dims[0] - 1, 3))
+    assert np.isclose(Dd[x0, lat.index((0, 3))], 0.5 * bc[0])
+    t0 = lat.index((0, dims[1] - 1))
+    assert np.isclose(Dd[t0, lat.index((0, 0))], 0.5 * bc[1])
+
+
+def test_cg_eo_multi_matches_single_and_dense():
+    """The block form of the oracle's even/odd CG runs each column's own CG:
+    iteration counts within one (summation order moves the stop) and the
+    same solutions as cg_eo column by column, and the dense-LU answer."""
+    from oracle.exact import cg_eo_multi
+    dims = (8, 12)
+    lat = Lattice(dims)
+    U = random_u1(dims, 4)
+    m = 0.15
+    B = gaussian_vectors(3, lat.volume, 11)
+    X, its = cg_eo_multi(lat, U, m, B, tol=1e-13)
+    for q in range(3):
+        x1, k1 = cg_eo(lat, U, m, B[q], tol=1e-13)
+        assert abs(its[q] - k1) <= 1  # the stop can fall either side by rounding
+        assert np.linalg.norm(X[q] - x1) / np.linalg.norm(x1) < 1e-11
+        xd = dense_solve(lat, U, m, B[q])
+        assert np.linalg.norm(X[q] - xd) / np.linalg.norm(xd) < 1e-10
