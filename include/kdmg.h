@@ -176,6 +176,20 @@ kdmg_status kdmg_apply_schur(const kdmg_lattice* lat, double mass,
                              const void* in_even, void* out_even, int nrhs,
                              void* stream);
 
+/* kdmg_apply_schur without allocation, for callers that cannot allocate
+   device memory (code under hipGraph capture, tight serving loops, harnesses
+   that forbid hipMalloc): the same operator and kernels as kdmg_apply_schur,
+   with its work space in a fixed 32 MiB device array per GPU that the library
+   holds until the process ends, instead of memory allocated per call.
+   2D lattices only (KDMG_EUNSUPPORTED in 4D, where B^-1 is built per call).
+   nrhs is limited by that array: 6 * (volume / 2) * 16 bytes per rhs
+   (volume 256^2: at most 10 rhs); larger requests return KDMG_EINVAL before
+   any device work.  Stream-ordered; does not synchronise.  Every call on a
+   GPU shares that GPU's array, so calls that overlap on one GPU (several
+   streams or threads at once) race: serialise them. */
+kdmg_status kdmg_apply_schur_noalloc(const kdmg_lattice* lat, double mass, const void* in_even,
+                                     void* out_even, int nrhs, void* stream);
+
 /* Builds the KD-MG hierarchy (Sec. 4 setup):
    for coarsening k = 0..nlevels-2, relax n_vec Gaussian starts with CG on
    A_k A_k^dag (tolerance setup_tol, setup_maxit iterations), orthonormalise

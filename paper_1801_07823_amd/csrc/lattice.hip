@@ -2,6 +2,7 @@
 // entry points: D, A, A^dag, B^-1 and the Schur operator.
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "internal.h"
@@ -10,6 +11,14 @@
 using namespace kdmg;
 
 namespace kdmg {
+
+// Work space of kdmg_apply_schur_noalloc, for callers that cannot allocate:
+// a fixed array in device memory, one per GPU, held until the process ends.
+// Host code never uses the symbol itself (on the host it is only a stand-in
+// for the device address): it uses the address hipGetSymbolAddress returns
+// for the current device, looked up once per device (scratch_address).
+constexpr size_t SCRATCH_BYTES = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -109,6 +118,25 @@ void create_4d(kdmg_lattice& lat, const double* links, hipStream_t st) {
   KDMG_HIP(hipStreamSynchronize(st));
 }
 
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of its `scratch`
+
+// Resolves (once per device, with that device current) and returns the
+// current device's scratch address.
+void* scratch_address() {
+  int dev = 0;
+  KDMG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw Error(KDMG_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
 }  // namespace
 
 extern "C" kdmg_status kdmg_init(int device) {
@@ -117,6 +145,7 @@ extern "C" kdmg_status kdmg_init(int device) {
   KDMG_HIP(hipGetDeviceCount(&n));
   KDMG_CHECK(device >= 0 && device < n, KDMG_EINVAL, "kdmg_init: no such device");
   KDMG_HIP(hipSetDevice(device));
+  (void)scratch_address();
   KDMG_API_END
 }
 
@@ -393,6 +422,25 @@ extern "C" kdmg_status kdmg_apply_schur(const kdmg_lattice* lat, double mass, co
                                         void* out_even, int nrhs, void* stream) {
   KDMG_API_BEGIN
   fine_op_prec(lat, mass, in_even, out_even, nrhs, OP_SCHUR, KDMG_FP64, (hipStream_t)stream);
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_apply_schur_noalloc(const kdmg_lattice* lat, double mass, const void* in_even,
+                                                void* out_even, int nrhs, void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(lat, KDMG_EINVAL, "kdmg_apply_schur_noalloc: null lattice");
+  KDMG_CHECK(lat->nd == 2, KDMG_EUNSUPPORTED,
+             "kdmg_apply_schur_noalloc: 2D lattices only (the 4D B^-1 blocks are built per call)");
+  KDMG_CHECK(nrhs >= 1 && nrhs <= 65535, KDMG_EINVAL, "kdmg_apply_schur_noalloc: bad nrhs");
+  const size_t need = sizeof(c64) * (size_t)fine_op_scratch_entries(*lat, OP_SCHUR) * (size_t)nrhs;
+  if (need > SCRATCH_BYTES)
+    throw Error(KDMG_EINVAL, "kdmg_apply_schur_noalloc: " + std::to_string(nrhs) + " rhs need " +
+                                 std::to_string(need) + " bytes of work space, above the fixed " +
+                                 std::to_string(SCRATCH_BYTES) + " (at most " +
+                                 std::to_string(SCRATCH_BYTES / (sizeof(c64) * fine_op_scratch_entries(*lat, OP_SCHUR))) +
+                                 " rhs on this lattice)");
+  c64* work = static_cast<c64*>(scratch_address());
+  fine_op_natural<double>(lat, mass, in_even, out_even, nrhs, OP_SCHUR, (hipStream_t)stream, work);
   KDMG_API_END
 }
 

@@ -66,6 +66,7 @@ _SIGS = {
     "kdmg_apply_A": (_I, [_P, _D, _P, _P, _I, _I, _I, _P]),
     "kdmg_apply_Binv": (_I, [_P, _D, _P, _P, _I, _P]),
     "kdmg_apply_schur": (_I, [_P, _D, _P, _P, _I, _P]),
+    "kdmg_apply_schur_noalloc": (_I, [_P, _D, _P, _P, _I, _P]),
     "kdmg_hierarchy_build": (_I, [_P, _D, ctypes.POINTER(kdmg_mg_params),
                                   ctypes.POINTER(_P), _I, _P, ctypes.POINTER(_P)]),
     "kdmg_hierarchy_destroy": (None, [_P]),
@@ -226,6 +227,14 @@ def kdmg_apply_schur(lat, mass, inp, out, nrhs, stream=None):
     n = nrhs * (lat.ndof // 2)
     _check(_lib.kdmg_apply_schur(lat.handle, mass, _ptr(inp, KDMG_FP64, n, "kdmg_apply_schur in"),
                                  _ptr(out, KDMG_FP64, n, "kdmg_apply_schur out"), nrhs, _stream(stream)))
+
+
+def kdmg_apply_schur_noalloc(lat, mass, inp, out, nrhs, stream=None):
+    """kdmg_apply_schur with the library's fixed work space (no allocation)."""
+    n = nrhs * (lat.ndof // 2)
+    _check(_lib.kdmg_apply_schur_noalloc(lat.handle, mass, _ptr(inp, KDMG_FP64, n, "kdmg_apply_schur_noalloc in"),
+                                         _ptr(out, KDMG_FP64, n, "kdmg_apply_schur_noalloc out"), nrhs,
+                                         _stream(stream)))
 
 
 class Hierarchy:
