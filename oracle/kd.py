@@ -14,7 +14,7 @@ identity.
 import numpy as np
 import scipy.sparse as sp
 
-from .staggered import dirac_matrix, epsilon_dof
+from .staggered import dirac_matrix, dirac_matrix_naik, epsilon_dof
 
 
 def block_of_site(lat):
@@ -66,12 +66,20 @@ def block_inverse(lat, B):
 
 
 class KDOperator:
-    """The Kahler-Dirac preconditioned operator A = D B^-1 and its pieces."""
+    """The Kahler-Dirac preconditioned operator A = D B^-1 and its pieces.
 
-    def __init__(self, lat, U, m):
+    naik=True takes the Naik-improved D (eq. "freehisq").  Its three-link hops
+    always leave the KD block, so B is the plain block with its hops scaled by
+    9/8 and the new terms sit in C; but a hop from x_mu = 2n + 1 lands two
+    blocks away, in a block of the same parity, so A_ee != 1 and the
+    block-parity Schur form of the plain operator does not apply (has_schur
+    is False; the solver then iterates on the full A)."""
+
+    def __init__(self, lat, U, m, naik=False):
         self.lat = lat
         self.m = float(m)
-        self.D = dirac_matrix(lat, U, m)
+        self.naik = bool(naik)
+        self.D = dirac_matrix_naik(lat, U, m) if naik else dirac_matrix(lat, U, m)
         self.B, self.C = split_B_C(lat, self.D)
         self.Binv = block_inverse(lat, self.B)
         n = self.D.shape[0]
@@ -84,9 +92,10 @@ class KDOperator:
         self.A_eo = A[self.even][:, self.odd].tocsr()
         self.A_oe = A[self.odd][:, self.even].tocsr()
         ne = self.even.size
+        self.has_schur = not self.naik
         # Schur complement on even KD blocks (Table 1, level-1 operator)
         self.S = (sp.identity(ne, dtype=np.complex128, format="csr")
-                  - self.A_eo @ self.A_oe).tocsr()
+                  - self.A_eo @ self.A_oe).tocsr() if self.has_schur else None
         self.eps = epsilon_dof(lat)
         self.n = n
 

@@ -66,6 +66,7 @@ class MGParams:
     coarse_tol: float = 0.2
     coarse_maxit: int = 256
     coarse_exact: bool = False   # dense LU solve on the coarsest level (not the paper's CGNE)
+    fine_schur: bool = True      # level 1 on the KD-block-parity Schur system (False: on the full A)
 
 
 def vdot(a, b):
@@ -220,10 +221,12 @@ class Level:
 class Hierarchy:
     """Level 0 holds the fine KD operator; level k >= 1 the Galerkin operators."""
 
-    def __init__(self, lat, U, m, params, psi0):
+    def __init__(self, lat, U, m, params, psi0, naik=False):
         self.lat = lat
         self.params = params
-        self.kd = KDOperator(lat, U, m)
+        self.kd = KDOperator(lat, U, m, naik=naik)
+        # the fine solve runs on the Schur system where it exists (Table 1)
+        self.fine_schur = bool(params.fine_schur and self.kd.has_schur)
         self.nullvecs = []
         self.setup_its = []
         self.P = []
@@ -357,7 +360,7 @@ class Solver:
 
     def _op(self, level):
         if level == 0:
-            S = self.h.kd.S
+            S = self.h.kd.S if self.h.fine_schur else self.h.kd.A
 
             def f(v):
                 self.stats.fine_applies += 1
@@ -367,11 +370,11 @@ class Solver:
         return lambda v: op @ v
 
     def _restrict(self, level, r):
-        P = self.h.P_even if level == 0 else self.h.P[level]
+        P = self.h.P_even if level == 0 and self.h.fine_schur else self.h.P[level]
         return P.conj().T @ r
 
     def _prolong(self, level, e):
-        P = self.h.P_even if level == 0 else self.h.P[level]
+        P = self.h.P_even if level == 0 and self.h.fine_schur else self.h.P[level]
         return P @ e
 
     def coarse_solve(self, level, r):
@@ -400,11 +403,18 @@ class Solver:
     def solve(self, b, tol=1e-10):
         kd = self.h.kd
         self.stats = Stats(self.h.nlevels)
-        bt = kd.schur_rhs(b)
         bnorm = norm(b)
-        y, its, _ = gcr(self._op(0), bt, lambda v: self.kcycle(0, v),
-                        self.p.outer_restart, self.p.outer_maxit, tol * bnorm)
-        x = kd.reconstruct(b, y)
+        if self.h.fine_schur:
+            # || b - D x || equals the Schur residual (reading of Sec. 4)
+            bt = kd.schur_rhs(b)
+            y, its, _ = gcr(self._op(0), bt, lambda v: self.kcycle(0, v),
+                            self.p.outer_restart, self.p.outer_maxit, tol * bnorm)
+            x = kd.reconstruct(b, y)
+        else:
+            # A y = b with x = B^-1 y; b - A y = b - D x exactly
+            y, its, _ = gcr(self._op(0), b, lambda v: self.kcycle(0, v),
+                            self.p.outer_restart, self.p.outer_maxit, tol * bnorm)
+            x = kd.Binv @ y
         res = norm(b - kd.D @ x) / bnorm
         st = self.stats
         info = {
