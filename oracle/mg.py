@@ -67,6 +67,8 @@ class MGParams:
     coarse_maxit: int = 256
     coarse_exact: bool = False   # dense LU solve on the coarsest level (not the paper's CGNE)
     fine_schur: bool = True      # level 1 on the KD-block-parity Schur system (False: on the full A)
+    fine_op: str = "A"           # operator coarsened and solved: "A" = D B^-1 (the paper's method);
+                                 # "D" = the staggered D itself, the naive Galerkin MG of Sec. 3.2
 
 
 def vdot(a, b):
@@ -225,12 +227,15 @@ class Hierarchy:
         self.lat = lat
         self.params = params
         self.kd = KDOperator(lat, U, m, naik=naik)
+        self.naive = params.fine_op == "D"
+        if params.fine_op not in ("A", "D"):
+            raise ValueError("fine_op must be 'A' or 'D'")
         # the fine solve runs on the Schur system where it exists (Table 1)
-        self.fine_schur = bool(params.fine_schur and self.kd.has_schur)
+        self.fine_schur = bool(params.fine_schur and self.kd.has_schur and not self.naive)
         self.nullvecs = []
         self.setup_its = []
         self.P = []
-        self.ops = [self.kd.A]
+        self.ops = [self.kd.D if self.naive else self.kd.A]
         self.aggr = []
         dims = None
         ndof_site = None
@@ -360,7 +365,7 @@ class Solver:
 
     def _op(self, level):
         if level == 0:
-            S = self.h.kd.S if self.h.fine_schur else self.h.kd.A
+            S = self.h.kd.S if self.h.fine_schur else self.h.ops[0]
 
             def f(v):
                 self.stats.fine_applies += 1
@@ -411,10 +416,10 @@ class Solver:
                             self.p.outer_restart, self.p.outer_maxit, tol * bnorm)
             x = kd.reconstruct(b, y)
         else:
-            # A y = b with x = B^-1 y; b - A y = b - D x exactly
+            # A y = b with x = B^-1 y (b - A y = b - D x exactly), or D x = b
             y, its, _ = gcr(self._op(0), b, lambda v: self.kcycle(0, v),
                             self.p.outer_restart, self.p.outer_maxit, tol * bnorm)
-            x = kd.Binv @ y
+            x = y if self.h.naive else kd.Binv @ y
         res = norm(b - kd.D @ x) / bnorm
         st = self.stats
         info = {
