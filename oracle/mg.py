@@ -69,6 +69,8 @@ class MGParams:
     fine_schur: bool = True      # level 1 on the KD-block-parity Schur system (False: on the full A)
     fine_op: str = "A"           # operator coarsened and solved: "A" = D B^-1 (the paper's method);
                                  # "D" = the staggered D itself, the naive Galerkin MG of Sec. 3.2
+    asymmetric: bool = False     # R != P^dag: chiral doubling with gamma_5^{L/R} and block
+                                 # bi-orthonormalisation on every coarsening (Sec. 5, App. A)
 
 
 def vdot(a, b):
@@ -208,9 +210,72 @@ def prolongator(vecs, aggr):
                          shape=(nf, aggr.n_coarse_sites * 2 * nvec)).tocsr()
 
 
-def galerkin(P, A):
-    """A_hat = P^dag A P."""
-    return (P.conj().T @ (A @ P)).tocsr()
+def galerkin(P, A, R=None):
+    """A_hat = R A P with R = P^dag unless given."""
+    R = P.conj().T if R is None else R
+    return (R @ (A @ P)).tocsr()
+
+
+def lu_nopivot(M):
+    """M = L U with L unit lower and U upper triangular, no pivoting
+    (Doolittle), as the thin-LU of Sec. 5 (eq. thinlu)."""
+    n = M.shape[0]
+    L = np.eye(n, dtype=np.complex128)
+    U = np.array(M, dtype=np.complex128)
+    for k in range(n):
+        if U[k, k] == 0:
+            raise np.linalg.LinAlgError("zero pivot in the thin LU")
+        for i in range(k + 1, n):
+            L[i, k] = U[i, k] / U[k, k]
+            U[i, k:] -= L[i, k] * U[k, k:]
+    return L, np.triu(U)
+
+
+def asymmetric_transfer(V, Vbar, aggr, gL, gR):
+    """Asymmetric coarsening (Sec. 5, eqs. prcplx and thinlu; App. A).
+
+    V, Vbar: right and left vectors [nvec][n_f]; gL, gR: the operator pair of
+    the level (gamma_5^L = eps B^-1 and gamma_5^R = B eps on the fine level,
+    sigma_1^{L/R} on coarser ones), local to aggregates.  Per aggregate Z:
+      R~ = [ Vbar_i^dag ; V_i^dag gL ] (rows),  P~ = [ V_i , gR Vbar_i ] (columns),
+      R~ P~ = L U (thin LU),  R = L^-1 R~,  P = P~ U^-1  (so R P = 1),
+    and the coarse pair sigma_1^L = U^-dag sigma_1 L, sigma_1^R = U sigma_1 L^-dag,
+    with sigma_1 exchanging the two halves.  Coarse dof order per aggregate:
+    the n_vec V-columns, then the n_vec gR Vbar columns.
+    Returns sparse P (n_f x n_c), R (n_c x n_f), sigma_1^L, sigma_1^R."""
+    nvec, nf = V.shape
+    nz = aggr.n_coarse_sites
+    nd = 2 * nvec
+    gRVb = (gR @ Vbar.T).T            # [nvec][n_f]: gR Vbar_i
+    VgL = (gL.T @ V.conj().T).T       # [nvec][n_f]: the rows V_i^dag gL
+    s1 = np.block([[np.zeros((nvec, nvec)), np.eye(nvec)], [np.eye(nvec), np.zeros((nvec, nvec))]])
+    order = np.argsort(aggr.agg_of_dof, kind="stable")
+    bounds = np.searchsorted(aggr.agg_of_dof[order], np.arange(nz + 1))
+    pr, pc, pv, rr, rc, rv = [], [], [], [], [], []
+    sl = np.zeros((nz, nd, nd), dtype=np.complex128)
+    sr = np.zeros((nz, nd, nd), dtype=np.complex128)
+    for z in range(nz):
+        dofs = order[bounds[z]:bounds[z + 1]]
+        Rt = np.vstack([Vbar[:, dofs].conj(), VgL[:, dofs]])       # nd x |Z|
+        Pt = np.hstack([V[:, dofs].T, gRVb[:, dofs].T])            # |Z| x nd
+        L, Uu = lu_nopivot(Rt @ Pt)
+        Rz = np.linalg.solve(L, Rt)
+        Pz = Pt @ np.linalg.inv(Uu)
+        sl[z] = np.linalg.inv(Uu).conj().T @ s1 @ L
+        sr[z] = Uu @ s1 @ np.linalg.inv(L).conj().T
+        cols = z * nd + np.arange(nd)
+        pr.append(np.repeat(dofs, nd))
+        pc.append(np.tile(cols, dofs.size))
+        pv.append(Pz.ravel())
+        rr.append(np.repeat(cols, dofs.size))
+        rc.append(np.tile(dofs, nd))
+        rv.append(Rz.ravel())
+    nc = nz * nd
+    P = sp.coo_matrix((np.concatenate(pv), (np.concatenate(pr), np.concatenate(pc))), shape=(nf, nc)).tocsr()
+    R = sp.coo_matrix((np.concatenate(rv), (np.concatenate(rr), np.concatenate(rc))), shape=(nc, nf)).tocsr()
+    SL = sp.block_diag(list(sl), format="csr")
+    SR = sp.block_diag(list(sr), format="csr")
+    return P, R, SL, SR
 
 
 class Level:
@@ -235,11 +300,18 @@ class Hierarchy:
         self.nullvecs = []
         self.setup_its = []
         self.P = []
+        self.R = []
         self.ops = [self.kd.D if self.naive else self.kd.A]
         self.aggr = []
         dims = None
         ndof_site = None
         nvec_prev = None
+        if params.asymmetric:
+            # the level's operator pair: gamma_5^{L/R} of A (eqs. gamma5L, gamma5R),
+            # or eps twice for D (eps-Hermiticity)
+            E = sp.diags(self.kd.eps).tocsr()
+            gpair = (E, E) if self.naive else ((E @ self.kd.Binv).tocsr(), (self.kd.B @ E).tocsr())
+            self.gamma_pairs = [gpair]
         for k, lp in enumerate(params.levels):
             op = self.ops[-1]
             if psi0[k] is None:
@@ -257,15 +329,24 @@ class Hierarchy:
                 ag = aggregation_level1(lat, lp.agg)
             else:
                 ag = aggregation_coarse(dims, ndof_site, nvec_prev, lp.agg)
-            P = prolongator(V, ag)
+            if params.asymmetric:
+                # the left vectors are the same relaxed vectors (the construction
+                # allows any; Sec. 5)
+                P, R, sL, sR = asymmetric_transfer(V, V, ag, *self.gamma_pairs[-1])
+                self.gamma_pairs.append((sL, sR))
+            else:
+                P = prolongator(V, ag)
+                R = P.conj().T.tocsr()
             self.aggr.append(ag)
             self.P.append(P)
-            self.ops.append(galerkin(P, op))
+            self.R.append(R)
+            self.ops.append(galerkin(P, op, R))
             dims = ag.coarse_dims
             ndof_site = 2 * lp.nvec
             nvec_prev = lp.nvec
         self.coarse_dims = dims
         self.P_even = self.P[0][self.kd.even].tocsr()
+        self.R_even = self.R[0][:, self.kd.even].tocsr()
         self.coarse_lu = None
         if params.coarse_exact:
             self.coarse_lu = scipy.linalg.lu_factor(self.ops[-1].toarray())
@@ -375,8 +456,8 @@ class Solver:
         return lambda v: op @ v
 
     def _restrict(self, level, r):
-        P = self.h.P_even if level == 0 and self.h.fine_schur else self.h.P[level]
-        return P.conj().T @ r
+        R = self.h.R_even if level == 0 and self.h.fine_schur else self.h.R[level]
+        return R @ r
 
     def _prolong(self, level, e):
         P = self.h.P_even if level == 0 and self.h.fine_schur else self.h.P[level]
