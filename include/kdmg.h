@@ -108,6 +108,15 @@ typedef struct {
                                  paper's choice: a stronger preconditioner;
                                  at most 32768 coarsest dofs, 32 n^2 bytes of
                                  device memory for n dofs) */
+  int fine_op;                /* operator that is coarsened and solved on the
+                                 fine level: 0 (default) A = D B^-1, the
+                                 Kahler-Dirac preconditioned operator of the
+                                 paper; 1 D itself, the Galerkin multigrid
+                                 that Sec. 3.2 shows to fail (Fig. "residstag"),
+                                 kept as a negative control.  With 1, or on a
+                                 Naik lattice, the fine solve runs on the full
+                                 lattice instead of the KD-block-parity Schur
+                                 system.  2D lattices only. */
 } kdmg_mg_params;
 
 /* Per right-hand side result of kdmg_solve. */
@@ -141,6 +150,23 @@ kdmg_status kdmg_init(int device);
    other than (nd 2, ncolor 1) and (nd 4, ncolor 3). */
 kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor, const int* bc_sign,
                                 const double* links_host, void* stream, kdmg_lattice** out);
+/* Switches the lattice's operator to the Naik-improved staggered operator of
+   Sec. 2.1 (eq. "freehisq"), or back (enable = 0):
+     D = m + 1/2 sum_mu eta_mu(x) [ c1 (U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu))
+                                  + c3 (W_mu(x) psi(x+3mu) - W_mu(x-3mu)^dag psi(x-3mu)) ],
+   c1 = 9/8, c3 = -1/24, W_mu(x) = U_mu(x) U_mu(x+mu) U_mu(x+2mu).  (The
+   printed operator carries 9/16 and 1/48 under an overall 1/2, whose own
+   spectrum is half the one printed after it; these coefficients give that
+   spectrum, m +- i sqrt(sum sin^2 p (1 + sin^2 p / 6)^2).)  Every operator and
+   solve on the lattice then uses it: kdmg_apply_D, kdmg_apply_A (the KD block
+   is the plain one with its hops scaled by 9/8; the three-link hops are part of
+   C), and hierarchies built afterwards, whose fine solve runs on the full
+   lattice because the three-link hops join KD blocks of the same parity
+   (kdmg_apply_schur returns KDMG_EUNSUPPORTED).  First aggregates must be at
+   least 2 KD blocks wide.  Hierarchies built before the switch must not be
+   used after it.  2D U(1) only (KDMG_EUNSUPPORTED otherwise); extents >= 8.
+   Runs on `stream` and synchronises it. */
+kdmg_status kdmg_lattice_set_naik(kdmg_lattice* lat, int enable, void* stream);
 void kdmg_lattice_destroy(kdmg_lattice* lat);
 /* Device bytes held by the lattice. */
 kdmg_status kdmg_lattice_footprint(const kdmg_lattice* lat, size_t* bytes);

@@ -267,6 +267,88 @@ __global__ __launch_bounds__(256) void k_dslash_nat(Cx<VT>* __restrict__ out, co
   }
 }
 
+// ------------------------------------------------------- Naik three-link hops
+// The Naik-improved operator (Sec. 2.1, eq. "freehisq") adds to every site
+// the hops x -> x +- 3 mu with the three-link transporter W_mu(x) =
+// U_mu(x) U_mu(x+mu) U_mu(x+2mu).  Stored folded like the one-link hops:
+// W~_mu(x) = 1/2 eta_mu(x) bc W_mu(x) (bc: the boundary sign when the hop
+// crosses the boundary), [mu][site]; the backward hop is -W~_mu(x-3mu)^*,
+// since eta_mu(x - 3mu) = eta_mu(x).  A three-link hop always leaves the KD
+// block (and joins sites of opposite eps).
+
+// block-layout index of site (x0, x1)
+__host__ __device__ __forceinline__ long blk_site_index(const Geo2& g, int x0, int x1) {
+  const int X0 = x0 >> 1, X1 = x1 >> 1;
+  return (long)((X0 + X1) & 1) * g.half + 4L * blk_index(g, X0, X1) + (x0 & 1) + 2 * (x1 & 1);
+}
+
+// Block-layout site e -> its four three-hop neighbours (+x, -x, +t, -t).
+struct Hop3 {
+  long xp, xm, tp, tm;
+  float eps;  // eps(x) of the site itself
+};
+__device__ __forceinline__ Hop3 hop3_of(const Geo2& g, long e) {
+  const int p = e >= g.half ? 1 : 0;
+  const long rem = e - (long)p * g.half;
+  const int b = (int)(rem >> 2), s = (int)(rem & 3);
+  int X0, X1;
+  blk_coords(g, p, b, X0, X1);
+  const int x0 = 2 * X0 + (s & 1), x1 = 2 * X1 + (s >> 1);
+  const int x0p = x0 + 3 >= g.Lx ? x0 + 3 - g.Lx : x0 + 3, x0m = x0 < 3 ? x0 - 3 + g.Lx : x0 - 3;
+  const int x1p = x1 + 3 >= g.Lt ? x1 + 3 - g.Lt : x1 + 3, x1m = x1 < 3 ? x1 - 3 + g.Lt : x1 - 3;
+  Hop3 h;
+  h.xp = blk_site_index(g, x0p, x1);
+  h.xm = blk_site_index(g, x0m, x1);
+  h.tp = blk_site_index(g, x0, x1p);
+  h.tm = blk_site_index(g, x0, x1m);
+  h.eps = ((x0 + x1) & 1) ? -1.f : 1.f;
+  return h;
+}
+
+// out += coef * C3 in on full block-layout vectors (C3: the three-link hops),
+// one thread per site; eps_in multiplies the source by eps (the targets all
+// have eps = -eps(x)).  Grid (sites / 256, rhs).
+template <class R, class LT, class VT>
+__global__ __launch_bounds__(256) void k_hop3(Cx<VT>* out, long so, const Cx<VT>* in, long si, R coef,
+                                               const Cx<LT>* wl, Geo2 g, int eps_in, const int* act) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const long f = 2 * g.half;
+  if (e >= f || !is_active(act, r)) return;
+  const Hop3 n = hop3_of(g, e);
+  const Cx<VT>* src = in + r * si;
+  const Cx<R> vxp = ld<R>(src[n.xp]), vxm = ld<R>(src[n.xm]), vtp = ld<R>(src[n.tp]), vtm = ld<R>(src[n.tm]);
+  const Cx<R> wx = ld<R>(wl[e]), wxm = ld<R>(wl[n.xm]), wt = ld<R>(wl[f + e]), wtm = ld<R>(wl[f + n.tm]);
+  Cx<R> h = wx * vxp - cmul_conj(wxm, vxm) + wt * vtp - cmul_conj(wtm, vtm);
+  const R c = eps_in ? coef * (R)(-n.eps) : coef;
+  Cx<VT>& o = out[r * so + e];
+  o = st<VT>(ld<R>(o) + c * h);
+}
+
+// Naik-improved D in natural site order, one thread per site:
+// out = m in + c1 (one-link hops) + c3 (three-link hops), links folded
+// ([mu][site]: U~ one-link, W~ three-link).
+template <class R, class LT, class VT>
+__global__ __launch_bounds__(256) void k_dslash_naik_nat(Cx<VT>* __restrict__ out, const Cx<VT>* __restrict__ in,
+                                                         const Cx<LT>* __restrict__ U, const Cx<LT>* __restrict__ W,
+                                                         int Lx, int Lt, long vol, R m, R c1, R c3) {
+  const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (x >= vol) return;
+  const int x1 = (int)(x / Lx), x0 = (int)(x - (long)x1 * Lx);
+  auto wrap = [](int a, int L) { return a >= L ? a - L : (a < 0 ? a + L : a); };
+  const long i1xp = (long)x1 * Lx + wrap(x0 + 1, Lx), i1xm = (long)x1 * Lx + wrap(x0 - 1, Lx);
+  const long i1tp = (long)wrap(x1 + 1, Lt) * Lx + x0, i1tm = (long)wrap(x1 - 1, Lt) * Lx + x0;
+  const long i3xp = (long)x1 * Lx + wrap(x0 + 3, Lx), i3xm = (long)x1 * Lx + wrap(x0 - 3, Lx);
+  const long i3tp = (long)wrap(x1 + 3, Lt) * Lx + x0, i3tm = (long)wrap(x1 - 3, Lt) * Lx + x0;
+  const Cx<VT>* v = in + (long)r * vol;
+  Cx<R> h1 = ld<R>(U[x]) * ld<R>(v[i1xp]) - cmul_conj(ld<R>(U[i1xm]), ld<R>(v[i1xm])) +
+             ld<R>(U[vol + x]) * ld<R>(v[i1tp]) - cmul_conj(ld<R>(U[vol + i1tm]), ld<R>(v[i1tm]));
+  Cx<R> h3 = ld<R>(W[x]) * ld<R>(v[i3xp]) - cmul_conj(ld<R>(W[i3xm]), ld<R>(v[i3xm])) +
+             ld<R>(W[vol + x]) * ld<R>(v[i3tp]) - cmul_conj(ld<R>(W[vol + i3tm]), ld<R>(v[i3tm]));
+  out[(long)r * vol + x] = st<VT>(m * ld<R>(v[x]) + c1 * h1 + c3 * h3);
+}
+
 // gather / scatter between an external ordering and the block layout:
 // dst[r][i] = src[r][idx[i]]  (gather)   or  dst[r][idx[i]] = src[r][i]  (scatter)
 template <class TO, class TI>
@@ -420,8 +502,10 @@ __global__ __launch_bounds__(256) void k_prolong1(Cx<VO>* out, long so, const Cx
 // W[x][c'][j] = sum_{s' in block(x), chir(s')=c'} B^-1[x][s'] P[s'][j]   (FP64)
 // grid: (blocks, nv, 2 parities)
 template <class LT>
+// wmode 0: W = B^-1 P (the KD Galerkin product); 1: W = P (Galerkin on D
+// itself); 2: W = B P (its block-local part P^dag B P).
 __global__ __launch_bounds__(256) void k_galerkin_w1(c64* W, const c64* P, const Cx<LT>* links,
-                                                     Geo2 g, int nv, double m) {
+                                                     Geo2 g, int nv, double m, int wmode) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, p = blockIdx.z;
   if (b >= g.Nb2) return;
@@ -431,7 +515,14 @@ __global__ __launch_bounds__(256) void k_galerkin_w1(c64* W, const c64* P, const
   for (int cp = 0; cp < 2; ++cp) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = chir2(s) == cp ? P[(base + s) * nv + j] : c64{0, 0};
-    binv_block<double>(L, m, v, w);
+    if (wmode == 0) {
+      binv_block<double>(L, m, v, w);
+    } else if (wmode == 2) {
+      b_block<double>(L, m, v, w);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) w[s] = v[s];
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) W[((base + s) * 2 + cp) * nv + j] = w[s];
   }
@@ -442,7 +533,7 @@ __global__ __launch_bounds__(256) void k_galerkin_w1(c64* W, const c64* P, const
 // 3/4 = +-t.
 template <class LT>
 __global__ __launch_bounds__(1024) void k_galerkin1(c64* Yt, const c64* P, const c64* W,
-                                                    const Cx<LT>* links, Geo2 g, Agg2 a) {
+                                                    const Cx<LT>* links, Geo2 g, Agg2 a, int ident) {
   const int Z = blockIdx.x;
   const int nv = a.nv, ndc = 2 * nv;
   const long nZ = (long)a.Ncx * a.Nct;
@@ -487,9 +578,75 @@ __global__ __launch_bounds__(1024) void k_galerkin1(c64* Yt, const c64* P, const
         cfma_conj(acc[dxm], P2, -(conj(ld<double>(Lxm[5])) * Wat(n.xm, 3)));
       }
     }
-    if (row == col) acc[0].re += 1.0;
+    if (ident && row == col) acc[0].re += 1.0;
 #pragma unroll
     for (int d = 0; d < 5; ++d) Yt[(((long)d * nZ + Z) * ndc + col) * ndc + row] = acc[d];
+  }
+}
+
+// Galerkin on D itself: the block-local part, self block += coef P^dag W_B
+// with W_B = B P (k_galerkin_w1 mode 2).  One workgroup per coarse site.
+template <class LT>
+__global__ __launch_bounds__(1024) void k_galerkin1_self(c64* Yt, const c64* P, const c64* WB, Geo2 g, Agg2 a,
+                                                          double coef) {
+  const int Z = blockIdx.x;
+  const int nv = a.nv, ndc = 2 * nv;
+  const int Z0 = Z % a.Ncx, Z1 = Z / a.Ncx;
+  for (int pair = threadIdx.x; pair < ndc * ndc; pair += blockDim.x) {
+    const int row = pair / ndc, col = pair % ndc;
+    const int c = row / nv, i = row % nv, cp = col / nv, j = col % nv;
+    c64 acc{0, 0};
+    for (int k = 0; k < a.a0 * a.a1; ++k) {
+      const int X0 = Z0 * a.a0 + k % a.a0, X1 = Z1 * a.a1 + k / a.a0;
+      const long base = (long)((X0 + X1) & 1) * g.half + 4L * blk_index(g, X0, X1);
+      for (int s = 0; s < 4; ++s)
+        if (chir2(s) == c) cfma_conj(acc, P[(base + s) * nv + i], WB[((base + s) * 2 + cp) * nv + j]);
+    }
+    c64& y = Yt[((long)Z * ndc + col) * ndc + row];
+    y.re += coef * acc.re;
+    y.im += coef * acc.im;
+  }
+}
+
+// The Naik term of the level-1 Galerkin product: blocks += coef P^dag C3 W,
+// with C3 the three-link hops.  A hop that leaves the aggregate lands in the
+// neighbouring one (aggregates at least 2 KD blocks = 4 sites wide) and is
+// filed under its direction, as the one-link hops are.
+template <class LT>
+__global__ __launch_bounds__(1024) void k_galerkin1_hop3(c64* Yt, const c64* P, const c64* W, const Cx<LT>* wl,
+                                                          Geo2 g, Agg2 a, double coef) {
+  const int Z = blockIdx.x;
+  const int nv = a.nv, ndc = 2 * nv;
+  const long nZ = (long)a.Ncx * a.Nct, f = 2 * g.half;
+  const int Z0 = Z % a.Ncx, Z1 = Z / a.Ncx, e0 = 2 * a.a0, e1 = 2 * a.a1;
+  for (int pair = threadIdx.x; pair < ndc * ndc; pair += blockDim.x) {
+    const int row = pair / ndc, col = pair % ndc;
+    const int c = row / nv, i = row % nv, cp = col / nv, j = col % nv;
+    c64 acc[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) acc[d] = c64{0, 0};
+    for (int k = 0; k < a.a0 * a.a1; ++k) {
+      const int X0 = Z0 * a.a0 + k % a.a0, X1 = Z1 * a.a1 + k / a.a0;
+      const long base = (long)((X0 + X1) & 1) * g.half + 4L * blk_index(g, X0, X1);
+      for (int s = 0; s < 4; ++s) {
+        if (chir2(s) != c) continue;
+        const long e = base + s;
+        const int lx = (2 * X0 + (s & 1)) % e0, lt = (2 * X1 + (s >> 1)) % e1;  // position in the aggregate
+        const Hop3 n = hop3_of(g, e);
+        const c64 Pv = P[e * nv + i];
+        auto Wat = [&](long y) { return W[(y * 2 + cp) * nv + j]; };
+        cfma_conj(acc[lx + 3 >= e0 ? 1 : 0], Pv, ld<double>(wl[e]) * Wat(n.xp));
+        cfma_conj(acc[lx < 3 ? 2 : 0], Pv, -(conj(ld<double>(wl[n.xm])) * Wat(n.xm)));
+        cfma_conj(acc[lt + 3 >= e1 ? 3 : 0], Pv, ld<double>(wl[f + e]) * Wat(n.tp));
+        cfma_conj(acc[lt < 3 ? 4 : 0], Pv, -(conj(ld<double>(wl[f + n.tm])) * Wat(n.tm)));
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      c64& y = Yt[(((long)d * nZ + Z) * ndc + col) * ndc + row];
+      y.re += coef * acc[d].re;
+      y.im += coef * acc[d].im;
+    }
   }
 }
 

@@ -138,9 +138,11 @@ void galerkin_level1(kdmg_hierarchy& h, const Ctx& c) {
   const Transfer& T = h.T[0];
   const int nv = T.nv;
   const long f = 2 * g.half;
+  const Fine2<double> F = fine2<double>(lat, h.mass);
   if (!h.gal_w.p) h.gal_w.alloc(sizeof(c64) * f * 2 * nv);
+  // KD: W = B~^-1 P (at the rescaled mass); on D itself: W = P
   hipLaunchKernelGGL((k_galerkin_w1<double>), dim3(cdiv(g.Nb2, 256), nv, 2), dim3(256), 0, c.st,
-                     h.gal_w.as<c64>(), T.P64.as<c64>(), lat.links64.as<c64>(), g, nv, h.mass);
+                     h.gal_w.as<c64>(), T.P64.as<c64>(), lat.links64.as<c64>(), g, nv, F.me, h.naive ? 1 : 0);
   KDMG_LAUNCH_CHECK();
   CoarseLevel& C1 = h.L[1];
   if (!C1.Yt64.p) {
@@ -154,8 +156,25 @@ void galerkin_level1(kdmg_hierarchy& h, const Ctx& c) {
   const int nZ = T.a2.Ncx * T.a2.Nct;
   const int thr = C1.ndc * C1.ndc > 1024 ? 1024 : C1.ndc * C1.ndc;
   hipLaunchKernelGGL((k_galerkin1<double>), dim3(nZ), dim3(thr), 0, c.st, C1.Yt64.as<c64>(),
-                     T.P64.as<c64>(), h.gal_w.as<c64>(), lat.links64.as<c64>(), g, T.a2);
+                     T.P64.as<c64>(), h.gal_w.as<c64>(), lat.links64.as<c64>(), g, T.a2, h.naive ? 0 : 1);
   KDMG_LAUNCH_CHECK();
+  if (F.W) {  // Naik: + x P^dag C3 W
+    hipLaunchKernelGGL((k_galerkin1_hop3<double>), dim3(nZ), dim3(thr), 0, c.st, C1.Yt64.as<c64>(),
+                       T.P64.as<c64>(), h.gal_w.as<c64>(), lat.wl64.as<c64>(), g, T.a2, F.x);
+    KDMG_LAUNCH_CHECK();
+  }
+  if (h.naive) {
+    // the block-local part P^dag B~ P, then the overall factor s of D = s (B~ + C~)
+    hipLaunchKernelGGL((k_galerkin_w1<double>), dim3(cdiv(g.Nb2, 256), nv, 2), dim3(256), 0, c.st,
+                       h.gal_w.as<c64>(), T.P64.as<c64>(), lat.links64.as<c64>(), g, nv, F.me, 2);
+    hipLaunchKernelGGL(k_galerkin1_self<double>, dim3(nZ), dim3(thr), 0, c.st, C1.Yt64.as<c64>(), T.P64.as<c64>(),
+                       h.gal_w.as<c64>(), g, T.a2, 1.0);
+    KDMG_LAUNCH_CHECK();
+    if (F.s != 1.0) {
+      const long ny = (long)C1.ndir * C1.nsites * C1.ndc * C1.ndc;
+      launch_map(OpAxpby<double>{C1.Yt64.as<c64>(), C1.Yt64.as<c64>(), nullptr, ny, F.s, 0.0, nullptr}, ny, 1, c.st);
+    }
+  }
   finish_coarse_level(c, C1);
 }
 
@@ -324,6 +343,8 @@ void build_level1(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int relax
   const int nv = lp.nvec, a0 = lp.agg[0], a1 = lp.agg[1];
   KDMG_CHECK(a0 >= 1 && a1 >= 1 && g.Bx % a0 == 0 && g.Bt % a1 == 0, KDMG_EINVAL,
              "first aggregate must divide the KD-block lattice");
+  KDMG_CHECK(!lat.naik || (a0 >= 2 && a1 >= 2), KDMG_EINVAL,
+             "Naik operator: first aggregates must be at least 2 KD blocks wide (three-link hops)");
   KDMG_CHECK(nv >= 1 && nv <= 2 * a0 * a1 && 2 * nv <= 64, KDMG_EINVAL,
              "n_vec must not exceed the sites of one aggregate chirality (and 2 n_vec <= 64)");
   Transfer& T = h.T[0];
@@ -342,12 +363,27 @@ void build_level1(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int relax
   const c64* L = lat.links64.as<c64>();
   if (!relaxed) {
     DevBuf u(sizeof(c64) * f * nv), t(sizeof(c64) * f * nv), t2(sizeof(c64) * f * nv);
-    auto normal = [&](c64* out, const c64* in, const int* act) {
-      fullAdag_apply<double>(u.as<c64>(), t2.as<c64>(), in, t.as<c64>(), L, g, m, act, nv, c.st);
-      launch_hop<double, double, double>(out, f, t2.as<c64>(), f, u.as<c64>(), f, nullptr, 0, 0.0, 1.0,
-                                         L, g, 0, 2, m, 0, 0, act, nv, c.st);
-    };
-    relax(c, Vb.as<c64>(), f, nv, h.params.setup_tol, h.params.setup_maxit, normal);
+    if (!h.fine_full) {
+      auto normal = [&](c64* out, const c64* in, const int* act) {
+        fullAdag_apply<double>(u.as<c64>(), t2.as<c64>(), in, t.as<c64>(), L, g, m, act, nv, c.st);
+        launch_hop<double, double, double>(out, f, t2.as<c64>(), f, u.as<c64>(), f, nullptr, 0, 0.0, 1.0,
+                                           L, g, 0, 2, m, 0, 0, act, nv, c.st);
+      };
+      relax(c, Vb.as<c64>(), f, nv, h.params.setup_tol, h.params.setup_maxit, normal);
+    } else {
+      // the operator that is coarsened: A A^dag (Naik KD) or D D^dag (D itself)
+      const Fine2<double> F = fine2<double>(lat, m);
+      auto normal = [&](c64* out, const c64* in, const int* act) {
+        if (h.naive) {
+          fine2_Ddag<double, double>(u.as<c64>(), in, F, act, nv, c.st);
+          fine2_D<double, double>(out, u.as<c64>(), nullptr, F, act, nv, c.st);
+        } else {
+          fine2_Adag<double, double>(u.as<c64>(), nullptr, in, t.as<c64>(), F, act, nv, c.st);
+          fine2_A<double, double>(out, u.as<c64>(), nullptr, t.as<c64>(), F, act, nv, c.st);
+        }
+      };
+      relax(c, Vb.as<c64>(), f, nv, h.params.setup_tol, h.params.setup_maxit, normal);
+    }
   }
   T.relaxed.alloc(Vb.bytes);
   KDMG_HIP(hipMemcpyAsync(T.relaxed.p, Vb.p, Vb.bytes, hipMemcpyDeviceToDevice, c.st));
@@ -486,11 +522,16 @@ extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass
              KDMG_EINVAL, "bad solver parameters");
   for (int k = 0; k < params->nlevels - 1; ++k)
     KDMG_CHECK(psi0_host[k] != nullptr, KDMG_EINVAL, "missing starting vectors");
+  KDMG_CHECK(params->fine_op == 0 || params->fine_op == 1, KDMG_EINVAL, "fine_op must be 0 or 1");
+  KDMG_CHECK(lat->nd == 2 || (params->fine_op == 0 && !lat->naik), KDMG_EUNSUPPORTED,
+             "fine_op = 1 is built for 2D lattices");
   auto h = std::make_unique<kdmg_hierarchy>();
   h->lat = lat;
   h->mass = mass;
   h->params = *params;
   h->nlevels = params->nlevels;
+  h->naive = params->fine_op == 1;
+  h->fine_full = h->naive || lat->naik;
   h->L.resize(h->nlevels);
   h->T.resize(h->nlevels - 1);
   int nvmax = 1;
@@ -512,6 +553,9 @@ namespace {
 
 bool same_shape(const kdmg_hierarchy& a, const kdmg_hierarchy& b) {
   if (a.nlevels != b.nlevels || a.lat->nd != b.lat->nd || a.lat->nc != b.lat->nc) return false;
+  if (a.fine_full != b.fine_full || a.naive != b.naive || a.lat->naik != b.lat->naik ||
+      a.params.coarse_solver != b.params.coarse_solver)
+    return false;
   for (int mu = 0; mu < 4; ++mu)
     if (a.lat->dims[mu] != b.lat->dims[mu]) return false;
   for (int k = 0; k < a.nlevels - 1; ++k) {
@@ -559,6 +603,8 @@ extern "C" kdmg_status kdmg_hierarchy_at_mass(const kdmg_hierarchy* base, double
   h->nlevels = base->nlevels;
   h->T = base->T;
   h->derived = true;
+  h->naive = base->naive;
+  h->fine_full = base->fine_full;
   h->L.resize(h->nlevels);
   rebuild_coarse_ops(*h, (hipStream_t)stream);
   copy_tuned(*base, *h);
@@ -578,6 +624,8 @@ extern "C" kdmg_status kdmg_hierarchy_set_mass(kdmg_hierarchy* h, const kdmg_hie
     h->lat = base->lat;
     h->T = base->T;
     h->derived = true;
+    h->naive = base->naive;
+    h->fine_full = base->fine_full;
     copy_tuned(*base, *h);
   }
   h->mass = mass;

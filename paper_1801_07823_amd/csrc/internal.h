@@ -43,9 +43,17 @@ struct kdmg_lattice {
   // natural site -> block-layout index; even-block rank -> index in the even half
   kdmg::DevBuf perm_full, perm_even;
   std::vector<int> h_perm_full, h_perm_even;
+  // Naik-improved operator (2D U(1), kdmg_lattice_set_naik):
+  // D = m + c1 (one-link hops) + c3 (three-link hops)
+  int naik = 0;
+  double c1 = 1.0, c3 = 0.0;
+  kdmg::DevBuf wl64, wl16;          // folded three-link transporters, block layout [mu][2 half]
+  kdmg::DevBuf natw64, natw16;      // the same in natural order [mu][volume]
+  std::vector<kdmg::c64> h_links;   // 2D: the uploaded links, kept for the transporters
   size_t footprint() const {
     return links64.bytes + links16.bytes + links32.bytes + nat64.bytes + nat16.bytes +
-           perm_full.bytes + perm_even.bytes + lk64.bytes + lk32.bytes + lk16.bytes + nb4.bytes;
+           perm_full.bytes + perm_even.bytes + lk64.bytes + lk32.bytes + lk16.bytes + nb4.bytes +
+           wl64.bytes + wl16.bytes + natw64.bytes + natw16.bytes;
   }
 };
 
@@ -80,6 +88,14 @@ void launch_dslash_blk(Cx<VT>* out, long so, const Cx<VT>* in, long si, const Cx
                        hipStream_t st) {
   hipLaunchKernelGGL((k_dslash_blk<R, LT, VT>), fine_grid(g, nrhs, 2), dim3(256), 0, st, out, so, in,
                      si, sub, ss, links, g, (R)m, act);
+  KDMG_LAUNCH_CHECK();
+}
+
+template <class R, class LT, class VT>
+void launch_hop3(Cx<VT>* out, long so, const Cx<VT>* in, long si, double coef, const Cx<LT>* wl, const Geo2& g,
+                 int eps_in, const int* act, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_hop3<R, LT, VT>), dim3(cdiv(2 * g.half, 256), nrhs), dim3(256), 0, st, out, so, in, si,
+                     (R)coef, wl, g, eps_in, act);
   KDMG_LAUNCH_CHECK();
 }
 
@@ -128,6 +144,89 @@ void fullAdag_apply(Cx<R>* out, Cx<R>* out2, const Cx<R>* v, Cx<R>* t, const Cx<
   const long f = 2 * g.half;
   launch_hop<R, LT, R>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, links, g, 0, 2, m, 0, 1, act, nrhs, st);
   launch_binv<R, LT, R>(out, f, out2, f, t, f, v, f, links, g, 0, 2, m, 1, act, nrhs, st);
+}
+
+// ------------------------------------------- 2D fine operators, full lattice
+// The fine operator of a 2D lattice in one precision, for the solves that
+// iterate on the full lattice (the Naik-improved operator, whose three-link
+// hops join KD blocks of the same parity, and multigrid on D itself).  With
+// D = m + c1 H1 + c3 H3 (H1, H3 the one- and three-link hops) written as
+//   D = s (B~ + C1 + x C3),  s = c1,  x = c3 / c1,  B~ = m / c1 + (intra-block H1),
+// A = D B^-1 = 1 + (C1 + x C3) B~^-1 needs only the plain block kernels at the
+// rescaled mass (the Naik block is the plain one rescaled, Sec. 2.1).
+template <class LT>
+struct Fine2 {
+  const Cx<LT>* L;  // folded one-link hops, block layout
+  const Cx<LT>* W;  // folded three-link hops, block layout (null: none)
+  Geo2 g;
+  double me;        // m / c1
+  double s;         // c1
+  double x;         // c3 / c1
+  double m;         // the mass of D
+};
+
+// The 2D fine operator of `lat` at mass m, FP64 (LT = double) or FP16-stored (LT = _Float16).
+template <class LT>
+Fine2<LT> fine2(const kdmg_lattice& lat, double m) {
+  const bool h = sizeof(LT) == 2;
+  const void* L = h ? lat.links16.p : lat.links64.p;
+  const void* W = lat.naik ? (h ? lat.wl16.p : lat.wl64.p) : nullptr;
+  return Fine2<LT>{(const Cx<LT>*)L, (const Cx<LT>*)W, lat.g, m / lat.c1, lat.c1, lat.c3 / lat.c1, m};
+}
+
+// out = a x + b y (in place allowed)
+template <class T>
+struct OpAxpby {
+  Cx<T>* out; const Cx<T>* x; const Cx<T>* y; long n; double a, b; const int* act;
+  __device__ bool active(int r) const { return is_active(act, r); }
+  __device__ void elem(int r, long i) const {
+    const long o = r * n + i;
+    Cx<T> v = (T)a * x[o];
+    if (y) v += (T)b * y[o];
+    out[o] = v;
+  }
+};
+
+// out = A v, or resid - A v;  t: full-lattice temporary
+template <class R, class LT>
+void fine2_A(Cx<R>* out, const Cx<R>* v, const Cx<R>* resid, Cx<R>* t, const Fine2<LT>& F, const int* act,
+             int nrhs, hipStream_t st) {
+  const long f = 2 * F.g.half;
+  launch_binv<R, LT, R>(t, f, nullptr, 0, v, f, nullptr, 0, F.L, F.g, 0, 2, F.me, 0, act, nrhs, st);
+  if (!resid)
+    launch_hop<R, LT, R>(out, f, t, f, v, f, nullptr, 0, 0.0, 1.0, F.L, F.g, 0, 2, F.me, 0, 0, act, nrhs, st);
+  else
+    launch_hop<R, LT, R>(out, f, t, f, resid, f, v, f, -1.0, -1.0, F.L, F.g, 0, 2, F.me, 0, 0, act, nrhs, st);
+  if (F.W) launch_hop3<R, LT, R>(out, f, t, f, resid ? -F.x : F.x, F.W, F.g, 0, act, nrhs, st);
+}
+
+// out = A^dag v = v + eps B~^-1 (C1 + x C3) eps v;  optionally out2 = B~^-1 out
+template <class R, class LT>
+void fine2_Adag(Cx<R>* out, Cx<R>* out2, const Cx<R>* v, Cx<R>* t, const Fine2<LT>& F, const int* act, int nrhs,
+                hipStream_t st) {
+  const long f = 2 * F.g.half;
+  launch_hop<R, LT, R>(t, f, v, f, nullptr, 0, nullptr, 0, 0.0, 1.0, F.L, F.g, 0, 2, F.me, 0, 1, act, nrhs, st);
+  if (F.W) launch_hop3<R, LT, R>(t, f, v, f, F.x, F.W, F.g, 1, act, nrhs, st);
+  launch_binv<R, LT, R>(out, f, out2, f, t, f, v, f, F.L, F.g, 0, 2, F.me, 1, act, nrhs, st);
+}
+
+// out = D v, or resid - D v
+template <class R, class LT>
+void fine2_D(Cx<R>* out, const Cx<R>* v, const Cx<R>* resid, const Fine2<LT>& F, const int* act, int nrhs,
+             hipStream_t st) {
+  const long f = 2 * F.g.half;
+  launch_dslash_blk<R, LT, R>(out, f, v, f, nullptr, 0, F.L, F.g, F.me, act, nrhs, st);
+  if (F.W) launch_hop3<R, LT, R>(out, f, v, f, F.x, F.W, F.g, 0, act, nrhs, st);
+  if (resid || F.s != 1.0)
+    launch_map(OpAxpby<R>{out, out, resid, f, resid ? -F.s : F.s, 1.0, act}, f, nrhs, st);
+}
+
+// out = D^dag v = 2 m v - D v  (D - m is anti-Hermitian)
+template <class R, class LT>
+void fine2_Ddag(Cx<R>* out, const Cx<R>* v, const Fine2<LT>& F, const int* act, int nrhs, hipStream_t st) {
+  const long f = 2 * F.g.half;
+  fine2_D<R, LT>(out, v, nullptr, F, act, nrhs, st);
+  launch_map(OpAxpby<R>{out, out, v, f, -1.0, 2.0 * F.m, act}, f, nrhs, st);
 }
 
 // ------------------------------------------------------------ 4D fine operators
@@ -293,6 +392,10 @@ struct kdmg_hierarchy {
   kdmg::DevBuf gal_w;                 // Galerkin scratch W = B^-1 P (level 1), kept for rebuilds
   kdmg::DevBuf binv64, binv32;        // 4D: dense B^-1 blocks at this mass (FP64, FP32)
   kdmg::DenseInverse dinv;            // coarsest inverse (params.coarse_solver == 1)
+  // The fine level: iterate on the KD-block-parity Schur system (false), or on
+  // the full lattice (true: the Naik-improved operator, or multigrid on D
+  // itself, params.fine_op == 1, which is `naive`).
+  bool fine_full = false, naive = false;
   bool use_graphs = true;             // replay captured chunks of the coarsest CGNE
   kdmg::SolveWS* ws = nullptr;
   // event timing of the coarsest CGNE kernels (kdmg_hierarchy_kernel_timing)

@@ -193,6 +193,7 @@ extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor, 
 
   std::vector<c64> nat;
   fold_links_2d(*lat, links_host, nat);
+  lat->h_links.assign(reinterpret_cast<const c64*>(links_host), reinterpret_cast<const c64*>(links_host) + 2 * V);
   std::vector<c64> blk(2L * g.Nb2 * 8);
   lat->h_perm_full.assign(V, 0);
   lat->h_perm_even.assign(V / 2, 0);
@@ -243,6 +244,54 @@ extern "C" kdmg_status kdmg_lattice_create(int nd, const int* dims, int ncolor, 
   KDMG_API_END
 }
 
+extern "C" kdmg_status kdmg_lattice_set_naik(kdmg_lattice* lat, int enable, void* stream) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(lat, KDMG_EINVAL, "kdmg_lattice_set_naik: null lattice");
+  KDMG_CHECK(lat->nd == 2 && lat->nc == 1, KDMG_EUNSUPPORTED, "kdmg_lattice_set_naik: 2D U(1) lattices only");
+  if (!enable) {
+    lat->naik = 0;
+    lat->c1 = 1.0;
+    lat->c3 = 0.0;
+    return KDMG_OK;
+  }
+  KDMG_CHECK(lat->dims[0] >= 8 && lat->dims[1] >= 8, KDMG_EINVAL,
+             "kdmg_lattice_set_naik: extents must be at least 8 (three-link hops)");
+  hipStream_t st = (hipStream_t)stream;
+  const int Lx = lat->dims[0], Lt = lat->dims[1];
+  const long V = lat->volume, f = 2 * lat->half;
+  const c64* U = lat->h_links.data();
+  std::vector<c64> natw(2 * V), blkw(2 * V);
+  for (long x = 0; x < V; ++x) {
+    const int x0 = (int)(x % Lx), x1 = (int)(x / Lx);
+    for (int mu = 0; mu < 2; ++mu) {
+      const int L = mu == 0 ? Lx : Lt, xm = mu == 0 ? x0 : x1;
+      c64 w{1.0, 0.0};
+      for (int k = 0; k < 3; ++k) {
+        const int y0 = mu == 0 ? (x0 + k) % Lx : x0, y1 = mu == 1 ? (x1 + k) % Lt : x1;
+        w = w * U[(long)mu * V + (long)y1 * Lx + y0];
+      }
+      const double eta = mu == 1 && (x0 & 1) ? -1.0 : 1.0;
+      const double bc = xm + 3 >= L ? (double)lat->bc[mu] : 1.0;
+      const c64 wf{0.5 * eta * bc * w.re, 0.5 * eta * bc * w.im};
+      natw[(long)mu * V + x] = wf;
+      blkw[(long)mu * f + blk_site_index(lat->g, x0, x1)] = wf;
+    }
+  }
+  lat->natw64.alloc(sizeof(c64) * 2 * V);
+  lat->natw16.alloc(sizeof(c16) * 2 * V);
+  lat->wl64.alloc(sizeof(c64) * 2 * f);
+  lat->wl16.alloc(sizeof(c16) * 2 * f);
+  KDMG_HIP(hipMemcpyAsync(lat->natw64.p, natw.data(), lat->natw64.bytes, hipMemcpyHostToDevice, st));
+  KDMG_HIP(hipMemcpyAsync(lat->wl64.p, blkw.data(), lat->wl64.bytes, hipMemcpyHostToDevice, st));
+  convert<_Float16, double>(lat->natw16.as<c16>(), lat->natw64.as<c64>(), 2 * V, 1, nullptr, st);
+  convert<_Float16, double>(lat->wl16.as<c16>(), lat->wl64.as<c64>(), 2 * f, 1, nullptr, st);
+  KDMG_HIP(hipStreamSynchronize(st));
+  lat->naik = 1;
+  lat->c1 = 9.0 / 8.0;
+  lat->c3 = -1.0 / 24.0;
+  KDMG_API_END
+}
+
 extern "C" void kdmg_lattice_destroy(kdmg_lattice* lat) { delete lat; }
 
 extern "C" kdmg_status kdmg_lattice_footprint(const kdmg_lattice* lat, size_t* bytes) {
@@ -283,6 +332,21 @@ extern "C" kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const 
     } else {
       throw Error(KDMG_EINVAL, "kdmg_apply_D: bad precision");
     }
+    return KDMG_OK;
+  }
+  if (lat->naik) {
+    const dim3 gn(cdiv(V, 256), nrhs);
+    if (prec == KDMG_FP64)
+      hipLaunchKernelGGL((k_dslash_naik_nat<double, double, double>), gn, dim3(256), 0, st, (c64*)out,
+                         (const c64*)in, lat->nat64.as<c64>(), lat->natw64.as<c64>(), lat->dims[0], lat->dims[1], V,
+                         mass, lat->c1, lat->c3);
+    else if (prec == KDMG_MIXED)
+      hipLaunchKernelGGL((k_dslash_naik_nat<float, _Float16, float>), gn, dim3(256), 0, st, (c32*)out,
+                         (const c32*)in, lat->nat16.as<c16>(), lat->natw16.as<c16>(), lat->dims[0], lat->dims[1], V,
+                         (float)mass, (float)lat->c1, (float)lat->c3);
+    else
+      throw Error(KDMG_EINVAL, "kdmg_apply_D: bad precision");
+    KDMG_LAUNCH_CHECK();
     return KDMG_OK;
   }
   // several rhs per thread (links read once per site, more loads in flight)
@@ -376,17 +440,24 @@ void fine_op_natural(const kdmg_lattice* lat, double mass, const void* in, void*
   }
   const Cx<LT>* L = (const Cx<LT>*)(sizeof(R) == 8 ? lat->links64.p : lat->links16.p);
   if (op == OP_SCHUR) {
+    KDMG_CHECK(!lat->naik, KDMG_EUNSUPPORTED,
+               "the Naik-improved operator has no KD-block-parity Schur form (its three-link hops join "
+               "blocks of the same parity)");
     launch_permute<R, R>(a, h, vin, V / 2, lat->perm_even.as<int>(), V / 2, 1, nrhs, st);
     schur_apply<R, LT>(b, a, nullptr, t, w, L, g, mass, nullptr, nrhs, st);
     launch_permute<R, R>(vout, V / 2, b, h, lat->perm_even.as<int>(), V / 2, 0, nrhs, st);
   } else {
+    const Fine2<LT> F = fine2<LT>(*lat, mass);
     launch_permute<R, R>(a, f, vin, V, lat->perm_full.as<int>(), V, 1, nrhs, st);
-    if (op == OP_A)
-      fullA_apply<LT, R>(b, a, t, L, g, mass, nullptr, nrhs, st);
-    else if (op == OP_ADAG)
-      fullAdag_apply<LT, R>(b, nullptr, a, t, L, g, mass, nullptr, nrhs, st);
-    else
-      launch_binv<R, LT, R>(b, f, nullptr, 0, a, f, nullptr, 0, L, g, 0, 2, mass, 0, nullptr, nrhs, st);
+    if (op == OP_A) {
+      fine2_A<R, LT>(b, a, nullptr, t, F, nullptr, nrhs, st);
+    } else if (op == OP_ADAG) {
+      fine2_Adag<R, LT>(b, nullptr, a, t, F, nullptr, nrhs, st);
+    } else {
+      // B^-1 = B~^-1 / s for the rescaled block
+      launch_binv<R, LT, R>(b, f, nullptr, 0, a, f, nullptr, 0, L, g, 0, 2, F.me, 0, nullptr, nrhs, st);
+      if (F.s != 1.0) launch_map(OpAxpby<R>{b, b, nullptr, f, 1.0 / F.s, 0.0, nullptr}, f, nrhs, st);
+    }
     launch_permute<R, R>(vout, V, b, f, lat->perm_full.as<int>(), V, 0, nrhs, st);
   }
   if (own.p) KDMG_HIP(hipStreamSynchronize(st));  // the work space is freed on return
@@ -482,4 +553,5 @@ extern "C" void kdmg_default_params(kdmg_mg_params* p) {
   p->outer_stall = 0;
   p->coarse_tail = 16;
   p->coarse_solver = 0;
+  p->fine_op = 0;
 }

@@ -384,6 +384,13 @@ class Runner {
         else
           schur_apply4<T, _Float16, float>(out, in, resid, L.v<T>(L.t), L.v<T>(L.w), fine4_mixed(), act, nrhs_,
                                            c_.st);
+      } else if (h_.fine_full) {
+        using LT = std::conditional_t<sizeof(T) == 8, double, _Float16>;
+        const Fine2<LT> F = fine2<LT>(lat, h_.mass);
+        if (h_.naive)
+          fine2_D<T, LT>(out, in, resid, F, act, nrhs_, c_.st);
+        else
+          fine2_A<T, LT>(out, in, resid, L.v<T>(L.t), F, act, nrhs_, c_.st);
       } else if constexpr (sizeof(T) == 8) {
         schur_apply<T, double>(out, in, resid, L.v<T>(L.t), L.v<T>(L.w), lat.links64.as<c64>(), lat.g,
                                h_.mass, act, nrhs_, c_.st);
@@ -408,11 +415,12 @@ class Runner {
     with_prec(N.prec, [&](auto tag) {
       using TO = decltype(tag);
       Cx<TO>* out = N.v<TO>(N.b);
-      const long si = l == 0 ? h_.lat->half : ws_.lv[l].n;
+      const long si = ws_.lv[l].n;
+      const int even_only = l == 0 && !h_.fine_full;
       if (p16)
-        transfer_restrict<TO, _Float16, TI, TO>(T, *h_.lat, &h_.L[l], out, in, si, l == 0, act, nrhs_, c_.st);
+        transfer_restrict<TO, _Float16, TI, TO>(T, *h_.lat, &h_.L[l], out, in, si, even_only, act, nrhs_, c_.st);
       else
-        transfer_restrict<TO, double, TI, TO>(T, *h_.lat, &h_.L[l], out, in, si, l == 0, act, nrhs_, c_.st);
+        transfer_restrict<TO, double, TI, TO>(T, *h_.lat, &h_.L[l], out, in, si, even_only, act, nrhs_, c_.st);
     });
   }
 
@@ -422,14 +430,15 @@ class Runner {
     LevelWS& N = ws_.lv[l + 1];
     const Transfer& T = h_.T[l];
     const bool p16 = ws_.prec == KDMG_MIXED;
-    const long so = l == 0 ? h_.lat->half : ws_.lv[l].n;
+    const long so = ws_.lv[l].n;
+    const int npar = l == 0 && h_.fine_full ? 2 : 1;
     with_prec(N.prec, [&](auto tag) {
       using TI = decltype(tag);
       const Cx<TI>* in = N.v<TI>(N.xs);
       if (p16)
-        transfer_prolong<TO, _Float16, TI, TO>(T, *h_.lat, x, so, x, so, in, 1, act, nrhs_, c_.st);
+        transfer_prolong<TO, _Float16, TI, TO>(T, *h_.lat, x, so, x, so, in, npar, act, nrhs_, c_.st);
       else
-        transfer_prolong<TO, double, TI, TO>(T, *h_.lat, x, so, x, so, in, 1, act, nrhs_, c_.st);
+        transfer_prolong<TO, double, TI, TO>(T, *h_.lat, x, so, x, so, in, npar, act, nrhs_, c_.st);
     });
   }
 
@@ -506,10 +515,16 @@ class Runner {
   int outer(double tol) {
     const kdmg_mg_params& P = h_.params;
     const kdmg_lattice& lat = *h_.lat;
-    const long n = lat.half;
     LevelWS& L0 = ws_.lv[0];
+    const long n = L0.n;
     auto op64 = [&](c64* o, const c64* i, const c64* res, const int* a) {
-      if (lat.nd == 4)
+      if (h_.fine_full) {
+        const Fine2<double> F = fine2<double>(lat, h_.mass);
+        if (h_.naive)
+          fine2_D<double, double>(o, i, res, F, a, nrhs_, c_.st);
+        else
+          fine2_A<double, double>(o, i, res, ws_.tfull.as<c64>(), F, a, nrhs_, c_.st);
+      } else if (lat.nd == 4)
         schur_apply4<double, double, double>(o, i, res, ws_.tfull.as<c64>(), ws_.wfull.as<c64>(), fine4_64(), a,
                                              nrhs_, c_.st);
       else
@@ -527,7 +542,8 @@ class Runner {
         convert<double, float>(z, z32, n, nrhs_, a, c_.st);
       }
     };
-    return gcr_solve<double>(c_, nrhs_, n, ws_.bt.as<c64>(), ws_.ye.as<c64>(), ws_.re.as<c64>(),
+    return gcr_solve<double>(c_, nrhs_, n, h_.fine_full ? ws_.bfull.as<c64>() : ws_.bt.as<c64>(),
+                             ws_.ye.as<c64>(), ws_.re.as<c64>(),
                              ws_.Zo.as<c64>(), ws_.Wo.as<c64>(), P.outer_restart, P.outer_maxit, tol,
                              ws_.bnorm2.as<double>(), ws_.kout.k, nullptr, op64, prec,
                              trace_enabled(), P.outer_stall);
@@ -569,11 +585,12 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
   A(ws->xfull, c64s * f);
   A(ws->tfull, c64s * f);
   A(ws->wfull, c64s * f);
+  const long n0 = h.fine_full ? f : half;  // the fine solve's space
   A(ws->bt, c64s * half);
-  A(ws->ye, c64s * half);
-  A(ws->re, c64s * half);
-  A(ws->Zo, c64s * half * P.outer_restart);
-  A(ws->Wo, c64s * half * P.outer_restart);
+  A(ws->ye, c64s * n0);
+  A(ws->re, c64s * n0);
+  A(ws->Zo, c64s * n0 * P.outer_restart);
+  A(ws->Wo, c64s * n0 * P.outer_restart);
   A(ws->bnorm2, sizeof(double) * nrhs);
   A(ws->rnorm2, sizeof(double) * nrhs);
   ws->kout.init(nrhs, P.outer_restart);
@@ -583,7 +600,7 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
     const bool coarsest = l == h.nlevels - 1;
     L.prec = (prec == KDMG_MIXED && !coarsest) ? Prec::F32 : Prec::F64;
     L.esz = L.prec == Prec::F64 ? sizeof(c64) : sizeof(c32);
-    L.n = l == 0 ? half : h.L[l].n();
+    L.n = l == 0 ? n0 : h.L[l].n();
     const size_t v = L.esz * nrhs * L.n;
     if (!coarsest) {
       A(L.r1, v);
@@ -635,8 +652,8 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
     }
   }
   if (prec == KDMG_MIXED) {
-    A(ws->xin32, sizeof(c32) * nrhs * half);
-    A(ws->xout32, sizeof(c32) * nrhs * half);
+    A(ws->xin32, sizeof(c32) * nrhs * n0);
+    A(ws->xout32, sizeof(c32) * nrhs * n0);
   }
   ws->bytes = tot;
   return ws.release();
@@ -644,19 +661,19 @@ SolveWS* make_ws(kdmg_hierarchy& h, int nrhs, kdmg_prec prec, hipStream_t st) {
 
 size_t ws_bytes_estimate(const kdmg_hierarchy& h, int nrhs, kdmg_prec prec) {
   const kdmg_mg_params& P = h.params;
-  const long half = h.lat->half, f = 2 * half;
-  size_t b = sizeof(c64) * (size_t)nrhs * (5 * f + (3 + 2 * P.outer_restart) * half);
+  const long half = h.lat->half, f = 2 * half, n0 = h.fine_full ? f : half;
+  size_t b = sizeof(c64) * (size_t)nrhs * (5 * f + half + (2 + 2 * P.outer_restart) * n0);
   for (int l = 0; l < h.nlevels; ++l) {
     const bool coarsest = l == h.nlevels - 1;
     const size_t esz = (prec == KDMG_MIXED && !coarsest) ? 8 : 16;
-    const long n = l == 0 ? half : h.L[l].n();
+    const long n = l == 0 ? n0 : h.L[l].n();
     const size_t v = esz * nrhs * n;
     if (!coarsest) b += 4 * v;
     if (l == 0) b += 2 * esz * nrhs * f;
     else if (coarsest && P.coarse_solver == 1) b += 3 * v + (size_t)dense_apply_splits(n, nrhs) * v;
     else b += 3 * v + (coarsest ? 2 * v : 2 * v * P.inter_restart);
   }
-  if (prec == KDMG_MIXED) b += 2 * sizeof(c32) * nrhs * half;
+  if (prec == KDMG_MIXED) b += 2 * sizeof(c32) * nrhs * n0;
   return b;
 }
 
@@ -730,8 +747,9 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   launch_permute<double, double>(ws.bfull.as<c64>(), f, (const c64*)b, V, lat.perm_full.as<int>(), V, 1,
                                  nrhs, st);
   launch_map_reduce<1>(OpResidNorm{ws.bfull.as<c64>(), f, f, ws.bnorm2.as<double>()}, f, nrhs, 1, c.rs, st);
-  // b~_e = b_e - A_eo b_o = b_e - C_eo B_o^-1 b_o
-  if (d4) {
+  // b~_e = b_e - A_eo b_o = b_e - C_eo B_o^-1 b_o  (the full-lattice solve takes b as it is)
+  if (h->fine_full) {
+  } else if (d4) {
     const Fine4<double, double> F = run.fine4_64();
     launch4_binv<double, double>(ws.tfull.as<c64>(), f, ws.bfull.as<c64>(), f, nullptr, 0, F.Bv, F.g, 1, 1, 0,
                                  nullptr, nrhs, st);
@@ -744,6 +762,19 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
                                        nullptr, 0, 0.0, -1.0, L64, g, 0, 1, h->mass, 0, 0, nullptr, nrhs, st);
   }
   const int its = run.outer(tol);
+  if (h->fine_full) {
+    // x = y (D itself) or x = B^-1 y = B~^-1 y / s
+    const Fine2<double> F = fine2<double>(lat, h->mass);
+    if (h->naive) {
+      launch_map(OpStridedCopy{ws.xfull.as<c64>(), f, ws.ye.as<c64>(), f, f}, f, nrhs, st);
+    } else {
+      launch_binv<double, double, double>(ws.xfull.as<c64>(), f, nullptr, 0, ws.ye.as<c64>(), f, nullptr, 0, L64, g,
+                                          0, 2, F.me, 0, nullptr, nrhs, st);
+      if (F.s != 1.0)
+        launch_map(OpAxpby<double>{ws.xfull.as<c64>(), ws.xfull.as<c64>(), nullptr, f, 1.0 / F.s, 0.0, nullptr}, f,
+                   nrhs, st);
+    }
+  } else {
   // y_o = b_o - C_oe B_e^-1 y_e ; x = B^-1 y
   launch_map(OpStridedCopy{ws.yfull.as<c64>(), f, ws.ye.as<c64>(), half, half}, half, nrhs, st);
   if (d4) {
@@ -762,9 +793,13 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
     launch_binv<double, double, double>(ws.xfull.as<c64>(), f, nullptr, 0, ws.yfull.as<c64>(), f, nullptr, 0,
                                         L64, g, 0, 2, h->mass, 0, nullptr, nrhs, st);
   }
+  }
   launch_permute<double, double>((c64*)x, V, ws.xfull.as<c64>(), f, lat.perm_full.as<int>(), V, 0, nrhs, st);
   // true residual ||b - D x|| in FP64
-  if (d4) {
+  if (h->fine_full) {
+    fine2_D<double, double>(ws.tfull.as<c64>(), ws.xfull.as<c64>(), ws.bfull.as<c64>(),
+                            fine2<double>(lat, h->mass), nullptr, nrhs, st);
+  } else if (d4) {
     const Fine4<double, double> F = run.fine4_64();
     launch4_hop<double, double>(ws.tfull.as<c64>(), f, ws.xfull.as<c64>(), f, ws.bfull.as<c64>(), f, nullptr, 0,
                                 0.0, -1.0, F.lk, F.nb4, F.g, 0, 2, F.m, 2, 0, nullptr, nrhs, st);

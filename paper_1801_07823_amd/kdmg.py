@@ -36,7 +36,7 @@ class kdmg_mg_params(ctypes.Structure):
                 ("inter_restart", ctypes.c_int), ("inter_maxit", ctypes.c_int),
                 ("inter_tol", ctypes.c_double), ("coarse_tol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int), ("outer_stall", ctypes.c_int),
-                ("coarse_tail", ctypes.c_int), ("coarse_solver", ctypes.c_int)]
+                ("coarse_tail", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("fine_op", ctypes.c_int)]
 
 
 class kdmg_solve_info(ctypes.Structure):
@@ -61,6 +61,7 @@ _SIGS = {
     "kdmg_init": (_I, [_I]),
     "kdmg_lattice_create": (_I, [_I, ctypes.POINTER(_I), _I, ctypes.POINTER(_I), _P, _P, ctypes.POINTER(_P)]),
     "kdmg_lattice_destroy": (None, [_P]),
+    "kdmg_lattice_set_naik": (_I, [_P, _I, _P]),
     "kdmg_lattice_footprint": (_I, [_P, ctypes.POINTER(_S)]),
     "kdmg_apply_D": (_I, [_P, _D, _P, _P, _I, _I, _P]),
     "kdmg_apply_A": (_I, [_P, _D, _P, _P, _I, _I, _I, _P]),
@@ -192,6 +193,11 @@ class Lattice:
         _check(_lib.kdmg_lattice_create(nd, arr, nc, bca, links.ctypes.data_as(_P), _stream(stream),
                                         ctypes.byref(h)))
         self.handle = h
+
+    def set_naik(self, enable=True, stream=None):
+        """kdmg_lattice_set_naik: switch to the Naik-improved operator (2D U(1))."""
+        _check(_lib.kdmg_lattice_set_naik(self.handle, 1 if enable else 0, _stream(stream)))
+        self.naik = bool(enable)
 
     def footprint(self):
         b = _S()
