@@ -32,18 +32,22 @@ WORKLOAD = {"workload": "2D U(1) staggered KD-MG solve", "lattice": [256, 256], 
             "coarsest": "exact: product with the explicit FP64 inverse of the 6144-dof coarsest operator "
                         "(option beside Table 1's CGNE tol 0.2, measured in cgne_coarsest)",
             "gauge": "quenched heatbath, 200 sweeps"}
-# HBM traffic of the dominant kernels from two rocprofv3 --pmc passes
-# (FETCH_SIZE, then WRITE_SIZE) over `bench.py --kernel-profile`, in bytes
-# per launch averaged over k_cgne_A and k_cgne_B, for the launch shape the
-# tuner picks here (MFMA, blocks staged in LDS, 32 rhs per workgroup, 1024
-# threads; taken from the dispatches of its timing runs, where every rhs is
-# active).  FETCH_SIZE read 32784 KiB
-# and WRITE_SIZE 65536 KiB for a 64 MiB elementwise copy, so FETCH_SIZE is
-# scaled by 2.0 and WRITE_SIZE by 1.0.  Valid only for the kernel source it
-# was measured on (sha256 of coarse_fast.cuh); otherwise reported as null.
-TRAFFIC = {"coarse_fast_sha256": "ef7256408755d5ae044f1bb7fa62d08e7c1c28a7ce0478d42ec5b3e42db524ee",
-           "n_vec_2": 12,
-           "bytes_per_launch": ((13688.1 + 12286.7) * 2.0 + (6400.0 + 3328.6) * 1.0) / 2 * 1024}
+# HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE) over `bench.py --kernel-profile`, scaled by what the same
+# counters read for a 64 MiB elementwise copy in that run (FETCH_SIZE 32782.7
+# KiB -> x2.0, WRITE_SIZE 65536 KiB -> x1.0).  Valid only for the kernel source
+# it was measured on (sha256 of the file); otherwise reported as null.
+#   * the headline's coarsest product, k_dn_apply + k_dn_reduce per call:
+#     FETCH 310009.3 + 12301.2 KiB, WRITE 24576.0 + 3072.4 KiB;
+#   * the Table 1 form's fused CGNE pair k_cgne_A / k_cgne_B (average of the
+#     pair, 32 rhs, the tuned MFMA shape).
+TRAFFIC = {"dense": {"file": "coarsest_dense.hip",
+                     "sha256": "f02b12428d57c031549e3f789e14e02e72bbce0e915a3d020e3a18f97ce14824",
+                     "bytes_per_launch": ((310009.3 + 12301.2) * 2.0 + (24576.0 + 3072.4) * 1.0) * 1024},
+           "cgne": {"file": "coarse_fast.cuh",
+                    "sha256": "ef7256408755d5ae044f1bb7fa62d08e7c1c28a7ce0478d42ec5b3e42db524ee",
+                    "n_vec_2": 12,
+                    "bytes_per_launch": ((13688.1 + 12286.7) * 2.0 + (6400.0 + 3328.6) * 1.0) / 2 * 1024}}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
@@ -148,14 +152,15 @@ def start_cpu_leg(nproc):
 
 # ------------------------------------------------------------------ GPU leg
 
-def traffic_per_launch():
+def traffic_per_launch(kind):
     import hashlib
-    src = os.path.join(ROOT, "paper_1801_07823_amd", "csrc", "coarse_fast.cuh")
+    t = TRAFFIC[kind]
+    src = os.path.join(ROOT, "paper_1801_07823_amd", "csrc", t["file"])
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if sha != TRAFFIC["coarse_fast_sha256"] or NV2 != TRAFFIC["n_vec_2"]:
+    if sha != t["sha256"] or NV2 != t.get("n_vec_2", NV2):
         return None
-    return TRAFFIC["bytes_per_launch"]
+    return t["bytes_per_launch"]
 
 
 def event_time(fn, reps):
@@ -589,6 +594,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle worker processes of the CPU baseline (0: available cores - 2, at most 14)")
+    ap.add_argument("--naik-steps", type=int, default=2,
+                    help="timed steps of the Naik-operator KD-MG solve (0: skip)")
+    ap.add_argument("--negative-control", type=int, default=1,
+                    help="1: report the stalled Galerkin MG on D itself beside the headline")
     ap.add_argument("--cgne-steps", type=int, default=2,
                     help="timed steps of the Table 1 CGNE-coarsest variant (0: skip)")
     ap.add_argument("--kernel-profile", action="store_true",
@@ -725,9 +734,49 @@ def main():
                 "level3_avg": [round(i["level_avg_its"][1], 1) for i in infc],
                 "max_true_rel_resid": max(i["true_rel_resid"] for i in infc),
                 "k_cgne_us_per_launch": t_c * 1e6, "k_cgne_hbm_frac": bytes_c / t_c / 1e9 / HBM_PEAK_GBS,
-                "traffic": traffic_per_launch()}
+                "traffic": traffic_per_launch("cgne")}
         del hc, xc
         print("cgne coarsest: %.1f solves/s" % cgne["value"], file=sys.stderr, flush=True)
+
+    # the Naik-improved operator (Sec. 2.1) on the same field, rhs and null-vector
+    # starts, the same hierarchy shape and coarsest solve; its fine solve runs
+    # on the full lattice (no block-parity Schur form)
+    naik = None
+    if a.naik_steps > 0:
+        latn = kdmg.Lattice(DIMS, U)
+        latn.set_naik(True)
+        t0 = time.perf_counter()
+        hn = kdmg.Hierarchy(latn, MASS, params(), psi0)
+        torch.cuda.synchronize()
+        setup_n = time.perf_counter() - t0
+        xn = torch.empty_like(b)
+        kdmg.kdmg_solve(hn, b, xn, NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(a.naik_steps):
+            infn, _ = kdmg.kdmg_solve(hn, b, xn, NRHS, 1e-10, prec=kdmg.KDMG_MIXED)
+        torch.cuda.synchronize()
+        Tn = time.perf_counter() - t0
+        naik = {"value": NRHS * a.naik_steps / Tn, "unit": "solves/s", "steps": a.naik_steps, "setup_s": setup_n,
+                "operator": "Naik-improved staggered D, coefficients 9/8 and -1/24, three-link transporters",
+                "outer": [i["outer_its"] for i in infn], "level2_avg": [round(i["level_avg_its"][0], 2) for i in infn],
+                "max_true_rel_resid": max(i["true_rel_resid"] for i in infn),
+                "converged": all(i["converged"] for i in infn)}
+        print("naik: %.1f solves/s" % naik["value"], file=sys.stderr, flush=True)
+        del hn, xn, latn
+
+    # negative control (Sec. 3.2): the same K-cycle coarsening D itself instead
+    # of A = D B^-1, from the same starts, capped at 30 outer iterations
+    negative = None
+    if a.negative_control:
+        hd = kdmg.Hierarchy(lat, MASS, params(fine_op=1, outer_maxit=30), psi0)
+        xd = torch.empty_like(b)
+        infd, std = kdmg.kdmg_solve(hd, b[:4].contiguous(), xd[:4], 4, 1e-10, prec=kdmg.KDMG_MIXED,
+                                    raise_on_noconv=False)
+        negative = {"method": "Galerkin multigrid on D itself (fine_op = 1), 4 rhs, outer FGCR capped at 30",
+                    "converged": [i["converged"] for i in infd],
+                    "true_rel_resid": [i["true_rel_resid"] for i in infd]}
+        del hd, xd
 
     # the paper's comparison solver: CG on the site even/odd Schur system,
     # FP64, the same NRHS rhs batched, to the same true-residual target
@@ -810,7 +859,7 @@ def main():
                 "peak": FP64_PEAK_TFLOPS if mfma_bound else HBM_PEAK_GBS,
                 "unit": "TFLOP/s" if mfma_bound else "GB/s",
                 "frac": (t_mfma if mfma_bound else t_hbm) / t_c,
-                "traffic": None,
+                "traffic": traffic_per_launch("dense"),
                 "us_per_launch": t_c * 1e6, "launches_timed": cs_launches,
                 "algorithmic_bytes_per_launch": bytes_c, "flops_per_launch": flops,
                 "hbm_gbs": bytes_c / t_c / 1e9}
@@ -837,6 +886,8 @@ def main():
                             "outer_its": [i["outer_its"] for i in info64],
                             "mixed_over_fp64": value / fp64_rate if fp64_rate else None},
         "cgne_coarsest": cgne,
+        "naik": naik,
+        "negative_control": negative,
         "cg_eo": cg_eo,
         "dslash": dslash,
         "roofline": roofline,
