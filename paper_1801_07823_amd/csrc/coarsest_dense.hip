@@ -188,10 +188,12 @@ __global__ __launch_bounds__(256) void k_dn_adj(c64* X, const c64* Ninv, const c
 }
 
 // part[s][r][i] = sum_{k in split s} X[i][k] b[r][k] for a 64-row x (16 NT)-rhs
-// tile.  Each 32-wide k-chunk of X and b is staged in LDS with coalesced
-// loads; wave w contracts rows 16w..16w+15 against NT 16-rhs tiles with
-// v_mfma_f64_16x16x4 (Gauss: three real products per complex one).  Loads
-// past the end of a split read a clamped address and are replaced by zero.
+// tile.  Each 32-wide k-chunk of X and b is staged in LDS from coalesced
+// loads; the next chunk's loads are issued into registers before the current
+// chunk is contracted, so their latency overlaps the MFMAs.  Wave w contracts
+// rows 16w..16w+15 against NT 16-rhs tiles with v_mfma_f64_16x16x4 (Gauss:
+// three real products per complex one).  Loads past the end of a split read a
+// clamped address and are replaced by zero.
 template <int NT>
 __global__ __launch_bounds__(256) void k_dn_apply(c64* part, const c64* __restrict__ X, const c64* __restrict__ b,
                                                   long n, int nrhs, long kc) {
@@ -211,22 +213,37 @@ __global__ __launch_bounds__(256) void k_dn_apply(c64* part, const c64* __restri
     p2[t] = v4{0, 0, 0, 0};
     p3[t] = v4{0, 0, 0, 0};
   }
-  for (long kb = k0; kb < k1; kb += 32) {
+  c64 rx[8], rbv[2 * NT];
+  auto fetch = [&](long kb) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int e = j * 256 + threadIdx.x, r = e >> 5, k = e & 31;
       const long gr = min(row0 + r, n - 1), gk = kb + k;
       const c64 v = X[gr * n + min(gk, n - 1)];
-      Xs[r][k] = gk < k1 ? v : c64{0, 0};
+      rx[j] = gk < k1 ? v : c64{0, 0};
     }
 #pragma unroll
     for (int j = 0; j < 2 * NT; ++j) {
       const int e = j * 256 + threadIdx.x, c = e >> 5, k = e & 31;
       const long gc = min(rb + c, nrhs - 1), gk = kb + k;
       const c64 v = b[gc * n + min(gk, n - 1)];
-      Bs[c][k] = gk < k1 ? v : c64{0, 0};
+      rbv[j] = gk < k1 ? v : c64{0, 0};
+    }
+  };
+  fetch(k0);
+  for (long kb = k0; kb < k1; kb += 32) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = j * 256 + threadIdx.x;
+      Xs[e >> 5][e & 31] = rx[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * NT; ++j) {
+      const int e = j * 256 + threadIdx.x;
+      Bs[e >> 5][e & 31] = rbv[j];
     }
     __syncthreads();
+    if (kb + 32 < k1) fetch(kb + 32);  // in flight during the contraction below
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const c64 a = Xs[16 * w + (l & 15)][4 * s + (l >> 4)];
