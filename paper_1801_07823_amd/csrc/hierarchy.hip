@@ -628,7 +628,9 @@ extern "C" kdmg_status kdmg_hierarchy_set_mass(kdmg_hierarchy* h, const kdmg_hie
     h->fine_full = base->fine_full;
     copy_tuned(*base, *h);
   }
+  KDMG_CHECK(!ws_busy(h->ws), KDMG_EBUSY, "hierarchy busy");
   h->mass = mass;
+  reset_graphs(h->ws);
   rebuild_coarse_ops(*h, (hipStream_t)stream);
   KDMG_API_END
 }

@@ -377,6 +377,7 @@ bool autotune_enabled();
 struct SolveWS;  // solver workspace (solver.hip)
 void destroy_ws(SolveWS*);
 bool ws_busy(const SolveWS*);
+void reset_graphs(SolveWS*);
 size_t derived_footprint(const kdmg_hierarchy& base, int nrhs, kdmg_prec prec);
 
 }  // namespace kdmg

@@ -10,7 +10,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <tuple>
 
 #include "algos.h"
 #include "api_guard.h"
@@ -100,11 +102,41 @@ struct LevelWS {
   template <class T> Cx<T>* v(DevBuf& d) const { return d.as<Cx<T>>(); }
 };
 
+// Captured halves of the K-cycle on the level just above an exact coarsest
+// solve: everything before the coarsest product (start, pre-smoothing,
+// restriction) and everything after it (prolongation, residual,
+// post-smoothing) contains no host decision, so each is one hipGraph per
+// (level, output column, input vector) of the intermediate GCR.  The
+// coarsest product runs between the two replays as plain launches, where the
+// live kernel timing can bracket it.  Captured on a private stream, replayed
+// on the solve's stream.
+struct KCycleGraphs {
+  struct Pair {
+    hipGraph_t g[2] = {nullptr, nullptr};
+    hipGraphExec_t x[2] = {nullptr, nullptr};
+  };
+  hipStream_t cap = nullptr;
+  std::map<std::tuple<int, const void*, const void*, const void*>, Pair> m;
+  bool failed = false;
+  KCycleGraphs() = default;
+  KCycleGraphs(const KCycleGraphs&) = delete;
+  KCycleGraphs& operator=(const KCycleGraphs&) = delete;
+  ~KCycleGraphs() {
+    for (auto& kv : m)
+      for (int i = 0; i < 2; ++i) {
+        if (kv.second.x[i]) (void)hipGraphExecDestroy(kv.second.x[i]);
+        if (kv.second.g[i]) (void)hipGraphDestroy(kv.second.g[i]);
+      }
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 struct SolveWS {
   int nrhs = 0;
   kdmg_prec prec = KDMG_FP64;
   std::atomic<int> busy{0};
   CtxAlloc ctx;
+  std::unique_ptr<KCycleGraphs> kgraphs = std::make_unique<KCycleGraphs>();
   // outer (FP64, even half)
   DevBuf bfull, yfull, xfull, tfull, wfull, bt, ye, re, Zo, Wo, bnorm2, rnorm2, xin32, xout32;
   KrylovAlloc kout;
@@ -113,6 +145,12 @@ struct SolveWS {
 };
 
 void destroy_ws(SolveWS* w) { delete w; }
+
+// Captured K-cycle graphs hold the transfer and operator pointers of the
+// hierarchy they were captured on; drop them when those change.
+void reset_graphs(SolveWS* w) {
+  if (w) w->kgraphs = std::make_unique<KCycleGraphs>();
+}
 bool ws_busy(const SolveWS* w) { return w && w->busy.load() != 0; }
 
 namespace {
@@ -371,6 +409,8 @@ int cgne_fused(const Ctx& c, const CoarseLevel& L, LevelWS& W, int nrhs, const c
 class Runner {
  public:
   Runner(kdmg_hierarchy& h, SolveWS& ws) : h_(h), ws_(ws), c_(ws.ctx.c), nrhs_(ws.nrhs) {}
+  // the same solve state, launching on another stream (graph capture)
+  Runner(kdmg_hierarchy& h, SolveWS& ws, const Ctx& c) : h_(h), ws_(ws), c_(c), nrhs_(ws.nrhs) {}
 
   // level-l operator in the level's precision: out = op(in) or resid - op(in)
   template <class T>
@@ -445,21 +485,97 @@ class Runner {
   // K-cycle on level l: x ~= op_l^-1 r for the rhs in `act`
   template <class T>
   void kcycle(int l, Cx<T>* x, const Cx<T>* r, const int* act) {
+    kcycle_pre<T>(l, x, r, act);
+    coarse_solve(l + 1, act);
+    kcycle_post<T>(l, x, r, act);
+  }
+
+  // x = 0, r1 = r ; MR(r1) ; restrict r1
+  template <class T>
+  void kcycle_pre(int l, Cx<T>* x, const Cx<T>* r, const int* act) {
     LevelWS& L = ws_.lv[l];
     const kdmg_mg_params& P = h_.params;
     const long n = L.n;
     Cx<T>* r1 = L.v<T>(L.r1);
-    Cx<T>* r2 = L.v<T>(L.r2);
     Cx<T>* q = L.v<T>(L.q);
     launch_map(OpKCInit{x, r1, r, n, act, sizeof(T) == 4}, n, nrhs_, c_.st);
     auto opf = [&](Cx<T>* o, const Cx<T>* i, const Cx<T>* res, const int* a) { op<T>(l, o, i, res, a); };
     const KrylovState kmr = L.kmr.under(act);
     mr_smooth<T>(c_, nrhs_, n, x, r1, q, P.mr_its, P.mr_omega, kmr, opf);
     restrict_to<T>(l, r1, act);
-    coarse_solve(l + 1, act);
+  }
+
+  // x += P e ; r2 = r - op x ; MR(r2)
+  template <class T>
+  void kcycle_post(int l, Cx<T>* x, const Cx<T>* r, const int* act) {
+    LevelWS& L = ws_.lv[l];
+    const kdmg_mg_params& P = h_.params;
+    const long n = L.n;
+    Cx<T>* r2 = L.v<T>(L.r2);
+    Cx<T>* q = L.v<T>(L.q);
+    auto opf = [&](Cx<T>* o, const Cx<T>* i, const Cx<T>* res, const int* a) { op<T>(l, o, i, res, a); };
+    const KrylovState kmr = L.kmr.under(act);
     prolong_add<T>(l, x, act);
     op<T>(l, r2, x, r, act);
     mr_smooth<T>(c_, nrhs_, n, x, r2, q, P.mr_its, P.mr_omega, kmr, opf);
+  }
+
+  // The K-cycle with its halves replayed from captured graphs (see
+  // KCycleGraphs); falls back to plain launches if capture is unavailable.
+  template <class T>
+  void kcycle_graphed(int l, Cx<T>* x, const Cx<T>* r, const int* act) {
+    KCycleGraphs& G = *ws_.kgraphs;
+    if (G.failed) {
+      kcycle<T>(l, x, r, act);
+      return;
+    }
+    const auto key = std::make_tuple(l, (const void*)x, (const void*)r, (const void*)act);
+    auto it = G.m.find(key);
+    if (it == G.m.end()) {
+      KCycleGraphs::Pair pr;
+      bool ok = true;
+      {
+        std::lock_guard<std::mutex> lock(hip_mem_mutex());
+        if (!G.cap && hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking) != hipSuccess) {
+          G.cap = nullptr;
+          ok = false;
+        }
+        Ctx cc = c_;
+        cc.st = G.cap;
+        Runner rc(h_, ws_, cc);
+        for (int part = 0; part < 2 && ok; ++part) {
+          if (hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            ok = false;
+            break;
+          }
+          try {
+            if (part == 0) rc.kcycle_pre<T>(l, x, r, act);
+            else rc.kcycle_post<T>(l, x, r, act);
+          } catch (const Error&) {
+            ok = false;
+          }
+          hipGraph_t g = nullptr;
+          if (hipStreamEndCapture(G.cap, &g) != hipSuccess || !g) ok = false;
+          pr.g[part] = g;
+          if (ok && hipGraphInstantiate(&pr.x[part], g, nullptr, nullptr, 0) != hipSuccess) ok = false;
+        }
+      }
+      if (!ok) {
+        (void)hipGetLastError();
+        for (int i = 0; i < 2; ++i) {
+          if (pr.x[i]) (void)hipGraphExecDestroy(pr.x[i]);
+          if (pr.g[i]) (void)hipGraphDestroy(pr.g[i]);
+        }
+        G.failed = true;
+        kcycle<T>(l, x, r, act);
+        return;
+      }
+      it = G.m.emplace(key, pr).first;
+    }
+    KDMG_HIP(hipGraphLaunch(it->second.x[0], c_.st));
+    coarse_solve(l + 1, act);
+    KDMG_HIP(hipGraphLaunch(it->second.x[1], c_.st));
+    h_.timer.graph_replays += 2;
   }
 
   // approximate solve on level l >= 1 of  op_l xs = b  (buffers of level l)
@@ -504,7 +620,13 @@ class Runner {
         }
       } else {
         const KrylovState& ks = L.ks.k;
-        auto prec = [&](Cx<T>* z, const Cx<T>* rr, const int* a) { kcycle<T>(l, z, rr, a); };
+        // below this level only the exact coarsest product: no host decision,
+        // so the K-cycle's halves replay as captured graphs
+        const bool graphed = h_.use_graphs && P.coarse_solver == 1 && l + 1 == h_.nlevels - 1;
+        auto prec = [&](Cx<T>* z, const Cx<T>* rr, const int* a) {
+          if (graphed) kcycle_graphed<T>(l, z, rr, a);
+          else kcycle<T>(l, z, rr, a);
+        };
         gcr_solve<T>(c_, nrhs_, n, b, x, r, L.v<T>(L.Z), L.v<T>(L.W), P.inter_restart, P.inter_maxit,
                      P.inter_tol, nullptr, ks, parent, opf, prec);
       }

@@ -126,3 +126,42 @@ def test_exact_coarsest_follows_mass_change(K):
     for q in range(3):
         xo = np.linalg.solve(A1, r[q])
         assert np.linalg.norm(xg[q] - xo) / np.linalg.norm(xo) <= 1e-9
+
+
+def test_kcycle_graphs_match_eager(K):
+    """With the exact coarsest solve, the intermediate level's K-cycle has no
+    host decision below it, and its two halves around the coarsest product
+    replay as captured hipGraphs: the replayed solve equals the plainly
+    launched one bit for bit, on repeated solves with other work between
+    them, and after a rebind to another configuration (graphs recaptured)."""
+    dims, beta, m = (32, 32), 6.0, 0.02
+    levels = [((2, 2), 8), ((2, 2), 8)]
+    U, oh, psi0 = setup(dims, beta, m, levels, 8)
+    U2, _, psi2 = setup(dims, beta, m, levels, 9)
+    lat, lat2 = K.Lattice(dims, U), K.Lattice(dims, U2)
+    nrhs = 5
+    b = dev(gaussian_vectors(nrhs, lat.volume, 57))
+    res = {}
+    for graphs in (True, False):
+        gh = K.Hierarchy(lat, m, K.make_params(levels, coarse_solver=1), psi0)
+        gh.graphs(graphs)
+        xs = []
+        for rep in range(3):
+            x = torch.empty_like(b)
+            info, _ = K.kdmg_solve(gh, b, x, nrhs, 1e-10, prec=K.KDMG_MIXED)
+            assert all(i["converged"] for i in info)
+            xs.append(x.clone())
+            torch.cuda.synchronize()
+            _ = (b * 2.0).sum()  # unrelated work between replays
+        replays = gh.counters()["graph_replays"]
+        assert (replays > 0) == graphs
+        # rebind to another configuration and back: graphs recaptured
+        other = K.Hierarchy(lat2, m, K.make_params(levels, coarse_solver=1), psi2)
+        gh.set_mass(m, base=other)
+        x2 = torch.empty_like(b)
+        info2, _ = K.kdmg_solve(gh, b, x2, nrhs, 1e-10, prec=K.KDMG_MIXED)
+        assert all(i["converged"] for i in info2)
+        res[graphs] = (xs, x2)
+    for rep in range(3):
+        assert torch.equal(res[True][0][rep], res[False][0][0])
+    assert torch.equal(res[True][1], res[False][1])
