@@ -44,7 +44,7 @@ WORKLOAD = {"workload": "2D U(1) staggered KD-MG solve", "lattice": [256, 256], 
 TRAFFIC = {"dense": {"file": "coarsest_dense.hip",
                      "sha256": "f02b12428d57c031549e3f789e14e02e72bbce0e915a3d020e3a18f97ce14824",
                      "bytes_per_launch": ((310009.3 + 12301.2) * 2.0 + (24576.0 + 3072.4) * 1.0) * 1024},
-           "cgne": {"file": "coarse_fast.cuh",
+           "cgne": {"file": "coarse_fast.h",
                     "sha256": "ef7256408755d5ae044f1bb7fa62d08e7c1c28a7ce0478d42ec5b3e42db524ee",
                     "n_vec_2": 12,
                     "bytes_per_launch": ((13688.1 + 12286.7) * 2.0 + (6400.0 + 3328.6) * 1.0) / 2 * 1024}}

@@ -117,6 +117,21 @@ typedef struct {
                                  Naik lattice, the fine solve runs on the full
                                  lattice instead of the KD-block-parity Schur
                                  system.  2D lattices only. */
+  int asymmetric;             /* 0 (default): R = P^dag with chiral doubling
+                                 (Sec. 3.3).  1: the asymmetric first
+                                 coarsening of Sec. 5 (eqs. "prcplx",
+                                 "thinlu") and App. A: per aggregate the
+                                 columns v_i and gamma5^R v_i = B eps v_i, the
+                                 rows v_i^dag and v_i^dag gamma5^L =
+                                 v_i^dag eps B^-1, bi-orthonormalised by a
+                                 thin LU without pivoting, so R != P^dag and
+                                 R P = 1.  Two levels, fine_op = 0, 2D
+                                 without Naik terms only; the transfers
+                                 depend on the mass through B, so such a
+                                 hierarchy cannot change its mass
+                                 (kdmg_hierarchy_at_mass / _set_mass return
+                                 KDMG_EUNSUPPORTED).  A zero pivot makes the
+                                 build fail with KDMG_EINVAL. */
 } kdmg_mg_params;
 
 /* Per right-hand side result of kdmg_solve. */
@@ -244,6 +259,13 @@ kdmg_status kdmg_hierarchy_get_nullvecs(const kdmg_hierarchy* h, int k, double* 
    complex128 [ndof_k][nvec], row x holding P[x, (Z(x), c(x), i)] for i < nvec,
    where Z(x), c(x) are the aggregate and chirality of dof x. */
 kdmg_status kdmg_hierarchy_get_prolongator(const kdmg_hierarchy* h, int k, double* host_out);
+/* Asymmetric coarsening only (kdmg_mg_params.asymmetric = 1, k = 0): copies
+   to host P and the transpose of R on the aggregates, complex128
+   [ndof_0][2 nvec] each: p_out[x][j] = P[x, (Z(x), j)] and
+   r_out[x][j] = R[(Z(x), j), x], coarse dof j < nvec from v_j and
+   j >= nvec from B eps v_(j - nvec) (Sec. 5, eq. "prcplx").  Either output
+   may be null.  KDMG_EINVAL for a symmetric hierarchy. */
+kdmg_status kdmg_hierarchy_get_asym_transfer(const kdmg_hierarchy* h, int k, double* p_out, double* r_out);
 /* Copies to host the coarse operator of level k >= 1 as its stencil blocks:
    complex128 [ndir][nsites][ndof][ndof], ndir = 2*nd + 1, direction 0 the
    site itself, 1 + 2*mu the neighbour Z + mu, 2 + 2*mu the neighbour Z - mu;

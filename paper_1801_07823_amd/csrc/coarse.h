@@ -13,7 +13,7 @@
 // Vectors are [rhs][X][dof].
 #pragma once
 #include "common.h"
-#include "blas.cuh"
+#include "blas.h"
 
 namespace kdmg {
 

@@ -29,7 +29,7 @@
 #include <algorithm>
 
 #include "common.h"
-#include "blas.cuh"
+#include "blas.h"
 
 namespace kdmg {
 

@@ -27,7 +27,7 @@
 // needs it instead of being stored.
 #pragma once
 #include "common.h"
-#include "blas.cuh"
+#include "blas.h"
 
 namespace kdmg {
 

@@ -28,7 +28,7 @@
 // dense column-major 48 x 48 matrix per block.
 #pragma once
 #include "common.h"
-#include "blas.cuh"
+#include "blas.h"
 
 namespace kdmg {
 

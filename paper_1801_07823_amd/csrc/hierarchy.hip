@@ -128,6 +128,31 @@ void upload(const Ctx& c, DevBuf& dst, const double* host, size_t bytes) {
 // when the level already exists (a rebuild at another mass).
 void galerkin_level1_4d(kdmg_hierarchy& h, const Ctx& c);
 
+// Asymmetric form (asym2d.h): W = B^-1 P, then A_hat = 1 + R C W.
+void galerkin_level1_asym(kdmg_hierarchy& h, const Ctx& c) {
+  const kdmg_lattice& lat = *h.lat;
+  const Geo2& g = lat.g;
+  const Transfer& T = h.T[0];
+  const int ndc = 2 * T.nv;
+  hipLaunchKernelGGL((k_galerkin_wa<double>), dim3(cdiv(g.Nb2, 256), ndc, 2), dim3(256), 0, c.st,
+                     h.gal_w.as<c64>(), T.P64.as<c64>(), lat.links64.as<c64>(), g, ndc, h.mass);
+  KDMG_LAUNCH_CHECK();
+  CoarseLevel& C1 = h.L[1];
+  if (!C1.Yt64.p) {
+    C1.nd = 2;
+    C1.dims[0] = T.a2.Ncx;
+    C1.dims[1] = T.a2.Nct;
+    C1.ndc = ndc;
+    make_nbr(C1);
+    C1.Yt64.alloc(sizeof(c64) * (size_t)C1.ndir * C1.nsites * C1.ndc * C1.ndc);
+  }
+  const int thr = ndc * ndc > 1024 ? 1024 : ndc * ndc;
+  hipLaunchKernelGGL((k_galerkin1a<double>), dim3(T.a2.Ncx * T.a2.Nct), dim3(thr), 0, c.st, C1.Yt64.as<c64>(),
+                     T.R64.as<c64>(), h.gal_w.as<c64>(), lat.links64.as<c64>(), g, T.a2);
+  KDMG_LAUNCH_CHECK();
+  finish_coarse_level(c, C1);
+}
+
 void galerkin_level1(kdmg_hierarchy& h, const Ctx& c) {
   if (h.lat->nd == 4) {
     galerkin_level1_4d(h, c);
@@ -140,6 +165,10 @@ void galerkin_level1(kdmg_hierarchy& h, const Ctx& c) {
   const long f = 2 * g.half;
   const Fine2<double> F = fine2<double>(lat, h.mass);
   if (!h.gal_w.p) h.gal_w.alloc(sizeof(c64) * f * 2 * nv);
+  if (T.asym) {
+    galerkin_level1_asym(h, c);
+    return;
+  }
   // KD: W = B~^-1 P (at the rescaled mass); on D itself: W = P
   hipLaunchKernelGGL((k_galerkin_w1<double>), dim3(cdiv(g.Nb2, 256), nv, 2), dim3(256), 0, c.st,
                      h.gal_w.as<c64>(), T.P64.as<c64>(), lat.links64.as<c64>(), g, nv, F.me, h.naive ? 1 : 0);
@@ -335,6 +364,37 @@ void build_level1_4d(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int re
   KDMG_HIP(hipStreamSynchronize(c.st));
 }
 
+// P and R of the asymmetric first coarsening from the orthonormalised
+// vectors V (block layout [nv][f]), at the hierarchy's mass.
+void build_asym_transfer(kdmg_hierarchy& h, const Ctx& c, const c64* V) {
+  const kdmg_lattice& lat = *h.lat;
+  Transfer& T = h.T[0];
+  const int ndc = 2 * T.nv, nd = 4 * T.a2.a0 * T.a2.a1, nZ = T.a2.Ncx * T.a2.Nct;
+  const long f = T.nfine;
+  const size_t smem = asym_build_lds(nd, ndc);
+  KDMG_CHECK(smem <= LDS_LIMIT, KDMG_EUNSUPPORTED, "asymmetric coarsening: aggregate too large for LDS");
+  T.asym = true;
+  T.P64.alloc(sizeof(c64) * f * ndc);
+  T.R64.alloc(sizeof(c64) * f * ndc);
+  DevBuf fail(sizeof(int));
+  KDMG_HIP(hipMemsetAsync(fail.p, 0, sizeof(int), c.st));
+  auto fn = k_asym_build<double>;
+  ensure_smem((const void*)fn, smem);
+  int threads = 2 * nd > 256 ? ((2 * nd + 63) / 64) * 64 : 256;
+  if (threads > 1024) threads = 1024;
+  hipLaunchKernelGGL(fn, dim3(nZ), dim3(threads), smem, c.st, T.P64.as<c64>(), T.R64.as<c64>(), V, f,
+                     lat.links64.as<c64>(), lat.g, T.a2, h.mass, fail.as<int>());
+  KDMG_LAUNCH_CHECK();
+  int failed = 0;
+  KDMG_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  KDMG_HIP(hipStreamSynchronize(c.st));
+  KDMG_CHECK(!failed, KDMG_EINVAL, "asymmetric coarsening: zero pivot in the thin LU of an aggregate");
+  T.P16.alloc(sizeof(c16) * f * ndc);
+  T.R16.alloc(sizeof(c16) * f * ndc);
+  convert<_Float16, double>(T.P16.as<c16>(), T.P64.as<c64>(), f * ndc, 1, nullptr, c.st);
+  convert<_Float16, double>(T.R16.as<c16>(), T.R64.as<c64>(), f * ndc, 1, nullptr, c.st);
+}
+
 // fine lattice -> first coarse lattice (2D U(1))
 void build_level1(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int relaxed) {
   const kdmg_lattice& lat = *h.lat;
@@ -388,6 +448,12 @@ void build_level1(kdmg_hierarchy& h, const Ctx& c, const double* psi0, int relax
   T.relaxed.alloc(Vb.bytes);
   KDMG_HIP(hipMemcpyAsync(T.relaxed.p, Vb.p, Vb.bytes, hipMemcpyDeviceToDevice, c.st));
   global_mgs(c, Vb.as<c64>(), f, nv);
+  if (h.params.asymmetric) {
+    build_asym_transfer(h, c, Vb.as<c64>());
+    galerkin_level1(h, c);
+    KDMG_HIP(hipStreamSynchronize(c.st));
+    return;
+  }
   // block QR per (aggregate, chirality)
   const int nZ = T.a2.Ncx * T.a2.Nct, nrows = 2 * a0 * a1;
   std::vector<int> rows((size_t)nZ * 2 * nrows);
@@ -525,6 +591,10 @@ extern "C" kdmg_status kdmg_hierarchy_build(const kdmg_lattice* lat, double mass
   KDMG_CHECK(params->fine_op == 0 || params->fine_op == 1, KDMG_EINVAL, "fine_op must be 0 or 1");
   KDMG_CHECK(lat->nd == 2 || (params->fine_op == 0 && !lat->naik), KDMG_EUNSUPPORTED,
              "fine_op = 1 is built for 2D lattices");
+  KDMG_CHECK(params->asymmetric == 0 || params->asymmetric == 1, KDMG_EINVAL, "asymmetric must be 0 or 1");
+  KDMG_CHECK(!params->asymmetric || (lat->nd == 2 && lat->nc == 1 && !lat->naik && params->fine_op == 0 &&
+                                     params->nlevels == 2),
+             KDMG_EUNSUPPORTED, "asymmetric coarsening: two levels of the 2D KD operator without Naik terms only");
   auto h = std::make_unique<kdmg_hierarchy>();
   h->lat = lat;
   h->mass = mass;
@@ -596,6 +666,8 @@ extern "C" kdmg_status kdmg_hierarchy_at_mass(const kdmg_hierarchy* base, double
   KDMG_CHECK(base && out, KDMG_EINVAL, "kdmg_hierarchy_at_mass: null argument");
   *out = nullptr;
   KDMG_CHECK(mass > 0.0, KDMG_EINVAL, "mass must be positive");
+  KDMG_CHECK(!base->params.asymmetric, KDMG_EUNSUPPORTED,
+             "asymmetric transfers depend on the mass: build a hierarchy at the new mass");
   auto h = std::make_unique<kdmg_hierarchy>();
   h->lat = base->lat;
   h->mass = mass;
@@ -617,6 +689,8 @@ extern "C" kdmg_status kdmg_hierarchy_set_mass(kdmg_hierarchy* h, const kdmg_hie
   KDMG_API_BEGIN
   KDMG_CHECK(h, KDMG_EINVAL, "kdmg_hierarchy_set_mass: null hierarchy");
   KDMG_CHECK(mass > 0.0, KDMG_EINVAL, "mass must be positive");
+  KDMG_CHECK(!h->params.asymmetric && !(base && base->params.asymmetric), KDMG_EUNSUPPORTED,
+             "asymmetric transfers depend on the mass: build a hierarchy at the new mass");
   if (base && base != h) {
     KDMG_CHECK(same_shape(*h, *base), KDMG_EINVAL,
                "kdmg_hierarchy_set_mass: base has a different lattice shape or level structure");
@@ -670,6 +744,7 @@ extern "C" kdmg_status kdmg_hierarchy_get_prolongator(const kdmg_hierarchy* h, i
   KDMG_API_BEGIN
   KDMG_CHECK(h && host_out && k >= 0 && k < h->nlevels - 1, KDMG_EINVAL, "bad level");
   const Transfer& T = h->T[k];
+  KDMG_CHECK(!T.asym, KDMG_EINVAL, "asymmetric hierarchy: use kdmg_hierarchy_get_asym_transfer");
   std::vector<c64> buf(T.P64.bytes / sizeof(c64));
   KDMG_HIP(hipMemcpy(buf.data(), T.P64.p, T.P64.bytes, hipMemcpyDeviceToHost));
   c64* o = reinterpret_cast<c64*>(host_out);
@@ -679,6 +754,27 @@ extern "C" kdmg_status kdmg_hierarchy_get_prolongator(const kdmg_hierarchy* h, i
       for (int i = 0; i < T.nv; ++i) o[x * T.nv + i] = buf[(size_t)lat.h_perm_full[x] * T.nv + i];
   } else {
     std::memcpy(o, buf.data(), T.P64.bytes);
+  }
+  KDMG_API_END
+}
+
+extern "C" kdmg_status kdmg_hierarchy_get_asym_transfer(const kdmg_hierarchy* h, int k, double* p_out,
+                                                        double* r_out) {
+  KDMG_API_BEGIN
+  KDMG_CHECK(h && k == 0 && h->nlevels >= 2 && h->T[0].asym, KDMG_EINVAL,
+             "kdmg_hierarchy_get_asym_transfer: not an asymmetric coarsening");
+  const Transfer& T = h->T[0];
+  const kdmg_lattice& lat = *h->lat;
+  const int ndc = 2 * T.nv;
+  std::vector<c64> buf(T.P64.bytes / sizeof(c64));
+  for (int which = 0; which < 2; ++which) {
+    double* out = which == 0 ? p_out : r_out;
+    if (!out) continue;
+    const DevBuf& src = which == 0 ? T.P64 : T.R64;
+    KDMG_HIP(hipMemcpy(buf.data(), src.p, src.bytes, hipMemcpyDeviceToHost));
+    c64* o = reinterpret_cast<c64*>(out);
+    for (long x = 0; x < lat.ndof; ++x)
+      for (int j = 0; j < ndc; ++j) o[x * ndc + j] = buf[(size_t)lat.h_perm_full[x] * ndc + j];
   }
   KDMG_API_END
 }

@@ -10,11 +10,12 @@
 #include <vector>
 
 #include "common.h"
-#include "blas.cuh"
-#include "fine2d.cuh"
-#include "fine4d.cuh"
-#include "coarse.cuh"
-#include "coarse_fast.cuh"
+#include "blas.h"
+#include "fine2d.h"
+#include "asym2d.h"
+#include "fine4d.h"
+#include "coarse.h"
+#include "coarse_fast.h"
 #include "dense.h"
 
 namespace kdmg {
@@ -35,7 +36,7 @@ struct kdmg_lattice {
   // folded links (1/2 eta bc U), block layout [2][Nb2][8]
   kdmg::DevBuf links64, links16, links32;
   // 4D SU(3): geometry, folded forward links [site][mu][3][3] and neighbour
-  // table [site][8] in block layout (see fine4d.cuh)
+  // table [site][8] in block layout (see fine4d.h)
   kdmg::Geo4 g4{};
   kdmg::DevBuf lk64, lk32, lk16, nb4;
   // folded links in natural order, per direction [mu][site]
@@ -356,9 +357,13 @@ struct Transfer {
   DevBuf neven4;                 // rows of each group with dof < half (a prefix of rows4)
   DevBuf relaxed;                // relaxed null vectors, FP64, internal layout [nv][n_k]
   long nfine = 0;                // entries per null vector (internal layout)
+  // k == 0, 2D, asymmetric coarsening: P64/P16 hold [fine dof][2 nv] and
+  // R64/R16 the restriction transposed, [fine dof][2 nv] (asym2d.h)
+  bool asym = false;
+  DevBuf R64, R16;
   size_t bytes() const {
     return P64.bytes + P16.bytes + children.bytes + parent.bytes + gdir.bytes + relaxed.bytes + rows4.bytes +
-           neven4.bytes + dgrp4.bytes;
+           neven4.bytes + dgrp4.bytes + R64.bytes + R16.bytes;
   }
 };
 
@@ -595,7 +600,18 @@ void transfer_restrict(const Transfer& T, const kdmg_lattice& lat, const CoarseL
                        Cx<VO>* out, const Cx<VI>* in, long si, int even_only, const int* act,
                        int nrhs, hipStream_t st) {
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
-  if (T.k == 0 && lat.nd == 4) {
+  if (T.k == 0 && T.asym) {
+    const Cx<PT>* Rt = (const Cx<PT>*)(sizeof(PT) == 8 ? T.R64.p : T.R16.p);
+    const int nd = 4 * T.a2.a0 * T.a2.a1, ndc = 2 * T.nv;
+    int RB = nrhs < 32 ? nrhs : 32;
+    auto bytes = [&] { return ((size_t)nd * ndc + (size_t)RB * nd) * sizeof(Cx<R>) + nd * sizeof(int); };
+    while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
+    KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "restriction: aggregate too large for LDS staging");
+    auto fn = k_restrict1a<R, PT, VI, VO>;
+    ensure_smem((const void*)fn, bytes());
+    hipLaunchKernelGGL(fn, dim3(T.a2.Ncx * T.a2.Nct, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, in, si, Rt,
+                       lat.g, T.a2, even_only, act, nrhs, RB);
+  } else if (T.k == 0 && lat.nd == 4) {
     dim3 grid(2 * T.nZ, cdiv(T.nv, R4_RI), cdiv(nrhs, R4_RR));
     hipLaunchKernelGGL((k4_restrict<R, PT, VI, VO>), grid, dim3(256), 0, st, out, in, si, P, T.rows4.as<int>(),
                        T.neven4.as<int>(), T.nrows4, T.nv, even_only, act, nrhs);
@@ -634,7 +650,17 @@ void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, l
                       const Cx<VO>* add, long sa, const Cx<VI>* in, int npar, const int* act,
                       int nrhs, hipStream_t st) {
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
-  if (T.k == 0 && lat.nd == 4) {
+  if (T.k == 0 && T.asym) {
+    const int nd = 4 * T.a2.a0 * T.a2.a1, ndc = 2 * T.nv;
+    int RB = nrhs < 32 ? nrhs : 32;
+    auto bytes = [&] { return ((size_t)nd * (ndc + 1) + (size_t)RB * ndc) * sizeof(Cx<R>) + nd * sizeof(int); };
+    while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
+    KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "prolongation: aggregate too large for LDS staging");
+    auto fn = k_prolong1a<R, PT, VI, VO>;
+    ensure_smem((const void*)fn, bytes());
+    hipLaunchKernelGGL(fn, dim3(T.a2.Ncx * T.a2.Nct, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, so, add, sa, in,
+                       P, lat.g, T.a2, npar, act, nrhs, RB);
+  } else if (T.k == 0 && lat.nd == 4) {
     const long n_out = npar == 1 ? lat.half : 2 * lat.half;
     constexpr int BS = sizeof(R) == 8 ? 128 : 256;
     const size_t bytes = (size_t)BS * (T.nv | 1) * sizeof(Cx<R>);

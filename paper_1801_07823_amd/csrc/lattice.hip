@@ -554,4 +554,5 @@ extern "C" void kdmg_default_params(kdmg_mg_params* p) {
   p->coarse_tail = 16;
   p->coarse_solver = 0;
   p->fine_op = 0;
+  p->asymmetric = 0;
 }

@@ -1,7 +1,7 @@
 // Setup kernels of the 4D SU(3) fine level: dense Kahler-Dirac block
 // inverses, block orthonormalisation (Cholesky-QR) and the level-1 Galerkin
-// product (layouts and formulas in fine4d.cuh).
-#include "fine4d.cuh"
+// product (layouts and formulas in fine4d.h).
+#include "fine4d.h"
 
 namespace kdmg {
 

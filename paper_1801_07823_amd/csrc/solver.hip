@@ -184,7 +184,7 @@ struct OpResidNorm {  // ||r||^2 -> out[r]
 };
 
 // Fused CGNE on the coarsest level: two kernels per iteration (see
-// coarse_fast.cuh), host reads the active flags every `poll` iterations.
+// coarse_fast.h), host reads the active flags every `poll` iterations.
 // Capture `n` CGNE iterations on the (idle-by-construction) capture of c.st.
 bool capture_chunk(ChunkGraph& G, const TileShape& sh, const CoarseLevel& L, c64* x, c64* r, c64* p,
                    const CgneState& s, int nrhs, int n) {

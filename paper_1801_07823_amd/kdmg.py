@@ -36,7 +36,8 @@ class kdmg_mg_params(ctypes.Structure):
                 ("inter_restart", ctypes.c_int), ("inter_maxit", ctypes.c_int),
                 ("inter_tol", ctypes.c_double), ("coarse_tol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int), ("outer_stall", ctypes.c_int),
-                ("coarse_tail", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("fine_op", ctypes.c_int)]
+                ("coarse_tail", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("fine_op", ctypes.c_int),
+                ("asymmetric", ctypes.c_int)]
 
 
 class kdmg_solve_info(ctypes.Structure):
@@ -74,6 +75,7 @@ _SIGS = {
     "kdmg_hierarchy_level_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "kdmg_hierarchy_get_nullvecs": (_I, [_P, _I, _P]),
     "kdmg_hierarchy_get_prolongator": (_I, [_P, _I, _P]),
+    "kdmg_hierarchy_get_asym_transfer": (_I, [_P, _I, _P, _P]),
     "kdmg_hierarchy_get_coarse_op": (_I, [_P, _I, _P]),
     "kdmg_coarse_apply": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
     "kdmg_restrict": (_I, [_P, _I, _P, _P, _I, _I, _P]),
@@ -302,6 +304,14 @@ class Hierarchy:
         out = np.zeros((self.ndof(k), nv), dtype=np.complex128)
         _check(_lib.kdmg_hierarchy_get_prolongator(self.handle, k, out.ctypes.data_as(_P)))
         return out
+
+    def asym_transfer(self, k=0):
+        """Asymmetric coarsening: (P, R^T) on the aggregates, each [ndof_0][2 nvec]."""
+        nd = 2 * self.params.lvl[k].nvec
+        p = np.zeros((self.ndof(k), nd), dtype=np.complex128)
+        r = np.zeros((self.ndof(k), nd), dtype=np.complex128)
+        _check(_lib.kdmg_hierarchy_get_asym_transfer(self.handle, k, p.ctypes.data_as(_P), r.ctypes.data_as(_P)))
+        return p, r
 
     def coarse_op(self, level):
         dims, nd = self.level_info(level)

@@ -47,4 +47,20 @@ def test_binding_loads_and_matches_header():
     assert p.outer_stall == 0  # the serving stall rule is off unless asked for
     assert p.coarse_tail == 16
     assert p.coarse_solver == 0  # Table 1: CGNE on the coarsest level
+    assert p.fine_op == 0 and p.asymmetric == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_params_layout_reaches_the_last_field():
+    """The library's kdmg_default_params writes every field of the binding's
+    struct, up to the last one: filled with a byte pattern first, no field
+    keeps it."""
+    import ctypes
+    from paper_1801_07823_amd import kdmg
+    p = kdmg.kdmg_mg_params()
+    ctypes.memset(ctypes.byref(p), 0x55, ctypes.sizeof(p))
+    kdmg._lib.kdmg_default_params(ctypes.byref(p))
+    assert p.coarse_tail == 16 and p.coarse_solver == 0 and p.fine_op == 0 and p.asymmetric == 0
+    last = kdmg.kdmg_mg_params._fields_[-1][0]
+    assert last == "asymmetric"
     assert kdmg._lib.kdmg_status_string(kdmg.KDMG_ENOCONV) == b"solver did not converge"
