@@ -598,6 +598,8 @@ def main():
                     help="timed steps of the Naik-operator KD-MG solve (0: skip)")
     ap.add_argument("--negative-control", type=int, default=1,
                     help="1: report the stalled Galerkin MG on D itself beside the headline")
+    ap.add_argument("--asym-steps", type=int, default=1,
+                    help="timed steps of the two-level symmetric / asymmetric coarsening leg (0: skip)")
     ap.add_argument("--cgne-steps", type=int, default=2,
                     help="timed steps of the Table 1 CGNE-coarsest variant (0: skip)")
     ap.add_argument("--kernel-profile", action="store_true",
@@ -765,6 +767,46 @@ def main():
         print("naik: %.1f solves/s" % naik["value"], file=sys.stderr, flush=True)
         del hn, xn, latn
 
+    # asymmetric first coarsening (Sec. 5, App. A) against the symmetric one:
+    # two levels (4x4 aggregates, the same n_vec and starts), the coarsest
+    # level -- 32^2 sites x 32 dofs -- solved by Table 1's CGNE (cap as the
+    # CGNE leg), mixed, the same 32 rhs, outer FGCR capped at 40 (the
+    # symmetric form needs about 20).  One untimed solve; the timed steps
+    # only follow where it converged.
+    asym = None
+    if a.asym_steps > 0:
+        asym = {}
+        for name, flag in (("symmetric", 0), ("asymmetric", 1)):
+            pa = kdmg.make_params([((4, 4), NV)], coarse_maxit=COARSE_MAXIT, coarse_solver=0, outer_maxit=40,
+                                  asymmetric=flag)
+            t0 = time.perf_counter()
+            ha = kdmg.Hierarchy(lat, MASS, pa, psi0[:1])
+            torch.cuda.synchronize()
+            setup_a = time.perf_counter() - t0
+            xa = torch.empty_like(b)
+            infa, _ = kdmg.kdmg_solve(ha, b, xa, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)
+            conv = all(i["converged"] for i in infa)
+            rate = None
+            if conv:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for i in range(a.asym_steps):
+                    infa, _ = kdmg.kdmg_solve(ha, b, xa, NRHS, 1e-10, prec=kdmg.KDMG_MIXED, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                rate = NRHS * a.asym_steps / (time.perf_counter() - t0)
+            asym[name] = {"value": rate, "unit": "solves/s", "setup_s": setup_a,
+                          "outer": [i["outer_its"] for i in infa],
+                          "level2_avg": [round(i["level_avg_its"][0], 1) for i in infa],
+                          "max_true_rel_resid": max(i["true_rel_resid"] for i in infa),
+                          "converged": all(i["converged"] for i in infa)}
+            print("%s two-level: %s solves/s, outer %d, residual %.2e" % (
+                name, "%.1f" % rate if rate else "-", max(asym[name]["outer"]), asym[name]["max_true_rel_resid"]),
+                file=sys.stderr, flush=True)
+            del ha, xa
+        asym["hierarchy"] = ("two levels: 4x4 aggregates n_vec %d, coarsest CGNE tol 0.2 at most %d iterations, "
+                             "outer FGCR at most 40" % (NV, COARSE_MAXIT))
+        asym["steps"] = a.asym_steps
+
     # negative control (Sec. 3.2): the same K-cycle coarsening D itself instead
     # of A = D B^-1, from the same starts, capped at 30 outer iterations
     negative = None
@@ -888,6 +930,7 @@ def main():
         "cgne_coarsest": cgne,
         "naik": naik,
         "negative_control": negative,
+        "asymmetric_coarsening": asym,
         "cg_eo": cg_eo,
         "dslash": dslash,
         "roofline": roofline,

@@ -131,7 +131,10 @@ typedef struct {
                                  hierarchy cannot change its mass
                                  (kdmg_hierarchy_at_mass / _set_mass return
                                  KDMG_EUNSUPPORTED).  A zero pivot makes the
-                                 build fail with KDMG_EINVAL. */
+                                 build fail with KDMG_EINVAL.  The mixed
+                                 V-cycle keeps P and R in FP32 here (not
+                                 FP16): when R~ P~ is ill-conditioned the
+                                 entries of P leave the FP16 range. */
 } kdmg_mg_params;
 
 /* Per right-hand side result of kdmg_solve. */

@@ -389,10 +389,10 @@ void build_asym_transfer(kdmg_hierarchy& h, const Ctx& c, const c64* V) {
   KDMG_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int), hipMemcpyDeviceToHost, c.st));
   KDMG_HIP(hipStreamSynchronize(c.st));
   KDMG_CHECK(!failed, KDMG_EINVAL, "asymmetric coarsening: zero pivot in the thin LU of an aggregate");
-  T.P16.alloc(sizeof(c16) * f * ndc);
-  T.R16.alloc(sizeof(c16) * f * ndc);
-  convert<_Float16, double>(T.P16.as<c16>(), T.P64.as<c64>(), f * ndc, 1, nullptr, c.st);
-  convert<_Float16, double>(T.R16.as<c16>(), T.R64.as<c64>(), f * ndc, 1, nullptr, c.st);
+  T.P32.alloc(sizeof(c32) * f * ndc);
+  T.R32.alloc(sizeof(c32) * f * ndc);
+  convert<float, double>(T.P32.as<c32>(), T.P64.as<c64>(), f * ndc, 1, nullptr, c.st);
+  convert<float, double>(T.R32.as<c32>(), T.R64.as<c64>(), f * ndc, 1, nullptr, c.st);
 }
 
 // fine lattice -> first coarse lattice (2D U(1))

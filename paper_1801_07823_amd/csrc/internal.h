@@ -357,13 +357,15 @@ struct Transfer {
   DevBuf neven4;                 // rows of each group with dof < half (a prefix of rows4)
   DevBuf relaxed;                // relaxed null vectors, FP64, internal layout [nv][n_k]
   long nfine = 0;                // entries per null vector (internal layout)
-  // k == 0, 2D, asymmetric coarsening: P64/P16 hold [fine dof][2 nv] and
-  // R64/R16 the restriction transposed, [fine dof][2 nv] (asym2d.h)
+  // k == 0, 2D, asymmetric coarsening: P64 holds [fine dof][2 nv] and R64
+  // the restriction transposed, [fine dof][2 nv] (asym2d.h); the mixed
+  // V-cycle reads the FP32 copies P32/R32 (the thin LU can make P's entries
+  // exceed the FP16 range when R~ P~ is ill-conditioned)
   bool asym = false;
-  DevBuf R64, R16;
+  DevBuf R64, P32, R32;
   size_t bytes() const {
     return P64.bytes + P16.bytes + children.bytes + parent.bytes + gdir.bytes + relaxed.bytes + rows4.bytes +
-           neven4.bytes + dgrp4.bytes + R64.bytes + R16.bytes;
+           neven4.bytes + dgrp4.bytes + R64.bytes + P32.bytes + R32.bytes;
   }
 };
 
@@ -601,13 +603,15 @@ void transfer_restrict(const Transfer& T, const kdmg_lattice& lat, const CoarseL
                        int nrhs, hipStream_t st) {
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
   if (T.k == 0 && T.asym) {
-    const Cx<PT>* Rt = (const Cx<PT>*)(sizeof(PT) == 8 ? T.R64.p : T.R16.p);
+    // FP64 values, or the FP32 copy where the symmetric form reads FP16
+    using PA = std::conditional_t<sizeof(PT) == 8, double, float>;
+    const Cx<PA>* Rt = (const Cx<PA>*)(sizeof(PT) == 8 ? T.R64.p : T.R32.p);
     const int nd = 4 * T.a2.a0 * T.a2.a1, ndc = 2 * T.nv;
     int RB = nrhs < 32 ? nrhs : 32;
     auto bytes = [&] { return ((size_t)nd * ndc + (size_t)RB * nd) * sizeof(Cx<R>) + nd * sizeof(int); };
     while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
     KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "restriction: aggregate too large for LDS staging");
-    auto fn = k_restrict1a<R, PT, VI, VO>;
+    auto fn = k_restrict1a<R, PA, VI, VO>;
     ensure_smem((const void*)fn, bytes());
     hipLaunchKernelGGL(fn, dim3(T.a2.Ncx * T.a2.Nct, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, in, si, Rt,
                        lat.g, T.a2, even_only, act, nrhs, RB);
@@ -651,15 +655,17 @@ void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, l
                       int nrhs, hipStream_t st) {
   const Cx<PT>* P = (const Cx<PT>*)(sizeof(PT) == 8 ? T.P64.p : T.P16.p);
   if (T.k == 0 && T.asym) {
+    using PA = std::conditional_t<sizeof(PT) == 8, double, float>;
+    const Cx<PA>* Pa = (const Cx<PA>*)(sizeof(PT) == 8 ? T.P64.p : T.P32.p);
     const int nd = 4 * T.a2.a0 * T.a2.a1, ndc = 2 * T.nv;
     int RB = nrhs < 32 ? nrhs : 32;
     auto bytes = [&] { return ((size_t)nd * (ndc + 1) + (size_t)RB * ndc) * sizeof(Cx<R>) + nd * sizeof(int); };
     while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
     KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "prolongation: aggregate too large for LDS staging");
-    auto fn = k_prolong1a<R, PT, VI, VO>;
+    auto fn = k_prolong1a<R, PA, VI, VO>;
     ensure_smem((const void*)fn, bytes());
     hipLaunchKernelGGL(fn, dim3(T.a2.Ncx * T.a2.Nct, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, so, add, sa, in,
-                       P, lat.g, T.a2, npar, act, nrhs, RB);
+                       Pa, lat.g, T.a2, npar, act, nrhs, RB);
   } else if (T.k == 0 && lat.nd == 4) {
     const long n_out = npar == 1 ? lat.half : 2 * lat.half;
     constexpr int BS = sizeof(R) == 8 ? 128 : 256;

@@ -3,8 +3,8 @@ thinlu; App. A) against the oracle's asymmetric_transfer, on identical
 relaxed null vectors:
   * P and R (through R^T) to 1e-11 relative max-norm, and R P = 1;
   * the Galerkin operator R A P to 1e-11;
-  * restriction and prolongation, FP64 to 1e-12, mixed (FP16-stored P and
-    R, FP32 vectors) element-wise within the FP16 bound of mixed_bounds.py;
+  * restriction and prolongation, FP64 to 1e-12, mixed (FP32-stored P and
+    R, FP32 vectors) element-wise within the FP32 bound of mixed_bounds.py;
   * two-level solves in FP64 and mixed, with the CGNE and the exact coarsest
     solve: true residual <= 1e-10, x within 1e-8 of dense LU, and the outer
     count within one of the oracle's asymmetric solve;
@@ -17,7 +17,7 @@ from oracle.staggered import Lattice as OLattice, dirac_matrix
 from oracle.mg import MGParams, LevelParams, Hierarchy as OHierarchy, Solver as OSolver
 from oracle.exact import dense_solve
 from synth import u1_heatbath, gaussian_vectors
-from mixed_bounds import fp16_coef, abs_terms, rounded, check_elementwise
+from mixed_bounds import fp32_coef, abs_terms, rounded, check_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -141,7 +141,7 @@ def test_restrict_prolong(K, case):
         torch.cuda.synchronize()
         v32 = rounded(v)
         nt = int(np.diff(R.tocsr().indptr).max())
-        check_elementwise(out32.cpu().numpy(), (R @ v32.T).T, abs_terms(R, v32), fp16_coef(nt),
+        check_elementwise(out32.cpu().numpy(), (R @ v32.T).T, abs_terms(R, v32), fp32_coef(nt),
                           "asymmetric restrict mixed nrhs=%d" % nr)
         e = gaussian_vectors(nr, nc, 70 + nr)
         outp = torch.empty((nr, nf), dtype=torch.complex128, device="cuda")
@@ -153,7 +153,7 @@ def test_restrict_prolong(K, case):
         torch.cuda.synchronize()
         e32 = rounded(e)
         nt = int(np.diff(P.tocsr().indptr).max())
-        check_elementwise(outp32.cpu().numpy(), (P @ e32.T).T, abs_terms(P, e32), fp16_coef(nt),
+        check_elementwise(outp32.cpu().numpy(), (P @ e32.T).T, abs_terms(P, e32), fp32_coef(nt),
                           "asymmetric prolong mixed nrhs=%d" % nr)
 
 

@@ -114,3 +114,22 @@ def test_asymmetric_solve(field):
     assert info["converged"] and info["outer_its"] <= 30, info
     xd = dense_solve(h.lat, field, 0.05, b)
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-8
+
+
+def test_asymmetric_coarse_operator_conditioning():
+    """App. A finds the asymmetric form less stable in two dimensions.  On a
+    smooth 32^2 field (beta = 10, m = 0.001, 4x4 aggregates, n_vec 16) its
+    coarse operator is about a hundred times worse conditioned than the
+    symmetric one (measured 3.7e4 against 390), which is what defeats the
+    coarsest CGNE(0.2) there."""
+    from synth import config_seed
+    seed = config_seed(32, 10.0, 0)
+    U, _ = u1_heatbath((32, 32), 10.0, 200, seed)
+    lat = Lattice((32, 32))
+    psi0 = [gaussian_vectors(16, lat.volume, seed, tag=1)]
+    conds = []
+    for asym in (False, True):
+        h = Hierarchy(lat, U, 0.001, MGParams(levels=[LevelParams((4, 4), 16)], asymmetric=asym), psi0)
+        s = np.linalg.svd(h.ops[1].toarray(), compute_uv=False)
+        conds.append(s[0] / s[-1])
+    assert conds[1] > 30 * conds[0], conds
