@@ -315,13 +315,14 @@ kdmg_status kdmg_coarsest_solve(kdmg_hierarchy* h, const void* in, void* out, in
    i.e. ||r_e|| <= tol m ||b|| for the true even residual r_e.  CG stops a
    rhs on its recursive residual; the true one is then recomputed, and rhs
    still above the target run further CG passes on the residual system
-   (at most 8 passes and maxit iterations in all).  2D lattices with even
-   extents; FP64.  b, x:
-   complex128 device vectors [nrhs][volume] in natural site order (x is
-   overwritten).  its_host: nrhs iteration counts (may be NULL).  Allocates
+   (at most 8 passes and maxit iterations in all).  FP64.  b, x: complex128
+   device vectors [nrhs][ndof] in natural site order, colours innermost (x
+   is overwritten).  its_host: nrhs iteration counts (may be NULL).  Allocates
    its work space per call and synchronises `stream`.  Returns KDMG_ENOCONV
    (x and its_host still written) if a rhs missed tol within maxit;
-   KDMG_EUNSUPPORTED for a 4D lattice, KDMG_EINVAL for bad arguments. */
+   KDMG_EUNSUPPORTED for lattices other than 2D U(1) and 4D SU(3) (every
+   extent even), KDMG_EINVAL for bad arguments.  The 4D call allocates a
+   natural-order copy of the links (4 * 9 * 16 V bytes) for its duration. */
 kdmg_status kdmg_solve_cg_eo(const kdmg_lattice* lat, double mass, const void* b, void* x, int nrhs,
                              double tol, int maxit, int* its_host, void* stream);
 
