@@ -72,7 +72,7 @@ struct CtxAlloc {
     partials.alloc(sizeof(double) * (size_t)slots * 3 * RED_MAX_BLOCKS);
     {
       std::lock_guard<std::mutex> g(hip_mem_mutex());
-      KDMG_HIP(hipHostMalloc((void**)&h_poll, sizeof(int) * (nrhs_max + 8), hipHostMallocDefault));
+      KDMG_HIP(hipHostMalloc((void**)&h_poll, sizeof(int) * (2 * nrhs_max + 8), hipHostMallocDefault));
     }
     c.st = st;
     c.rs.partials = partials.as<double>();
@@ -130,17 +130,37 @@ void mr_smooth(const Ctx& c, int nrhs, long n, Cx<T>* x, Cx<T>* r, Cx<T>* q, int
 // step, with a third of the vector traffic.
 // Stops a rhs when ||r||^2 <= tol^2 * (ext ? ext[r] : ||b||^2), and with
 // stall > 0 also when ||r|| has not halved over the last `stall` iterations.
+// poll_from > 0: the host reads the active flags only from iteration
+// poll_from on (and at restarts), so the first poll_from iterations run
+// without a host round trip; iterations after every rhs has converged are
+// no-ops on the device (every kernel skips inactive rhs, and the cycle's
+// x update uses each rhs' own column count), so the result is the same as
+// with a poll after every iteration.  *max_its_out then receives the largest
+// per-rhs iteration count of the call (the count a poll after every
+// iteration would have stopped at).
 template <class T, class OpF, class PrecF>
 int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* Zb,
               Cx<T>* Wb, int restart, int maxit, double tol, const double* ext,
               const KrylovState& k, const int* parent, OpF op, PrecF prec, bool trace = false,
-              int stall = 0) {
+              int stall = 0, int poll_from = 0, int* max_its_out = nullptr) {
   start_solve(c, k, parent, nrhs);
   launch_map_reduce<1>(OpInit<T>{x, r, nullptr, b, n, k, tol * tol, ext}, n, nrhs, 1, c.rs, c.st);
   const long vs = (long)nrhs * n;
   KDMG_CHECK(k.R >= restart && k.rec, KDMG_EINVAL, "GCR: cycle record too small");
   int its = 0;
-  if (!any_active(c, k.act, nrhs)) return 0;
+  // polls the active flags (and, in deferred-poll mode, the iteration counts)
+  auto poll = [&]() {
+    if (poll_from > 0 && max_its_out)
+      KDMG_HIP(hipMemcpyAsync(c.h_poll + nrhs, k.its, sizeof(int) * nrhs, hipMemcpyDeviceToHost, c.st));
+    const bool any = any_active(c, k.act, nrhs);
+    if (poll_from > 0 && max_its_out) {
+      int mx = 0;
+      for (int i = 0; i < nrhs; ++i) mx = std::max(mx, c.h_poll[nrhs + i]);
+      *max_its_out = mx;
+    }
+    return any;
+  };
+  if (poll_from == 0 && !poll()) return 0;
   int ncol = 0;  // columns of the current cycle
   auto end_cycle = [&]() {
     if (ncol == 0) return;
@@ -167,7 +187,7 @@ int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r
       ncol = kk + 1;
       ++its;
       if (trace) trace_residuals(c, k, nrhs, its, tol);
-      if (!any_active(c, k.act, nrhs)) {
+      if (its >= poll_from && !poll()) {
         end_cycle();
         return its;
       }
@@ -176,8 +196,9 @@ int gcr_solve(const Ctx& c, int nrhs, long n, const Cx<T>* b, Cx<T>* x, Cx<T>* r
     if (its >= maxit) break;
     op(r, x, b, k.act);  // r = b - op x (true residual at restart)
     launch_map_reduce<1>(OpResNorm<T>{r, n, k}, n, nrhs, 1, c.rs, c.st);
-    if (!any_active(c, k.act, nrhs)) break;
+    if (!poll()) break;
   }
+  if (poll_from > 0 && max_its_out) (void)poll();
   return its;
 }
 

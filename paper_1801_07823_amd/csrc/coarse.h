@@ -14,6 +14,7 @@
 #pragma once
 #include "common.h"
 #include "blas.h"
+#include "fine2d.h"
 
 namespace kdmg {
 
@@ -73,52 +74,83 @@ __global__ void k_dagger_build(Cx<T>* Yd, const Cx<T>* Yt, const int* nbr, int n
 
 // Restriction between coarse levels:
 // out[r][Z][c*nv + j] = sum_{X in Z} sum_{i<nvp} conj(Pst[X][c*nvp+i][j]) in[r][X][c*nvp+i]
-// Block: ndn * parts threads, grid (nZ, nrhs).  children[Z][nchild].
+// One workgroup per (aggregate Z, tile of RB rhs): the aggregate's P rows
+// (nchild * ndf of them) and the tile's input values are staged in LDS, so P
+// is read once per tile and the inputs with coalesced loads; thread o then
+// forms outputs (rhs o / ndn, coarse dof o % ndn).  grid (nZ, cdiv(nrhs, RB));
+// LDS (nchild ndf nv + RB nchild ndf) Cx<R>.  children[Z][nchild].
 template <class R, class PT, class VI, class VO>
 __global__ __launch_bounds__(256) void k_restrict_c(Cx<VO>* out, const Cx<VI>* in, const Cx<PT>* Pst,
                                                     const int* children, int nchild, int nsf,
-                                                    int ndf, int nZ, int nv, const int* act) {
-  const int Z = blockIdx.x, r = blockIdx.y;
-  if (!is_active(act, r)) return;
-  const int ndn = 2 * nv, nvp = ndf / 2;
-  const int col = threadIdx.x % ndn, part = threadIdx.x / ndn, nparts = blockDim.x / ndn;
-  const int c = col / nv, j = col % nv;
-  Cx<R> acc{0, 0};
-  const int nterm = nchild * nvp;
-  for (int f = part; f < nterm; f += nparts) {
-    const int ch = f / nvp, i = f % nvp;
-    const long X = children[(long)Z * nchild + ch];
-    const int a = c * nvp + i;
-    cfma_conj(acc, ld<R>(Pst[(X * ndf + a) * nv + j]), ld<R>(in[((long)r * nsf + X) * ndf + a]));
-  }
-  __shared__ Cx<R> sh[256];
-  sh[threadIdx.x] = acc;
+                                                    int ndf, int nZ, int nv, const int* act, int nrhs, int RB) {
+  extern __shared__ __align__(16) unsigned char xc_raw[];
+  const int Z = blockIdx.x, r0 = blockIdx.y * RB;
+  const int ndn = 2 * nv, nvp = ndf / 2, nrow = nchild * ndf;
+  Cx<R>* Ps = reinterpret_cast<Cx<R>*>(xc_raw);  // [nrow][nv]
+  Cx<R>* Vs = Ps + (long)nrow * nv;              // [RB][nrow]
+  const int* kids = children + (long)Z * nchild;
+  stage_rows<R, 4>(Ps, nv, nrow, nv, [&](int q, int j) {
+    const int ch = q / ndf, a = q - ch * ndf;
+    return ld<R>(Pst[((long)kids[ch] * ndf + a) * nv + j]);
+  });
+  stage_rows<R, 4>(Vs, nrow, RB, nrow, [&](int t, int q) {
+    const int ch = q / ndf, a = q - ch * ndf, r = r0 + t;
+    return r < nrhs && is_active(act, r) ? ld<R>(in[((long)r * nsf + kids[ch]) * ndf + a]) : Cx<R>{0, 0};
+  });
   __syncthreads();
-  if (part != 0) return;
-  for (int q = 1; q < nparts; ++q) acc += sh[q * ndn + col];
-  out[((long)r * nZ + Z) * ndn + col] = st<VO>(acc);
+  for (int o = threadIdx.x; o < RB * ndn; o += blockDim.x) {
+    const int t = o / ndn, col = o - t * ndn, r = r0 + t;
+    if (r >= nrhs || !is_active(act, r)) continue;
+    const int c = col / nv, j = col - c * nv;
+    const Cx<R>* v = Vs + (long)t * nrow;
+    Cx<R> acc{0, 0};
+    for (int ch = 0; ch < nchild; ++ch)
+      for (int i = 0; i < nvp; ++i) {
+        const int q = ch * ndf + c * nvp + i;
+        cfma_conj(acc, Ps[q * nv + j], v[q]);
+      }
+    out[((long)r * nZ + Z) * ndn + col] = st<VO>(acc);
+  }
 }
 
 // Prolongation between coarse levels:
 // out[r][X][a] = [add +] sum_j Pst[X][a][j] in[r][parent(X)][c(a)*nv + j]
+// One workgroup per (aggregate Z, tile of RB rhs), P rows (padded to nv + 1
+// against bank conflicts) and the tile's coarse values staged in LDS; thread
+// o forms outputs (rhs o / nrow, row o % nrow of the aggregate).
+// grid (nZ, cdiv(nrhs, RB)); LDS (nchild ndf (nv + 1) + RB ndn) Cx<R>.
 template <class R, class PT, class VI, class VO>
 __global__ __launch_bounds__(256) void k_prolong_c(Cx<VO>* out, const Cx<VO>* add, const Cx<VI>* in,
-                                                   const Cx<PT>* Pst, const int* parent, int nsf,
-                                                   int ndf, int nZ, int nv, const int* act) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (e >= (long)nsf * ndf || !is_active(act, r)) return;
-  const long X = e / ndf;
-  const int a = (int)(e % ndf);
-  const int c = a / (ndf / 2);
-  const int ndn = 2 * nv;
-  const Cx<VI>* ec = in + ((long)r * nZ + parent[X]) * ndn + c * nv;
-  const Cx<PT>* Px = Pst + e * nv;
-  Cx<R> acc{0, 0};
-  for (int j = 0; j < nv; ++j) cfma(acc, ld<R>(Px[j]), ld<R>(ec[j]));
-  const long o = (long)r * nsf * ndf + e;
-  if (add) acc += ld<R>(add[o]);
-  out[o] = st<VO>(acc);
+                                                   const Cx<PT>* Pst, const int* children, int nchild, int nsf,
+                                                   int ndf, int nZ, int nv, const int* act, int nrhs, int RB) {
+  extern __shared__ __align__(16) unsigned char xc_raw[];
+  const int Z = blockIdx.x, r0 = blockIdx.y * RB;
+  const int ndn = 2 * nv, nvp = ndf / 2, nrow = nchild * ndf, RP = nv + 1;
+  Cx<R>* Ps = reinterpret_cast<Cx<R>*>(xc_raw);  // [nrow][nv + 1]
+  Cx<R>* Es = Ps + (long)nrow * RP;              // [RB][ndn]
+  const int* kids = children + (long)Z * nchild;
+  stage_rows<R, 4>(Ps, RP, nrow, nv, [&](int q, int j) {
+    const int ch = q / ndf, a = q - ch * ndf;
+    return ld<R>(Pst[((long)kids[ch] * ndf + a) * nv + j]);
+  });
+  stage_rows<R, 4>(Es, ndn, RB, ndn, [&](int t, int j) {
+    const int r = r0 + t;
+    return r < nrhs ? ld<R>(in[((long)r * nZ + Z) * ndn + j]) : Cx<R>{0, 0};
+  });
+  __syncthreads();
+  for (int o = threadIdx.x; o < RB * nrow; o += blockDim.x) {
+    const int t = o / nrow, q = o - t * nrow, r = r0 + t;
+    if (r >= nrhs || !is_active(act, r)) continue;
+    const int ch = q / ndf, a = q - ch * ndf, c = a / nvp;
+    const long X = children[(long)Z * nchild + ch];
+    const Cx<R>* pq = Ps + q * RP;
+    const Cx<R>* er = Es + t * ndn + c * nv;
+    Cx<R> acc{0, 0};
+    for (int j = 0; j < nv; ++j) cfma(acc, pq[j], er[j]);
+    const long ob = ((long)r * nsf + X) * ndf + a;
+    if (add) acc += ld<R>(add[ob]);
+    out[ob] = st<VO>(acc);
+  }
 }
 
 // Galerkin triple product between coarse levels (FP64):

@@ -494,6 +494,11 @@ __global__ __launch_bounds__(1024) void k_capply_fast(Cx<VO>* __restrict__ out, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>));
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT;
+  if (act) {  // a tile of converged rhs has nothing to write
+    int mine = 0;
+    for (int t = threadIdx.x; t < ta.RT && r0 + t < nrhs; t += blockDim.x) mine |= act[r0 + t];
+    if (!__syncthreads_or(mine)) return;
+  }
   const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
   stage_all<R, OT, VI>(CORE == 1 && YL == 1 ? reinterpret_cast<Cx<R>*>(smem_raw + L.ys) : nullptr,
                        reinterpret_cast<Cx<R>*>(smem_raw + L.vs), Yt, in, nb, X, nsites, ndc, ndir, r0, ta.RT,

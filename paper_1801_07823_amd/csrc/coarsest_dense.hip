@@ -193,19 +193,26 @@ __global__ __launch_bounds__(256) void k_dn_adj(c64* X, const c64* Ninv, const c
 // chunk is contracted, so their latency overlaps the MFMAs.  Wave w contracts
 // rows 16w..16w+15 against NT 16-rhs tiles with v_mfma_f64_16x16x4 (Gauss:
 // three real products per complex one).  Loads past the end of a split read a
-// clamped address and are replaced by zero.
+// clamped address and are replaced by zero.  With `act`, a workgroup whose
+// rhs tile holds no active rhs returns at once (its partial sums are never
+// read: k_dn_reduce skips inactive rhs).
 template <int NT>
 __global__ __launch_bounds__(256) void k_dn_apply(c64* part, const c64* __restrict__ X, const c64* __restrict__ b,
-                                                  long n, int nrhs, long kc) {
+                                                  long n, int nrhs, long kc, const int* act) {
   constexpr int RW = 16 * NT;
   __shared__ c64 Xs[64][33];
   __shared__ c64 Bs[RW][33];
   using M = Mfma<double>;
   typedef M::v4 v4;
+  const int rb = blockIdx.z * RW;
+  if (act) {
+    int mine = 0;
+    for (int t = threadIdx.x; t < RW && rb + t < nrhs; t += blockDim.x) mine |= act[rb + t];
+    if (!__syncthreads_or(mine)) return;
+  }
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
   const long row0 = (long)blockIdx.x * 64;
   const long k0 = (long)blockIdx.y * kc, k1 = min(n, k0 + kc);
-  const int rb = blockIdx.z * RW;
   v4 p1[NT], p2[NT], p3[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -279,9 +286,16 @@ __global__ __launch_bounds__(256) void k_dn_apply(c64* part, const c64* __restri
 // out[r] = sum over splits in order; the coarse-solve statistics of the
 // active rhs (one iteration per call).
 __global__ __launch_bounds__(256) void k_dn_reduce(c64* out, const c64* part, long n, int nrhs, int S,
-                                                   const int* parent, int* its, int* calls, int* tot) {
+                                                   const int* parent, int* its, int* calls, int* tot,
+                                                   int* worked) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
+  if (worked && i == 0 && r == 0) {
+    int any = 0;
+    for (int q = 0; q < nrhs && !any; ++q) any = !parent || parent[q];
+    *worked = any;
+  }
+  if (parent && !parent[r]) return;
   if (i < n) {
     c64 s = part[(long)r * n + i];
     for (int q = 1; q < S; ++q) s += part[((long)q * nrhs + r) * n + i];
@@ -340,18 +354,19 @@ void build_dense_inverse(DenseInverse& D, const CoarseLevel& L, hipStream_t st) 
 }
 
 void dense_apply(const DenseInverse& D, c64* out, const c64* in, c64* part, int nrhs, const int* parent, int* its,
-                 int* calls, int* tot, hipStream_t st) {
+                 int* calls, int* tot, hipStream_t st, int* worked) {
   KDMG_CHECK(D.built, KDMG_EINVAL, "exact coarsest solve: inverse not built");
   const long n = D.n, kc = split_width(n, nrhs);
   const int S = (int)cdiv(n, kc);
   const unsigned rt = cdiv(n, 64);
   if (nrhs > 16)
     hipLaunchKernelGGL(k_dn_apply<2>, dim3(rt, S, cdiv(nrhs, 32)), dim3(256), 0, st, part, D.X.as<c64>(), in, n,
-                       nrhs, kc);
+                       nrhs, kc, parent);
   else
-    hipLaunchKernelGGL(k_dn_apply<1>, dim3(rt, S, 1), dim3(256), 0, st, part, D.X.as<c64>(), in, n, nrhs, kc);
+    hipLaunchKernelGGL(k_dn_apply<1>, dim3(rt, S, 1), dim3(256), 0, st, part, D.X.as<c64>(), in, n, nrhs, kc,
+                       parent);
   hipLaunchKernelGGL(k_dn_reduce, dim3(cdiv(n, 256), nrhs), dim3(256), 0, st, out, part, n, nrhs, S, parent, its,
-                     calls, tot);
+                     calls, tot, worked);
   KDMG_LAUNCH_CHECK();
 }
 

@@ -39,11 +39,13 @@ void build_dense_inverse(DenseInverse& D, const CoarseLevel& L, hipStream_t st);
 // K-split of the product for nrhs rhs: number of partial products.
 int dense_apply_splits(long n, int nrhs);
 
-// out[r] = X in[r] for r < nrhs; `part` holds dense_apply_splits(n, nrhs) *
-// nrhs * n complex entries.  The statistics of a coarse solve (one iteration
-// per call) are recorded in `its`, `calls`, `tot` for the rhs that `parent`
-// marks active (all when null); any may be null.
+// out[r] = X in[r] for the rhs r < nrhs that `parent` marks active (all when
+// null; the others' outputs are left as they were); `part` holds
+// dense_apply_splits(n, nrhs) * nrhs * n complex entries.  The statistics of
+// a coarse solve (one iteration per call) are recorded in `its`, `calls`,
+// `tot` for the active rhs; *worked receives whether any rhs was active.  Any
+// of these may be null.
 void dense_apply(const DenseInverse& D, c64* out, const c64* in, c64* part, int nrhs, const int* parent, int* its,
-                 int* calls, int* tot, hipStream_t st);
+                 int* calls, int* tot, hipStream_t st, int* worked = nullptr);
 
 }  // namespace kdmg

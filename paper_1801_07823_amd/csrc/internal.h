@@ -418,6 +418,10 @@ struct kdmg_hierarchy {
     // when the solve ends
     std::vector<std::pair<hipEvent_t, hipEvent_t>> dn_ev;
     size_t dn_used = 0;
+    // per event pair: whether the product had an active rhs (a product whose
+    // rhs had all converged returns at once and is not counted)
+    kdmg::DevBuf dn_work;
+    static constexpr size_t DN_CAP = 4096;
   } timer;
   ~kdmg_hierarchy();
   // device bytes owned by this hierarchy (borrowed transfers not included)
@@ -638,12 +642,16 @@ void transfer_restrict(const Transfer& T, const kdmg_lattice& lat, const CoarseL
       hipLaunchKernelGGL(fn, grid, dim3(256), bytes(), st, out, in, si, P, lat.g, T.a2, even_only, act, nrhs, RB);
     }
   } else {
-    const int ndn = 2 * T.nv;
-    int parts = 256 / ndn;
-    if (parts < 1) parts = 1;
-    dim3 grid(T.nZ, nrhs);
-    hipLaunchKernelGGL((k_restrict_c<R, PT, VI, VO>), grid, dim3(ndn * parts), 0, st, out, in, P,
-                       T.children.as<int>(), T.nchild, T.nsf, T.ndf, T.nZ, T.nv, act);
+    // tiles of up to 8 rhs: four or more workgroups per aggregate at 32 rhs
+    const int nrow = T.nchild * T.ndf;
+    int RB = nrhs < 8 ? nrhs : 8;
+    auto bytes = [&] { return ((size_t)nrow * T.nv + (size_t)RB * nrow) * sizeof(Cx<R>); };
+    while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
+    KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "restriction: aggregate too large for LDS staging");
+    auto fn = k_restrict_c<R, PT, VI, VO>;
+    ensure_smem((const void*)fn, bytes());
+    hipLaunchKernelGGL(fn, dim3(T.nZ, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, in, P, T.children.as<int>(),
+                       T.nchild, T.nsf, T.ndf, T.nZ, T.nv, act, nrhs, RB);
   }
   KDMG_LAUNCH_CHECK();
 }
@@ -685,9 +693,15 @@ void transfer_prolong(const Transfer& T, const kdmg_lattice& lat, Cx<VO>* out, l
     hipLaunchKernelGGL(fn, dim3(T.a2.Ncx * T.a2.Nct, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, so, add, sa, in,
                        P, lat.g, T.a2, npar, act, nrhs, RB);
   } else {
-    dim3 grid(cdiv((long)T.nsf * T.ndf, 256), nrhs);
-    hipLaunchKernelGGL((k_prolong_c<R, PT, VI, VO>), grid, dim3(256), 0, st, out, add, in, P,
-                       T.parent.as<int>(), T.nsf, T.ndf, T.nZ, T.nv, act);
+    const int nrow = T.nchild * T.ndf;
+    int RB = nrhs < 8 ? nrhs : 8;
+    auto bytes = [&] { return ((size_t)nrow * (T.nv + 1) + (size_t)RB * 2 * T.nv) * sizeof(Cx<R>); };
+    while (RB > 1 && bytes() > 64 * 1024) RB /= 2;
+    KDMG_CHECK(bytes() <= LDS_LIMIT, KDMG_EUNSUPPORTED, "prolongation: aggregate too large for LDS staging");
+    auto fn = k_prolong_c<R, PT, VI, VO>;
+    ensure_smem((const void*)fn, bytes());
+    hipLaunchKernelGGL(fn, dim3(T.nZ, cdiv(nrhs, RB)), dim3(256), bytes(), st, out, add, in, P, T.children.as<int>(),
+                       T.nchild, T.nsf, T.ndf, T.nZ, T.nv, act, nrhs, RB);
   }
   KDMG_LAUNCH_CHECK();
 }

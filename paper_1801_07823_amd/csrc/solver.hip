@@ -97,6 +97,9 @@ struct LevelWS {
   // rhs than kdmg_mg_params.coarse_tail only)
   int tail = 0;
   DevBuf tx, tr, tp, trr, ttarget, tact, tints, tPA, tPB, tidx;
+  // intermediate GCR above the exact coarsest solve: the iteration count of
+  // its last call, the first iteration after which the next call polls
+  int gcr_last = 0;
   std::unique_ptr<ChunkGraph> cg_graph_t;
   KrylovAlloc ks, kmr;
   template <class T> Cx<T>* v(DevBuf& d) const { return d.as<Cx<T>>(); }
@@ -593,7 +596,10 @@ class Runner {
         if constexpr (sizeof(T) == 8) {
           auto& tm = h_.timer;
           std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-          if (tm.on) {
+          int* worked = nullptr;
+          if (tm.on && tm.dn_used < tm.DN_CAP) {
+            if (!tm.dn_work.p) tm.dn_work.alloc(sizeof(int) * tm.DN_CAP);
+            worked = tm.dn_work.as<int>() + tm.dn_used;
             if (tm.dn_used == tm.dn_ev.size()) {
               std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
               KDMG_HIP(hipEventCreate(&e.first));
@@ -603,7 +609,8 @@ class Runner {
             ev = &tm.dn_ev[tm.dn_used++];
             KDMG_HIP(hipEventRecord(ev->first, c_.st));
           }
-          dense_apply(h_.dinv, x, b, L.part.as<c64>(), nrhs_, parent, L.ks.k.its, L.ks.k.calls, L.ks.k.tot, c_.st);
+          dense_apply(h_.dinv, x, b, L.part.as<c64>(), nrhs_, parent, L.ks.k.its, L.ks.k.calls, L.ks.k.tot, c_.st,
+                      worked);
           if (ev) KDMG_HIP(hipEventRecord(ev->second, c_.st));
         } else {
           throw Error(KDMG_EINVAL, "exact coarsest solve: the coarsest level runs in FP64");
@@ -627,8 +634,14 @@ class Runner {
           if (graphed) kcycle_graphed<T>(l, z, rr, a);
           else kcycle<T>(l, z, rr, a);
         };
+        // graphed: the host first reads the convergence flags after as many
+        // iterations as the last call took, so a call that repeats its
+        // count runs from start to finish without a host round trip
+        int mx = 0;
         gcr_solve<T>(c_, nrhs_, n, b, x, r, L.v<T>(L.Z), L.v<T>(L.W), P.inter_restart, P.inter_maxit,
-                     P.inter_tol, nullptr, ks, parent, opf, prec);
+                     P.inter_tol, nullptr, ks, parent, opf, prec, false, 0,
+                     graphed ? std::max(1, L.gcr_last) : 0, graphed ? &mx : nullptr);
+        if (graphed) L.gcr_last = mx;
       }
     });
   }
@@ -945,7 +958,11 @@ extern "C" kdmg_status kdmg_solve(kdmg_hierarchy* h, const void* b, void* x, int
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   {  // exact coarsest solve: kernel time of the products recorded in this solve
     auto& tm = h->timer;
+    std::vector<int> worked(tm.dn_used);
+    if (tm.dn_used)
+      KDMG_HIP(hipMemcpy(worked.data(), tm.dn_work.p, sizeof(int) * tm.dn_used, hipMemcpyDeviceToHost));
     for (size_t e = 0; e < tm.dn_used; ++e) {
+      if (!worked[e]) continue;  // every rhs had converged: the launch returned at once
       float ms = 0.f;
       KDMG_HIP(hipEventElapsedTime(&ms, tm.dn_ev[e].first, tm.dn_ev[e].second));
       tm.ms += ms;

@@ -133,7 +133,11 @@ def test_kcycle_graphs_match_eager(K):
     host decision below it, and its two halves around the coarsest product
     replay as captured hipGraphs: the replayed solve equals the plainly
     launched one bit for bit, on repeated solves with other work between
-    them, and after a rebind to another configuration (graphs recaptured)."""
+    them, and after a rebind to another configuration (graphs recaptured).
+    In that mode the intermediate GCR also defers its host poll of the
+    convergence flags to the iteration count of its previous call (iterations
+    past convergence are device no-ops): the per-rhs iteration statistics
+    agree too."""
     dims, beta, m = (32, 32), 6.0, 0.02
     levels = [((2, 2), 8), ((2, 2), 8)]
     U, oh, psi0 = setup(dims, beta, m, levels, 8)
@@ -145,12 +149,13 @@ def test_kcycle_graphs_match_eager(K):
     for graphs in (True, False):
         gh = K.Hierarchy(lat, m, K.make_params(levels, coarse_solver=1), psi0)
         gh.graphs(graphs)
-        xs = []
+        xs, stats = [], []
         for rep in range(3):
             x = torch.empty_like(b)
             info, _ = K.kdmg_solve(gh, b, x, nrhs, 1e-10, prec=K.KDMG_MIXED)
             assert all(i["converged"] for i in info)
             xs.append(x.clone())
+            stats.append([(i["outer_its"], tuple(i["level_avg_its"])) for i in info])
             torch.cuda.synchronize()
             _ = (b * 2.0).sum()  # unrelated work between replays
         replays = gh.counters()["graph_replays"]
@@ -161,7 +166,8 @@ def test_kcycle_graphs_match_eager(K):
         x2 = torch.empty_like(b)
         info2, _ = K.kdmg_solve(gh, b, x2, nrhs, 1e-10, prec=K.KDMG_MIXED)
         assert all(i["converged"] for i in info2)
-        res[graphs] = (xs, x2)
+        res[graphs] = (xs, x2, stats)
     for rep in range(3):
         assert torch.equal(res[True][0][rep], res[False][0][0])
+        assert res[True][2][rep] == res[False][2][0]
     assert torch.equal(res[True][1], res[False][1])
