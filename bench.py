@@ -233,7 +233,16 @@ def dslash_time(fn, out, reps):
 
 SERVE_SIZES = (64, 128, 256, 512)
 SERVE_BETAS = (3.0, 6.0, 10.0)
-SERVE_M_SETUP = 0.001
+# beta = 3 is served up to this lattice size.  On larger lattices the K-cycle
+# breaks down on such fields in the FP64 oracle as on the GPU (256^2, m =
+# 0.01, with the serving and the Table 1 null vectors, an exact coarsest LU,
+# and intermediate caps of 16 and 64 alike), the breakdown near the cutoff
+# that Sec. 4 accepts; there the configurations cycle through the other betas.
+SERVE_BETA3_MAX_L = 128
+# Null vectors are relaxed once per configuration at each of these masses, and
+# a request uses the set relaxed nearest its mass (in log scale): each set
+# serves a factor of about 3 either side of its mass over [1e-3, 1e-1].
+SERVE_M_SETUPS = (0.00316, 0.0316)
 # n_vec per coarsening for the served stream: 16 and 16 keep the intermediate
 # level effective on the rough beta = 3 fields (with 16 then 12 it hits its
 # 16-iteration cap there and the outer solve slows several-fold)
@@ -250,6 +259,13 @@ SERVE_SETUP_TOL, SERVE_SETUP_MAXIT = 1e-6, 1000
 SERVE_STALL = 16
 
 
+def _serve_betas(L, betas, beta3_max_L):
+    """The beta cycle of the configurations of lattice size L."""
+    if L > beta3_max_L:
+        return tuple(b for b in betas if b != 3.0) or tuple(betas)
+    return tuple(betas)
+
+
 def _serve_field(args):
     L, c, sweeps, betas = args
     from synth import u1_heatbath, config_seed
@@ -263,14 +279,16 @@ def serve_main(a):
     lattice sizes uniform in {64,128,256,512}^2, masses log-uniform in
     [1e-3, 1e-1], each request on one of `--serve-configs` resident
     configurations per size (beta cycling through `--serve-betas`, by default
-    3, 6, 10).  Reports the closed-loop
+    3, 6, 10; beta = 3 only up to `--serve-beta3-max-L`), with the null-vector
+    set relaxed nearest its mass (SERVE_M_SETUPS).  Reports the closed-loop
     capacity, then p50/p99 latency and solves/s for Poisson arrivals at
     fractions of it, and checks a sample of results alone against the mix."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
     from synth import gaussian_vectors, config_seed
     betas = tuple(a.serve_betas)
-    jobs = [(L, c, a.serve_sweeps, betas) for L in SERVE_SIZES for c in range(a.serve_configs)]
+    jobs = [(L, c, a.serve_sweeps, _serve_betas(L, betas, a.serve_beta3_max_L)) for L in SERVE_SIZES
+            for c in range(a.serve_configs)]
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=min(16, len(jobs))) as ex:
         fields = list(ex.map(_serve_field, jobs))
@@ -288,8 +306,8 @@ def serve_main(a):
         seed = config_seed(L, beta, c)
         nc1 = (L // 8) * (L // 8) * 2 * nv1
         psi0 = [gaussian_vectors(nv1, L * L, seed, tag=1), gaussian_vectors(nv2, nc1, seed, tag=2)]
-        h = kdmg.Hierarchy(lat, SERVE_M_SETUP, params, psi0)
-        cfgs.append((L, c, beta, lat, h))
+        hs = [kdmg.Hierarchy(lat, ms, params, psi0) for ms in SERVE_M_SETUPS]
+        cfgs.append((L, c, beta, lat, hs))
     torch.cuda.synchronize()
     print("setup of %d hierarchies: %.1f s" % (len(cfgs), time.perf_counter() - t0), file=sys.stderr, flush=True)
     rng = np.random.default_rng(12345)
@@ -302,6 +320,10 @@ def serve_main(a):
             L = cfgs[k][0]
             out.append((k, m, L, tag * 100000 + i))
         return out
+
+    def setup_index(m):
+        """The vector set relaxed nearest m (log scale)."""
+        return int(np.argmin([abs(math.log(m / ms)) for ms in SERVE_M_SETUPS]))
 
     def run(srv, ids, reqs, arrivals):
         """arrivals: seconds after start (None: all at once).  Returns latencies,
@@ -336,7 +358,7 @@ def serve_main(a):
             k, m, L, seed = reqs[i]
             b = torch.from_numpy(gaussian_vectors(1, L * L, seed, tag=0)).to("cuda")
             x = torch.zeros_like(b)
-            t = srv.submit(ids[k], m, b, x, 1, 1e-10, kdmg.KDMG_MIXED)
+            t = srv.submit(ids[k][setup_index(m)], m, b, x, 1, 1e-10, kdmg.KDMG_MIXED)
             live[t] = (i, x)
         while live:
             drain(True)
@@ -352,9 +374,9 @@ def serve_main(a):
 
 
 def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rng, failures):
-    ids = [srv.add_config(c[4]) for c in cfgs]
+    ids = [[srv.add_config(h) for h in c[4]] for c in cfgs]
     # warm-up: one request per configuration (tunes launch shapes, fills the pool)
-    warm = [(k, 0.01, cfgs[k][0], 900000 + k) for k in range(len(cfgs))]
+    warm = [(k, ms, cfgs[k][0], 900000 + 100 * k + j) for k in range(len(cfgs)) for j, ms in enumerate(SERVE_M_SETUPS)]
     t0 = time.perf_counter()
     run(srv, ids, warm, None)
     print("warm-up: %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
@@ -400,7 +422,7 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
     sample = list(range(min(a.serve_check, len(reqs))))
     alone = kdmg.Server(1, budget)
     try:
-        ids1 = [alone.add_config(c[4]) for c in cfgs]
+        ids1 = [[alone.add_config(h) for h in c[4]] for c in cfgs]
         _, _, xs1, _ = run(alone, ids1, [reqs[i] for i in sample], None)
     finally:
         alone.close()
@@ -411,7 +433,7 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
            "closed_loop_converged": closed_ok, "points": points,
            "slots": a.serve_slots, "hbm_budget_gb": a.serve_budget_gb, "configs": len(cfgs),
            "configs_per_size": a.serve_configs, "betas": list(a.serve_betas), "heatbath_sweeps": a.serve_sweeps,
-           "setup_mass": SERVE_M_SETUP, "prec": "mixed", "tol": 1e-10,
+           "setup_masses": list(SERVE_M_SETUPS), "beta3_max_L": a.serve_beta3_max_L, "prec": "mixed", "tol": 1e-10,
            "levels": "4x4 n_vec %d; 2x2 n_vec %d" % SERVE_NV,
            "setup_relaxation": {"tol": SERVE_SETUP_TOL, "maxit": SERVE_SETUP_MAXIT},
            "outer_maxit": 80, "outer_stall": SERVE_STALL,
@@ -604,6 +626,70 @@ def transfer_main(a):
     return 0
 
 
+# fine operators: (lattice, rhs, precision) cases; 256^2 x 32 mixed is the
+# solve's shape (in the Infinity Cache), the others exceed it
+FINE_CASES = (((256, 256), 32, "mixed"), ((2048, 2048), 1, "fp64"), ((2048, 2048), 32, "mixed"),
+              ((4096, 4096), 1, "fp64"), ((4096, 4096), 4, "mixed"))
+
+
+def fine_main(a):
+    """The fine operators the solve runs, on random U(1) fields: D in natural
+    order (k_dslash_nat) and A = 1 + C B^-1 in the block layout (k_binv, then
+    k_hop with the input added), each called `--fine-reps` times per case so
+    that a kernel trace or a counter pass sees them.  Algorithmic bytes per
+    launch (vectors 16 B FP64 / 8 B FP32 per complex, links 16 B FP64 / 4 B
+    FP16):
+      k_dslash_nat: per site, in + out per rhs and the two forward links;
+      k_binv:       per site, in + out per rhs and one intra-block link;
+      k_hop:        per site, in + added input + out per rhs and one
+                    inter-block link.
+    kdmg_apply_A also permutes natural <-> block layout (k_permute), which is
+    not part of the operator.  Prints one JSON line with the bytes and the time
+    per call (D: GPU time from graph replay; A: event time per API call); the
+    per-kernel durations come from the kernel trace."""
+    import numpy as np
+    import torch
+    from paper_1801_07823_amd import kdmg
+    kdmg.kdmg_init(0)
+    # calibration copy of known size for counter passes (reads 64 MiB, writes 64 MiB)
+    src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    rng = np.random.default_rng(9)
+    out = []
+    for dims, nr, pname in FINE_CASES:
+        V = dims[0] * dims[1]
+        U = np.exp(1j * rng.uniform(0, 2 * np.pi, size=(2, V, 1, 1)))
+        lat = kdmg.Lattice(dims, U)
+        del U
+        prec = kdmg.KDMG_FP64 if pname == "fp64" else kdmg.KDMG_MIXED
+        dt = torch.complex128 if pname == "fp64" else torch.complex64
+        vb, lb = (16, 16) if pname == "fp64" else (8, 4)
+        vi = torch.randn((nr, V), dtype=dt, device="cuda")
+        vo = torch.empty_like(vi)
+        rec = {"lattice": list(dims), "nrhs": nr, "prec": pname,
+               "bytes": {"k_dslash_nat": V * (2 * vb * nr + 2 * lb), "k_binv": V * (2 * vb * nr + lb),
+                         "k_hop": V * (3 * vb * nr + lb)}}
+        for name, fn in (("D", lambda: kdmg.kdmg_apply_D(lat, MASS, vi, vo, nr, prec=prec)),
+                         ("A", lambda: kdmg.kdmg_apply_A(lat, MASS, vi, vo, nr, prec=prec))):
+            for _ in range(a.fine_reps):
+                fn()
+            torch.cuda.synchronize()
+            # kdmg_apply_A allocates its work space per call (no graph capture):
+            # event time per call, host overhead and the layout permutations included
+            t = graph_time(fn, vo) if name == "D" else event_time(fn, a.fine_reps)
+            rec[name + "_us_per_call"] = t * 1e6 if t is not None else None
+        print("fine %s x %d %s: D %.1f us, A %.1f us per call" % (dims, nr, pname, rec["D_us_per_call"] or -1,
+                                                                rec["A_us_per_call"] or -1), file=sys.stderr, flush=True)
+        out.append(rec)
+        del vi, vo, lat
+        torch.cuda.empty_cache()
+    print(json.dumps({"fine_operators": out}))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -632,11 +718,16 @@ def main():
                     help="KD-MG and CG-eo on the benchmark field and rhs at these masses (one JSON line each)")
     ap.add_argument("--scan-outer", type=int, default=60, help="outer FGCR cap of the mass scan")
     ap.add_argument("--scan-cap", type=int, default=COARSE_MAXIT, help="coarsest CGNE cap of the mass scan")
+    ap.add_argument("--fine-profile", action="store_true",
+                    help="fine D and A = 1 + C B^-1 over in- and out-of-cache shapes, for kernel traces and counters")
+    ap.add_argument("--fine-reps", type=int, default=20)
     ap.add_argument("--transfer-profile", action="store_true",
                     help="2048^2 mixed restriction / prolongation calls for a kernel trace; prints no metric")
     ap.add_argument("--serve-configs", type=int, default=8)
     ap.add_argument("--serve-sweeps", type=int, default=200)
     ap.add_argument("--serve-betas", type=float, nargs="+", default=list(SERVE_BETAS))
+    ap.add_argument("--serve-beta3-max-L", type=int, default=SERVE_BETA3_MAX_L,
+                    help="largest lattice size served at beta = 3")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-closed", type=int, default=48)
@@ -658,6 +749,8 @@ def main():
         return su3_main(a)
     if a.transfer_profile:
         return transfer_main(a)
+    if a.fine_profile:
+        return fine_main(a)
     if a.mass_scan:
         return mass_scan_main(a)
     cpu = None if (a.no_cpu or a.kernel_profile) else start_cpu_leg(a.cpu_procs)

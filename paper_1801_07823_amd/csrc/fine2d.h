@@ -26,6 +26,8 @@
 // B^-1 is recomputed from the four intra-block links in every kernel that
 // needs it instead of being stored.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 #include "blas.h"
 
@@ -48,6 +50,55 @@ __host__ __device__ __forceinline__ int blk_index(const Geo2& g, int X0, int X1)
 }
 // chirality of site s in a block: 0 for eps=+1 (s0, s3), 1 for eps=-1 (s1, s2)
 __host__ __device__ __forceinline__ int chir2(int s) { return (s == 1 || s == 2) ? 1 : 0; }
+
+// Workgroup index renumbered so that each of the 8 XCDs (which receive
+// workgroups round-robin, XCD = index % 8, each with its own L2) takes one
+// contiguous range of the grid: data shared by neighbouring workgroups (the
+// rows x1 +- 1 of the Dslash, the 128-byte lines split between neighbouring
+// aggregates of the transfers) is then read through the same L2.
+__device__ __forceinline__ int xcd_block(unsigned b, unsigned nb) {
+  return (int)((nb % 8u == 0) ? (b & 7u) * (nb >> 3) + (b >> 3) : b);
+}
+
+// Two adjacent complex values, loaded or stored as one 8-byte (FP16) or
+// 16-byte (FP32) access.
+struct alignas(8) HPair {
+  Cx<_Float16> a, b;
+};
+struct alignas(16) FPair {
+  Cx<float> a, b;
+};
+
+// A block's four values (32 B in FP32: two 16-byte accesses; FP64: four).
+// p is 4-entry aligned: every block-layout vector here is.
+template <class R, class VT>
+__device__ __forceinline__ void load4(const Cx<VT>* p, Cx<R> v[4]) {
+  if constexpr (std::is_same<VT, float>::value) {
+    const FPair a = reinterpret_cast<const FPair*>(p)[0], b = reinterpret_cast<const FPair*>(p)[1];
+    v[0] = ld<R>(a.a);
+    v[1] = ld<R>(a.b);
+    v[2] = ld<R>(b.a);
+    v[3] = ld<R>(b.b);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = ld<R>(p[s]);
+  }
+}
+template <class R, class VT>
+__device__ __forceinline__ void store4(Cx<VT>* p, const Cx<R> v[4]) {
+  if constexpr (std::is_same<VT, float>::value) {
+    FPair a, b;
+    a.a = st<VT>(v[0]);
+    a.b = st<VT>(v[1]);
+    b.a = st<VT>(v[2]);
+    b.b = st<VT>(v[3]);
+    reinterpret_cast<FPair*>(p)[0] = a;
+    reinterpret_cast<FPair*>(p)[1] = b;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) p[s] = st<VT>(v[s]);
+  }
+}
 
 template <class R, class LT>
 __device__ __forceinline__ void load_intra(const Cx<LT>* L, Cx<R> k[4]) {
@@ -114,10 +165,22 @@ __device__ __forceinline__ void hop_block(const Geo2& g, int p, int b, const Nbr
   const Cx<LT>* Lo = links + ((size_t)p * g.Nb2 + b) * 8;
   const Cx<LT>* Lxm = links + ((size_t)q * g.Nb2 + n.xm) * 8;
   const Cx<LT>* Ltm = links + ((size_t)q * g.Nb2 + n.tm) * 8;
-  Cx<R> xp0 = ld<R>(in[4 * n.xp + 0]), xp2 = ld<R>(in[4 * n.xp + 2]);
-  Cx<R> xm1 = ld<R>(in[4 * n.xm + 1]), xm3 = ld<R>(in[4 * n.xm + 3]);
-  Cx<R> tp0 = ld<R>(in[4 * n.tp + 0]), tp1 = ld<R>(in[4 * n.tp + 1]);
-  Cx<R> tm2 = ld<R>(in[4 * n.tm + 2]), tm3 = ld<R>(in[4 * n.tm + 3]);
+  Cx<R> xp0, xp2, xm1, xm3, tp0, tp1, tm2, tm3;
+  if constexpr (std::is_same<VT, float>::value) {
+    // whole neighbour blocks in 16-byte accesses (the unused halves come from
+    // the same cache lines)
+    Cx<R> a[4], c[4], e[4], f[4];
+    load4<R, VT>(in + 4L * n.xp, a);
+    load4<R, VT>(in + 4L * n.xm, c);
+    load4<R, VT>(in + 4L * n.tp, e);
+    load4<R, VT>(in + 4L * n.tm, f);
+    xp0 = a[0], xp2 = a[2], xm1 = c[1], xm3 = c[3], tp0 = e[0], tp1 = e[1], tm2 = f[2], tm3 = f[3];
+  } else {
+    xp0 = ld<R>(in[4 * n.xp + 0]), xp2 = ld<R>(in[4 * n.xp + 2]);
+    xm1 = ld<R>(in[4 * n.xm + 1]), xm3 = ld<R>(in[4 * n.xm + 3]);
+    tp0 = ld<R>(in[4 * n.tp + 0]), tp1 = ld<R>(in[4 * n.tp + 1]);
+    tm2 = ld<R>(in[4 * n.tm + 2]), tm3 = ld<R>(in[4 * n.tm + 3]);
+  }
   if (eps_in) { xp2 = -xp2; xm1 = -xm1; tp1 = -tp1; tm2 = -tm2; }
   out[0] = -(cmul_conj(ld<R>(Lxm[4]), xm1) + cmul_conj(ld<R>(Ltm[6]), tm2));
   out[1] = ld<R>(Lo[4]) * xp0 - cmul_conj(ld<R>(Ltm[7]), tm3);
@@ -140,25 +203,28 @@ __global__ __launch_bounds__(256) void k_binv(Cx<VT>* out, long so, Cx<VT>* out2
                                                const Cx<VT>* in, long si, const Cx<VT>* add, long sa,
                                                const Cx<LT>* links, Geo2 g, int p0, R m, int eps_out,
                                                const int* act) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y, p = p0 + blockIdx.z;
   if (b >= g.Nb2 || !is_active(act, r)) return;
   Cx<R> L[4], v[4], w[4];
   load_intra<R, LT>(links + ((size_t)p * g.Nb2 + b) * 8, L);
   const long o = (long)p * g.half + 4L * b;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) v[s] = ld<R>(in[r * si + o + s]);
+  load4<R, VT>(in + r * si + o, v);
   binv_block<R>(L, m, v, w);
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (eps_out && (s == 1 || s == 2)) w[s] = -w[s];
-    if (add) w[s] += ld<R>(add[r * sa + o + s]);
-    out[r * so + o + s] = st<VT>(w[s]);
+  if (eps_out) {
+    w[1] = -w[1];
+    w[2] = -w[2];
   }
+  if (add) {
+    Cx<R> a[4];
+    load4<R, VT>(add + r * sa + o, a);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) w[s] += a[s];
+  }
+  store4<R, VT>(out + r * so + o, w);
   if (out2) {
     binv_block<R>(L, m, w, v);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) out2[r * so2 + o + s] = st<VT>(v[s]);
+    store4<R, VT>(out2 + r * so2 + o, v);
   }
 }
 
@@ -168,7 +234,7 @@ __global__ __launch_bounds__(256) void k_hop(Cx<VT>* out, long so, const Cx<VT>*
                                               const Cx<VT>* add, long sa, const Cx<VT>* add2,
                                               long sa2, R c2, R sgn, const Cx<LT>* links, Geo2 g,
                                               int p0, R m, int mode, int eps_in, const int* act) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y, p = p0 + blockIdx.z;
   if (b >= g.Nb2 || !is_active(act, r)) return;
   const Nbr2 n = nbr2(g, p, b);
@@ -180,17 +246,23 @@ __global__ __launch_bounds__(256) void k_hop(Cx<VT>* out, long so, const Cx<VT>*
     Cx<R> L[4], w[4];
     load_intra<R, LT>(links + ((size_t)p * g.Nb2 + b) * 8, L);
     binv_block<R>(L, m, h, w);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) out[r * so + o + s] = st<VT>(w[s]);
+    store4<R, VT>(out + r * so + o, w);
     return;
   }
+  Cx<R> v[4], a[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    Cx<R> v = sgn * h[s];
-    if (add) v += ld<R>(add[r * sa + o + s]);
-    if (add2) v += c2 * ld<R>(add2[r * sa2 + o + s]);
-    out[r * so + o + s] = st<VT>(v);
+  for (int s = 0; s < 4; ++s) v[s] = sgn * h[s];
+  if (add) {
+    load4<R, VT>(add + r * sa + o, a);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] += a[s];
   }
+  if (add2) {
+    load4<R, VT>(add2 + r * sa2 + o, a);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] += c2 * a[s];
+  }
+  store4<R, VT>(out + r * so + o, v);
 }
 
 // out = D in on full block-layout vectors; with `sub`, out = sub - D in.
@@ -218,14 +290,6 @@ __global__ __launch_bounds__(256) void k_dslash_blk(Cx<VT>* out, long so, const 
   }
 }
 
-// Workgroup index renumbered so that each of the 8 XCDs (which receive
-// workgroups round-robin, XCD = index % 8, each with its own L2) takes one
-// contiguous range of the grid: data shared by neighbouring workgroups (the
-// rows x1 +- 1 of the Dslash, the 128-byte lines split between neighbouring
-// aggregates of the transfers) is then read through the same L2.
-__device__ __forceinline__ int xcd_block(unsigned b, unsigned nb) {
-  return (int)((nb % 8u == 0) ? (b & 7u) * (nb >> 3) + (b >> 3) : b);
-}
 
 // D in natural site order: one thread per site and RB right-hand sides (the
 // site's four links are loaded once for all of them; every vector load of
@@ -264,6 +328,67 @@ __global__ __launch_bounds__(256) void k_dslash_nat(Cx<VT>* __restrict__ out, co
     acc += ut * v3[b];
     acc -= cmul_conj(utm, v4[b]);
     out[(long)(r0 + b) * vol + x] = st<VT>(acc);
+  }
+}
+
+// Mixed-precision D in natural site order with two sites per thread: the
+// sites x, x + 1 (x even) of a thread and their x-neighbours x - 1, x + 2 lie
+// in three aligned pairs, and the t-neighbours in two more, so every rhs
+// costs five 16-byte loads and one 16-byte store (FP32 complex), the links
+// four 8-byte loads (FP16 complex pairs) per thread.  Same arithmetic per
+// site as k_dslash_nat.  Lx even; vectors 16-byte aligned per rhs (vol even).
+template <int RB>
+__global__ __launch_bounds__(256) void k_dslash_nat2(Cx<float>* __restrict__ out, const Cx<float>* __restrict__ in,
+                                                     const Cx<_Float16>* __restrict__ Ux,
+                                                     const Cx<_Float16>* __restrict__ Ut, int Lx, int Lt, long vol,
+                                                     float m, int nrhs) {
+  const long pr = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int r0 = blockIdx.y * RB;
+  const long x = 2 * pr;
+  if (x >= vol) return;
+  const int x1 = (int)(x / Lx), x0 = (int)(x - (long)x1 * Lx);
+  const int x0l = x0 == 0 ? Lx - 2 : x0 - 2, x0r = x0 + 2 == Lx ? 0 : x0 + 2;
+  const int x1p = x1 + 1 == Lt ? 0 : x1 + 1, x1m = x1 == 0 ? Lt - 1 : x1 - 1;
+  // pair indices (a pair holds sites 2k, 2k + 1)
+  const long pc = x >> 1, pl = ((long)x1 * Lx + x0l) >> 1, prr = ((long)x1 * Lx + x0r) >> 1;
+  const long pu = ((long)x1p * Lx + x0) >> 1, pd = ((long)x1m * Lx + x0) >> 1;
+  const HPair* Uxp = reinterpret_cast<const HPair*>(Ux);
+  const HPair* Utp = reinterpret_cast<const HPair*>(Ut);
+  const HPair uxc = Uxp[pc], uxl = Uxp[pl], utc = Utp[pc], utd = Utp[pd];
+  const Cx<float> uxa = ld<float>(uxc.a), uxb = ld<float>(uxc.b), uxm = ld<float>(uxl.b);
+  const Cx<float> uta = ld<float>(utc.a), utb = ld<float>(utc.b), utma = ld<float>(utd.a), utmb = ld<float>(utd.b);
+  const FPair* vp = reinterpret_cast<const FPair*>(in);
+  const long hv = vol >> 1;
+  FPair c[RB], l[RB], rr[RB], u[RB], d[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const long row = (long)(r0 + b < nrhs ? r0 + b : r0) * hv;
+    c[b] = vp[row + pc];
+    l[b] = vp[row + pl];
+    rr[b] = vp[row + prr];
+    u[b] = vp[row + pu];
+    d[b] = vp[row + pd];
+  }
+  FPair* op = reinterpret_cast<FPair*>(out);
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    if (r0 + b >= nrhs) continue;
+    FPair o;
+    // site x: +x -> x + 1, -x -> x - 1 (left pair's second), +-t
+    Cx<float> acc = m * c[b].a;
+    acc += uxa * c[b].b;
+    acc -= cmul_conj(uxm, l[b].b);
+    acc += uta * u[b].a;
+    acc -= cmul_conj(utma, d[b].a);
+    o.a = acc;
+    // site x + 1: +x -> x + 2 (right pair's first), -x -> x
+    acc = m * c[b].b;
+    acc += uxb * rr[b].a;
+    acc -= cmul_conj(uxa, c[b].a);
+    acc += utb * u[b].b;
+    acc -= cmul_conj(utmb, d[b].b);
+    o.b = acc;
+    op[(long)(r0 + b) * hv + pc] = o;
   }
 }
 

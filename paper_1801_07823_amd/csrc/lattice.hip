@@ -367,12 +367,26 @@ extern "C" kdmg_status kdmg_apply_D(const kdmg_lattice* lat, double mass, const 
       hipLaunchKernelGGL((k_dslash_nat<R, LT, R, 1>), grid, dim3(256), 0, st, (Cx<R>*)out, (const Cx<R>*)in, Ul,
                          Ul + V, lat->dims[0], lat->dims[1], V, (R)mass, nrhs);
   };
-  if (prec == KDMG_FP64)
+  if (prec == KDMG_FP64) {
     launch(double{}, double{}, lat->nat64.as<c64>());
-  else if (prec == KDMG_MIXED)
-    launch(float{}, _Float16{}, lat->nat16.as<c16>());
-  else
+  } else if (prec == KDMG_MIXED && (((uintptr_t)in | (uintptr_t)out) & 15) != 0) {
+    launch(float{}, _Float16{}, lat->nat16.as<c16>());  // vectors not 16-byte aligned: one site per thread
+  } else if (prec == KDMG_MIXED) {
+    // two sites per thread with 16-byte vector accesses (k_dslash_nat2)
+    const Cx<_Float16>* Ul = lat->nat16.as<c16>();
+    const dim3 g2(cdiv(V / 2, 256), cdiv(nrhs, RB));
+    if (RB == 8)
+      hipLaunchKernelGGL(k_dslash_nat2<8>, g2, dim3(256), 0, st, (c32*)out, (const c32*)in, Ul, Ul + V, lat->dims[0],
+                         lat->dims[1], V, (float)mass, nrhs);
+    else if (RB == 4)
+      hipLaunchKernelGGL(k_dslash_nat2<4>, g2, dim3(256), 0, st, (c32*)out, (const c32*)in, Ul, Ul + V, lat->dims[0],
+                         lat->dims[1], V, (float)mass, nrhs);
+    else
+      hipLaunchKernelGGL(k_dslash_nat2<1>, g2, dim3(256), 0, st, (c32*)out, (const c32*)in, Ul, Ul + V, lat->dims[0],
+                         lat->dims[1], V, (float)mass, nrhs);
+  } else {
     throw Error(KDMG_EINVAL, "kdmg_apply_D: bad precision");
+  }
   KDMG_LAUNCH_CHECK();
   KDMG_API_END
 }
