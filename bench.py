@@ -257,6 +257,16 @@ SERVE_SETUP_TOL, SERVE_SETUP_MAXIT = 1e-6, 1000
 # so the near-cutoff fields the method cannot solve release their worker
 # instead of holding it for the full 80 iterations.
 SERVE_STALL = 16
+# Coarsest CGNE cap of the served hierarchies: small masses on the larger
+# lattices need more than the 1024 of the benchmark (reading the cap is a
+# cost only for the requests that reach it)
+SERVE_COARSE_MAXIT = 4096
+# Lattices up to this size take the exact coarsest solve (at most 2048
+# coarsest dofs: the inverse is rebuilt at each request's mass in a few ms);
+# on the rough beta = 3 fields at small mass the capped CGNE leaves the
+# K-cycle too weak there (128^2, m = 0.0013: the FP64 oracle stalls at a cap
+# of 1024 and converges with 4096 or the exact solve)
+SERVE_EXACT_MAX_L = 128
 
 
 def _serve_betas(L, betas, beta3_max_L):
@@ -297,8 +307,10 @@ def serve_main(a):
     from paper_1801_07823_amd import kdmg
     kdmg.kdmg_init(0)
     nv1, nv2 = SERVE_NV
-    params = kdmg.make_params([((4, 4), nv1), ((2, 2), nv2)], coarse_maxit=COARSE_MAXIT, outer_maxit=80,
-                              setup_tol=SERVE_SETUP_TOL, setup_maxit=SERVE_SETUP_MAXIT, outer_stall=SERVE_STALL)
+    def params_for(L):
+        return kdmg.make_params([((4, 4), nv1), ((2, 2), nv2)], coarse_maxit=SERVE_COARSE_MAXIT, outer_maxit=80,
+                                setup_tol=SERVE_SETUP_TOL, setup_maxit=SERVE_SETUP_MAXIT, outer_stall=SERVE_STALL,
+                                coarse_solver=1 if L <= SERVE_EXACT_MAX_L else 0)
     cfgs = []
     t0 = time.perf_counter()
     for L, c, beta, U, plaq in fields:
@@ -306,7 +318,7 @@ def serve_main(a):
         seed = config_seed(L, beta, c)
         nc1 = (L // 8) * (L // 8) * 2 * nv1
         psi0 = [gaussian_vectors(nv1, L * L, seed, tag=1), gaussian_vectors(nv2, nc1, seed, tag=2)]
-        hs = [kdmg.Hierarchy(lat, ms, params, psi0) for ms in SERVE_M_SETUPS]
+        hs = [kdmg.Hierarchy(lat, ms, params_for(L), psi0) for ms in SERVE_M_SETUPS]
         cfgs.append((L, c, beta, lat, hs))
     torch.cuda.synchronize()
     print("setup of %d hierarchies: %.1f s" % (len(cfgs), time.perf_counter() - t0), file=sys.stderr, flush=True)
@@ -343,6 +355,8 @@ def serve_main(a):
                     if len(lat_s) % 8 == 0:
                         print("  %d of %d requests done" % (len(lat_s), len(reqs)), file=sys.stderr, flush=True)
                     if st != kdmg.KDMG_OK:
+                        if st != kdmg.KDMG_ENOCONV:
+                            print("request %d: %s" % (i, srv.last_error), file=sys.stderr, flush=True)
                         k, m, L, _ = reqs[i]
                         failures.append({"L": L, "config": k, "mass": m, "status": st,
                                          "outer_its": info[0]["outer_its"],
@@ -383,12 +397,13 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
     closed = make_requests(a.serve_closed, 1)
     lat_c, info_c, _, span = run(srv, ids, closed, None)
     cap = len(closed) / span
+    cap_used = a.serve_capacity if a.serve_capacity > 0 else cap
     closed_ok = sum(int(info_c[i]["converged"]) for i in range(len(closed)))
     print("closed loop: %d requests (%d converged) in %.2f s -> %.2f requests/s" % (len(closed), closed_ok, span, cap),
           file=sys.stderr, flush=True)
     points = []
     for frac in a.serve_fracs:
-        qps = frac * cap
+        qps = frac * cap_used
         reqs = make_requests(a.serve_requests, 2 + len(points))
         arr = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
         lat_s, infos, xs, span = run(srv, ids, reqs, list(arr))
@@ -428,7 +443,7 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
         alone.close()
     diffs = [float(torch.linalg.norm(xs[i] - xs1[j]) / torch.linalg.norm(xs1[j])) for j, i in enumerate(sample)]
     res = {"metric": "served KD-MG solves, 2D U(1), L^2 in {64,128,256,512}^2, m log-uniform in [1e-3, 1e-1]",
-           "unit": "solves/s", "closed_loop_requests_per_s": cap,
+           "unit": "solves/s", "closed_loop_requests_per_s": cap, "capacity_for_load_points": cap_used,
            "closed_loop_solves_per_s": closed_ok / span, "closed_loop_requests": len(closed),
            "closed_loop_converged": closed_ok, "points": points,
            "slots": a.serve_slots, "hbm_budget_gb": a.serve_budget_gb, "configs": len(cfgs),
@@ -436,7 +451,8 @@ def _serve_measure(a, kdmg, torch, np, cfgs, srv, budget, run, make_requests, rn
            "setup_masses": list(SERVE_M_SETUPS), "beta3_max_L": a.serve_beta3_max_L, "prec": "mixed", "tol": 1e-10,
            "levels": "4x4 n_vec %d; 2x2 n_vec %d" % SERVE_NV,
            "setup_relaxation": {"tol": SERVE_SETUP_TOL, "maxit": SERVE_SETUP_MAXIT},
-           "outer_maxit": 80, "outer_stall": SERVE_STALL,
+           "outer_maxit": 80, "outer_stall": SERVE_STALL, "coarse_maxit": SERVE_COARSE_MAXIT,
+           "exact_coarsest_max_L": SERVE_EXACT_MAX_L,
            "server": stats, "failed_requests": failures,
            "alone_vs_mix_max_rel_diff": max(diffs) if diffs else None,
            "alone_vs_mix_identical": sum(d == 0.0 for d in diffs), "alone_checked": len(diffs)}
@@ -734,6 +750,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-fracs", type=float, nargs="+", default=[0.5, 0.8])
     ap.add_argument("--serve-check", type=int, default=8)
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="requests/s the load fractions refer to (0: this run's closed-loop rate)")
     a = ap.parse_args()
     if a.cpu_child is not None:
         cpu_baseline_child(a.cpu_child)

@@ -152,6 +152,12 @@ kdmg_hierarchy* run_request(kdmg_server& s, Request& r, Pooled slot, hipStream_t
     if (h) rc = kdmg_hierarchy_set_mass(h, base, r.mass, st);
     else rc = kdmg_hierarchy_at_mass(base, r.mass, st, &h);
   }
+  // Served solves launch plainly, without graph capture: a request rebinds
+  // its hierarchy (new mass, often a new configuration), which would recapture
+  // every graph anyway, and a capture in one worker overlapping another
+  // worker's first-use calls (the autotuner's timing launches, allocations)
+  // gave HIP errors on the first requests of a configuration.
+  if (rc == KDMG_OK && h) h->use_graphs = false;
   if (rc == KDMG_OK) rc = kdmg_solve(h, r.b, r.x, r.nrhs, r.tol, r.prec, r.info.data(), st);
   r.status = rc;
   if (rc != KDMG_OK) r.err = last_error_copy();

@@ -147,3 +147,37 @@ def test_admission_by_footprint(K, served):
         assert e.value.status == K.KDMG_ENOMEM
     finally:
         small.close()
+
+
+def test_served_exact_coarsest_first_requests(K):
+    """Configurations with the exact coarsest solve, every request queued at
+    once on fresh configurations, so the first requests of each tune launch
+    shapes while other workers solve: every request succeeds (served solves
+    run without graph capture), reaches 1e-10, and equals a direct solve."""
+    cfgs = []
+    for dims, beta, seed, levels in SERVED:
+        U, _ = u1_heatbath(dims, beta, 30, seed + 100)
+        lat = K.Lattice(dims, U)
+        psi0 = []
+        n = dims[0] * dims[1]
+        nsites = n // 4
+        for k, (agg, nv) in enumerate(levels):
+            psi0.append(gaussian_vectors(nv, n, seed, tag=1 + k))
+            nsites //= int(np.prod(agg))
+            n = nsites * 2 * nv
+        h = K.Hierarchy(lat, M_SETUP, K.make_params(levels, coarse_solver=1), psi0)
+        cfgs.append((dims, U, lat, h))
+    reqs = requests(cfgs, 12, 4)
+    xs, infos, st = serve(K, cfgs, reqs, 4, 8 << 30, all_at_once=True)
+    assert st["completed"] == len(reqs)
+    for (c, m, b), x, inf in zip(reqs, xs, infos):
+        dims, U = cfgs[c][0], cfgs[c][1]
+        D = dirac_matrix(OLattice(dims), U, m)
+        assert inf["converged"]
+        assert np.linalg.norm(b[0] - D @ x) / np.linalg.norm(b[0]) <= 1e-10
+        h = cfgs[c][3].at_mass(m)
+        bd = torch.from_numpy(b).to("cuda")
+        xd = torch.zeros_like(bd)
+        K.kdmg_solve(h, bd, xd, 1, 1e-10, prec=K.KDMG_MIXED)
+        xr = xd.cpu().numpy()[0]
+        assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-12
