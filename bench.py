@@ -709,8 +709,8 @@ def fine_main(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle worker processes of the CPU baseline (0: available cores - 2, at most 14)")
     ap.add_argument("--naik-steps", type=int, default=2,
