@@ -52,6 +52,7 @@ TRAFFIC = {"dense": {"file": "coarsest_dense.hip",
                     "bytes_per_launch": ((13688.1 + 12286.7) * 2.0 + (6400.0 + 3328.6) * 1.0) / 2 * 1024}}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def gauge_field():
@@ -1038,6 +1039,34 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_c, "flops_per_launch": flops,
                 "hbm_gbs": bytes_c / t_c / 1e9}
 
+    # the other kernel with a comparable share of the solve: the level-1
+    # stencil apply (FP32 MFMA, 32 rhs, the tuned shape the solve uses), timed
+    # by graph replay of the same call.  Algorithmic work per launch: the
+    # FP32 stencil blocks once (8 B per complex: ndir ndc^2 per site), the rhs
+    # in and out once (8 B each); 8 ndir ndc^2 nrhs flop per site.
+    dims1, nd1 = h.level_info(1)
+    ns1 = int(np.prod(dims1))
+    ndir1 = 2 * len(dims1) + 1
+    v1 = torch.randn((NRHS, ns1 * nd1), dtype=torch.complex64, device="cuda")
+    o1 = torch.empty_like(v1)
+    t1 = graph_time(lambda: kdmg.kdmg_coarse_apply(h, 1, v1, o1, NRHS, prec=kdmg.KDMG_MIXED), o1)
+    if t1 is None:
+        t1 = event_time(lambda: kdmg.kdmg_coarse_apply(h, 1, v1, o1, NRHS, prec=kdmg.KDMG_MIXED), 100)
+    bytes1 = 8.0 * ndir1 * nd1 * nd1 * ns1 + 2 * 8.0 * ns1 * nd1 * NRHS
+    flops1 = 8.0 * ndir1 * nd1 * nd1 * ns1 * NRHS
+    t_hbm1, t_mfma1 = bytes1 / (HBM_PEAK_GBS * 1e9), flops1 / (FP32_PEAK_TFLOPS * 1e12)
+    mb1 = t_mfma1 >= t_hbm1
+    roofline_l1 = {"kernel": "k_capply_fast (level-1 stencil apply, %d sites x %d dofs, FP32 stencil, %d rhs; "
+                             "MFMA f32 16x16x4)" % (ns1, nd1, NRHS),
+                   "bound": "mfma" if mb1 else "hbm",
+                   "achieved": flops1 / t1 / 1e12 if mb1 else bytes1 / t1 / 1e9,
+                   "peak": FP32_PEAK_TFLOPS if mb1 else HBM_PEAK_GBS,
+                   "unit": "TFLOP/s" if mb1 else "GB/s", "frac": (t_mfma1 if mb1 else t_hbm1) / t1,
+                   "us_per_launch": t1 * 1e6, "timing": "graph replay of the same call",
+                   "algorithmic_bytes_per_launch": bytes1, "flops_per_launch": flops1}
+    print("level-1 stencil: %.1f us per apply, %.2f of its roofline" % (t1 * 1e6, roofline_l1["frac"]),
+          file=sys.stderr, flush=True)
+
     cpu_res = None
     if cpu_wanted:
         print("cpu baseline: oracle hierarchy and solves on the host", file=sys.stderr, flush=True)
@@ -1068,6 +1097,7 @@ def main():
         "cg_eo": cg_eo,
         "dslash": dslash,
         "roofline": roofline,
+        "roofline_level1_stencil": roofline_l1,
         "cpu_baseline": cpu_res,
         "plaquette": ginfo["plaquette"],
     }
