@@ -108,7 +108,11 @@ __device__ __forceinline__ double group_sum(double v, int GS) {
   return v;
 }
 
-inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz) {
+// plain = true: the layout of the stencil apply alone (k_capply_fast), which
+// needs none of the fused CGNE's per-rhs scalars (S, sc, live) and writes its
+// output tile O over the panel once the contraction is done, so more
+// workgroups fit in a CU's LDS.
+inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz, bool plain = false) {
   LdsLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -124,10 +128,10 @@ inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz) {
   int nib = s.core ? 0 : ndc / s.TI, nrb = s.core ? 0 : s.RT / s.TR;
   L.red = take(s.core ? 0 : (size_t)(s.KS - 1) * nib * nrb * s.TI * s.TR * esz);
   const int nsl = s.core ? s.MT * 4 : nib;
-  L.S = take((size_t)nsl * s.RT * sizeof(double));
-  L.sc = take((size_t)(2 * s.RT + 1024) * sizeof(double));
-  L.live = take((size_t)s.RT * sizeof(int));
-  L.O = take((size_t)s.RT * ndc * esz);
+  L.S = take(plain ? 0 : (size_t)nsl * s.RT * sizeof(double));
+  L.sc = take(plain ? 0 : (size_t)(2 * s.RT + 1024) * sizeof(double));
+  L.live = take(plain ? 0 : (size_t)s.RT * sizeof(int));
+  L.O = plain ? L.vs : take((size_t)s.RT * ndc * esz);
   L.total = o;
   return L;
 }
@@ -458,7 +462,7 @@ __device__ __forceinline__ void run_core(Frag<R, FragN<CORE, TI, TR>::value>& f,
 
 // Device-side recomputation of the LDS layout (same arithmetic as the host).
 __device__ __forceinline__ LdsLayout lds_layout_dev(int core, int ylds, int RT, int TI, int TR, int KS, int MT,
-                                                    int ndc, int ndir, int esz) {
+                                                    int ndc, int ndir, int esz, bool plain = false) {
   LdsLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -473,10 +477,10 @@ __device__ __forceinline__ LdsLayout lds_layout_dev(int core, int ylds, int RT, 
   const int nib = core ? 0 : ndc / TI, nrb = core ? 0 : RT / TR;
   L.red = take(core ? 0 : (size_t)(KS - 1) * nib * nrb * TI * TR * esz);
   const int nsl = core ? MT * 4 : nib;
-  L.S = take((size_t)nsl * RT * sizeof(double));
-  L.sc = take((size_t)(2 * RT + 1024) * sizeof(double));
-  L.live = take((size_t)RT * sizeof(int));
-  L.O = take((size_t)RT * ndc * esz);
+  L.S = take(plain ? 0 : (size_t)nsl * RT * sizeof(double));
+  L.sc = take(plain ? 0 : (size_t)(2 * RT + 1024) * sizeof(double));
+  L.live = take(plain ? 0 : (size_t)RT * sizeof(int));
+  L.O = plain ? L.vs : take((size_t)RT * ndc * esz);
   L.total = o;
   return L;
 }
@@ -492,7 +496,7 @@ __global__ __launch_bounds__(1024) void k_capply_fast(Cx<VO>* __restrict__ out, 
                                                       const int* __restrict__ nbr, int nsites, int ndc, int ndir,
                                                       TileArgs ta, int nrhs, const int* act) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>));
+  const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>), true);
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT;
   if (act) {  // a tile of converged rhs has nothing to write
     int mine = 0;
@@ -506,6 +510,7 @@ __global__ __launch_bounds__(1024) void k_capply_fast(Cx<VO>* __restrict__ out, 
   __syncthreads();
   Frag<R, FragN<CORE, TI, TR>::value> f;
   run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yt, X, nsites, ndc, ndir, ta.RT, ta.KS, ta.MT, ta.NT);
+  __syncthreads();  // the output tile O overwrites the panel every wave has read
   Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
   frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
   const float inv_ndc = 1.0f / (float)ndc;

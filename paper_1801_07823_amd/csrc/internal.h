@@ -587,11 +587,13 @@ void coarse_apply_shape(const CoarseLevel& L, bool dag, Cx<R>* out, const Cx<R>*
   }
   const dim3 grid(L.nsites, cdiv(nrhs, s.RT));
   const TileArgs ta = tile_args(s);
+  // the stencil apply alone needs less LDS than the fused CGNE sharing the shape
+  const size_t smem = lds_layout(s, L.ndc, L.ndir, sizeof(Cx<R>), true).total;
 #define KDMG_LAUNCH_CAPPLY(C_, TI_, TR_, YL_)                                                              \
   {                                                                                                        \
     auto fn = k_capply_fast<R, OT, R, R, C_, TI_, TR_, YL_>;                                                    \
-    ensure_smem((const void*)fn, s.smem);                                                                  \
-    hipLaunchKernelGGL(fn, grid, dim3(s.threads), s.smem, st, out, in, add, (R)sgn, Y, L.nbr.as<int>(),    \
+    ensure_smem((const void*)fn, smem);                                                                    \
+    hipLaunchKernelGGL(fn, grid, dim3(s.threads), smem, st, out, in, add, (R)sgn, Y, L.nbr.as<int>(),      \
                        L.nsites, L.ndc, L.ndir, ta, nrhs, act);                                            \
   }
   KDMG_TILE_DISPATCH(s, KDMG_LAUNCH_CAPPLY);
