@@ -78,9 +78,23 @@ struct LdsLayout {
   size_t ys, vs, red, S, sc, live, O, total;
 };
 
-// panel row stride (complex entries): one pad entry keeps the rhs-strided LDS
-// stores of the dof-fastest gather off a single bank
-__host__ __device__ __forceinline__ int panel_stride(int RT) { return RT + 1; }
+// Panel row stride (complex entries) and the place of entry (contraction row
+// k, tile rhs r).  Tiles of fewer than 32 rhs keep one pad entry per row, so
+// the rhs-strided LDS stores of the dof-fastest gather do not hit a single
+// bank.  Tiles of 32 rhs (or a multiple) are unpadded and swizzled instead:
+// within each aligned group of 32 columns, column r of row k sits at
+// r ^ g(k), g(k) = 16 (k & 1) + ((k >> 1) & 15), a permutation of the 32
+// columns for every row.  With 64 four-byte banks and 8-byte entries, a row
+// of 32 entries covers every bank once, and
+//  * the gather's stores (32 consecutive rows of one rhs per half-wavefront)
+//    fall in 32 different columns;
+//  * the MFMA B-operand reads (16 consecutive columns of rows k and k + 1,
+//    k even, per half-wavefront) fall in opposite 16-column halves;
+// so neither access has a bank conflict.
+__host__ __device__ __forceinline__ int panel_stride(int RT) { return RT % 32 == 0 ? RT : RT + 1; }
+__host__ __device__ __forceinline__ int panel_at(int k, int r, int RT) {
+  return RT % 32 == 0 ? k * RT + (r ^ (((k & 1) << 4) | ((k >> 1) & 15))) : k * (RT + 1) + r;
+}
 
 // panel rows (contraction index k = dir * ndc + j) rounded up to the 8 of an
 // MFMA chunk pair; rows [ndir * ndc, kpad8) are zero
@@ -110,8 +124,11 @@ __device__ __forceinline__ double group_sum(double v, int GS) {
 
 // plain = true: the layout of the stencil apply alone (k_capply_fast), which
 // needs none of the fused CGNE's per-rhs scalars (S, sc, live) and writes its
-// output tile O over the panel once the contraction is done, so more
-// workgroups fit in a CU's LDS.
+// output tile O over the panel once the contraction is done; with the
+// stencil blocks streamed from global memory, the MFMA k-split partials
+// (written once every wave has left the contraction) go over the panel too.
+// At the level-1 shape (32 dofs, 5 directions) a 32-rhs tile then takes the
+// 40 KB panel alone (four workgroups per CU), a 16-rhs tile 22 KB (seven).
 inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz, bool plain = false) {
   LdsLayout L;
   size_t o = 0;
@@ -122,9 +139,13 @@ inline LdsLayout lds_layout(const TileShape& s, int ndc, int ndir, size_t esz, b
   };
   // stencil blocks (else read from global); also the MFMA k-split partials,
   // written after the contraction
-  L.ys = take(std::max(s.core && s.ylds ? (size_t)ndir * ndc * ndc * esz : 0,
-                       s.core && s.KS > 1 ? (size_t)(s.KS - 1) * s.MT * s.NT * 256 * esz : 0));
-  L.vs = take((size_t)kpad8(ndir * ndc) * panel_stride(s.RT) * esz);
+  const size_t ysz = s.core && s.ylds ? (size_t)ndir * ndc * ndc * esz : 0;
+  const size_t ksz = s.core && s.KS > 1 ? (size_t)(s.KS - 1) * s.MT * s.NT * 256 * esz : 0;
+  const size_t vsz = (size_t)kpad8(ndir * ndc) * panel_stride(s.RT) * esz;
+  const bool alias = plain && ysz == 0 && ksz <= vsz;
+  L.ys = take(alias ? 0 : std::max(ysz, ksz));
+  L.vs = take(vsz);
+  if (alias) L.ys = L.vs;
   int nib = s.core ? 0 : ndc / s.TI, nrb = s.core ? 0 : s.RT / s.TR;
   L.red = take(s.core ? 0 : (size_t)(s.KS - 1) * nib * nrb * s.TI * s.TR * esz);
   const int nsl = s.core ? s.MT * 4 : nib;
@@ -203,7 +224,7 @@ constexpr int YU = 4, SU = 8;
 // every load of a pass (stencil blocks, panel, partial sums) is issued before
 // any is consumed, so the common shapes pay a single memory round trip.
 //   Ys[(d*ndc + j)*ndc + i] = Y_dir(X)[i][j]            (when Ys != null)
-//   Vs[(d*ndc + j)*RTP + r] = v[r0 + r][nbr(X, d)][j]    (rhs >= nrhs read as 0;
+//   Vs[panel_at(d*ndc + j, r)] = v[r0 + r][nbr(X, d)][j] (rhs >= nrhs read as 0;
 //                                                         rows up to kpad8 zero)
 // With P != null ([rhs][site] partial sums of the previous kernel) the lane
 // g of rhs group t (t = tid / GS, g = tid % GS, GS = group_size(RT)) sums
@@ -254,7 +275,7 @@ __device__ __forceinline__ void stage_all(Cx<R>* Ys, Cx<R>* Vs, const Cx<OT>* __
     }
 #pragma unroll
     for (int d = 0; d < MAX_DIR; ++d)
-      if (pe && d < ndir) Vs[(d * ndc + j) * RTP + r] = tv[d];
+      if (pe && d < ndir) Vs[panel_at(d * ndc + j, r, RT)] = tv[d];
 #pragma unroll
     for (int u = 0; u < YU; ++u) {
       const int ey = yb + tid + u * nthr;
@@ -307,7 +328,7 @@ __device__ __forceinline__ void core_simt(Frag<R, TI * TR>& f, const Cx<OT>* __r
     for (int b = 0; b < TR; ++b) acc[a][b] = Cx<R>{0, 0};
   if (valid) {
     const int nk = ndir * ndc;
-    const int i0 = ib * TI, r0l = rb * TR, RTP = panel_stride(RT);
+    const int i0 = ib * TI, r0l = rb * TR;
     const long per = (long)ndc * ndc;
     const float inv_ndc = 1.0f / (float)ndc;
 #pragma unroll 8
@@ -318,7 +339,7 @@ __device__ __forceinline__ void core_simt(Frag<R, TI * TR>& f, const Cx<OT>* __r
 #pragma unroll
       for (int a = 0; a < TI; ++a) y[a] = ld<R>(yp[a]);
 #pragma unroll
-      for (int b = 0; b < TR; ++b) v[b] = Vs[k * RTP + r0l + b];
+      for (int b = 0; b < TR; ++b) v[b] = Vs[panel_at(k, r0l + b, RT)];
 #pragma unroll
       for (int a = 0; a < TI; ++a)
 #pragma unroll
@@ -395,8 +416,7 @@ __device__ __forceinline__ void core_mfma(Frag<R, 4>& f, Cx<R>* Ys, const Cx<OT>
       return ld<R>(Yt[((long)d * nsites + X) * per + (long)j * ndc + iac]);
     }
   };
-  const int RTP = panel_stride(RT);
-  auto loadB = [&](int k) -> Cx<R> { return Vs[min(k, K8 - 1) * RTP + cb]; };
+  auto loadB = [&](int k) -> Cx<R> { return Vs[panel_at(min(k, K8 - 1), cb, RT)]; };
   // Three real products per complex one (Gauss): with P1 = Ar Br,
   // P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi):  Re = P1 - P2, Im = P3 - P1 - P2.
   // Two accumulator sets (even / odd k-chunks) keep independent MFMAs in
@@ -472,8 +492,11 @@ __device__ __forceinline__ LdsLayout lds_layout_dev(int core, int ylds, int RT, 
   };
   const size_t ysz = core && ylds ? (size_t)ndir * ndc * ndc * esz : 0;
   const size_t ksz = core && KS > 1 ? (size_t)(KS - 1) * MT * (RT / 16) * 256 * esz : 0;
-  L.ys = take(ysz > ksz ? ysz : ksz);
-  L.vs = take((size_t)kpad8(ndir * ndc) * panel_stride(RT) * esz);
+  const size_t vsz = (size_t)kpad8(ndir * ndc) * panel_stride(RT) * esz;
+  const bool alias = plain && ysz == 0 && ksz <= vsz;
+  L.ys = take(alias ? 0 : (ysz > ksz ? ysz : ksz));
+  L.vs = take(vsz);
+  if (alias) L.ys = L.vs;
   const int nib = core ? 0 : ndc / TI, nrb = core ? 0 : RT / TR;
   L.red = take(core ? 0 : (size_t)(KS - 1) * nib * nrb * TI * TR * esz);
   const int nsl = core ? MT * 4 : nib;
@@ -499,9 +522,11 @@ __global__ __launch_bounds__(1024) void k_capply_fast(Cx<VO>* __restrict__ out, 
   const LdsLayout L = lds_layout_dev(CORE, YL, ta.RT, TI, TR, ta.KS, ta.MT, ndc, ndir, sizeof(Cx<R>), true);
   const int X = blockIdx.x, r0 = blockIdx.y * ta.RT;
   if (act) {  // a tile of converged rhs has nothing to write
-    int mine = 0;
-    for (int t = threadIdx.x; t < ta.RT && r0 + t < nrhs; t += blockDim.x) mine |= act[r0 + t];
-    if (!__syncthreads_or(mine)) return;
+    // every thread reads the same flags (uniform, scalar loads): no barrier
+    // and no LDS of the block-wide reduction
+    int any = 0;
+    for (int t = 0; t < ta.RT && r0 + t < nrhs; ++t) any |= act[r0 + t];
+    if (!any) return;
   }
   const Nbrs nb = load_nbrs(nbr, X, nsites, ndir);
   stage_all<R, OT, VI>(CORE == 1 && YL == 1 ? reinterpret_cast<Cx<R>*>(smem_raw + L.ys) : nullptr,
@@ -692,7 +717,6 @@ __global__ __launch_bounds__(1024) void k_cgne_A(Cx<R>* x, Cx<R>* r, const Cx<R>
   Frag<R, FragN<CORE, TI, TR>::value> f;
   run_core<R, OT, CORE, TI, TR, YL>(f, smem_raw, L, Yt, X, nsites, ndc, ndir, RT, ta.KS, ta.MT, ta.NT);
   const Cx<R>* Vs = reinterpret_cast<const Cx<R>*>(smem_raw + L.vs);
-  const int RTP = panel_stride(RT);
   Cx<R>* O = reinterpret_cast<Cx<R>*>(smem_raw + L.O);
   frag_to_tile<R, FragN<CORE, TI, TR>::value>(O, f, ndc);
   const float inv_ndc = 1.0f / (float)ndc;
@@ -707,7 +731,7 @@ __global__ __launch_bounds__(1024) void k_cgne_A(Cx<R>* x, Cx<R>* r, const Cx<R>
     const bool first = e == (int)threadIdx.x;
     const Cx<R> xv = first ? x0 : x[o];
     const Cx<R> rv_old = first ? r0v : r[o];
-    const Cx<R> pv = Vs[i * RTP + t];  // direction 0 is the site itself
+    const Cx<R> pv = Vs[panel_at(i, t, RT)];  // direction 0 is the site itself
     x[o] = xv + al * pv;
     const Cx<R> rv = rv_old - al * O[e];
     r[o] = rv;
