@@ -5,6 +5,9 @@
 // the level's real operator and keeps the fastest.  The fused coarsest-level
 // CGNE kernels share the choice, since they run the same stencil core.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdio>
 #include <vector>
 
@@ -98,6 +101,31 @@ TileShape tune_one(const CoarseLevel& L, int nrhs, hipStream_t st, bool verbose)
   return best;
 }
 
+// Tuned shapes shared by every hierarchy of the process.  A kernel's time
+// depends on the level's shape (sites, dofs per site, directions), the rhs
+// count and the precision, not on the operator's values, so each shape is
+// tuned once; every later hierarchy of the same shape then launches the same
+// kernels, in the same summation order, and gets bit-identical results from
+// identical inputs (near-tied candidates would otherwise be chosen by
+// timing noise).  The first tuner to publish a shape wins.
+namespace {
+std::mutex g_shape_mu;
+std::map<std::tuple<int, int, int, long>, TileShape> g_shapes;
+
+bool shared_shape(const CoarseLevel& L, long key, TileShape& out) {
+  std::lock_guard<std::mutex> g(g_shape_mu);
+  auto it = g_shapes.find(std::make_tuple(L.nsites, L.ndc, L.ndir, key));
+  if (it == g_shapes.end()) return false;
+  out = it->second;
+  return true;
+}
+
+TileShape publish_shape(const CoarseLevel& L, long key, const TileShape& s) {
+  std::lock_guard<std::mutex> g(g_shape_mu);
+  return g_shapes.emplace(std::make_tuple(L.nsites, L.ndc, L.ndir, key), s).first->second;
+}
+}  // namespace
+
 void autotune_level(const CoarseLevel& L, int nrhs, bool fp32, hipStream_t st) {
   const size_t esz = fp32 ? sizeof(c32) : sizeof(c64);
   const long key = (long)nrhs * 64 + (long)esz;
@@ -105,9 +133,16 @@ void autotune_level(const CoarseLevel& L, int nrhs, bool fp32, hipStream_t st) {
     std::lock_guard<std::mutex> g(*L.tune_mu);
     if (L.tuned.count(key)) return;
   }
+  TileShape known;
+  if (shared_shape(L, key, known)) {
+    std::lock_guard<std::mutex> g(*L.tune_mu);
+    L.tuned.emplace(key, known);
+    return;
+  }
   const char* e = std::getenv("KDMG_TUNE_VERBOSE");
   const bool verbose = e && e[0] == '1';
   TileShape best = fp32 ? tune_one<float, float>(L, nrhs, st, verbose) : tune_one<double, double>(L, nrhs, st, verbose);
+  best = publish_shape(L, key, best);
   std::lock_guard<std::mutex> g(*L.tune_mu);
   L.tuned.emplace(key, best);  // a concurrent tuner that finished first wins
 }
@@ -121,6 +156,12 @@ void autotune_cgne(const CoarseLevel& L, int nrhs, hipStream_t st) {
   {
     std::lock_guard<std::mutex> g(*L.tune_mu);
     if (L.tuned.count(key)) return;
+  }
+  TileShape known;
+  if (shared_shape(L, key, known)) {
+    std::lock_guard<std::mutex> g(*L.tune_mu);
+    L.tuned.emplace(key, known);
+    return;
   }
   const char* ev = std::getenv("KDMG_TUNE_VERBOSE");
   const bool verbose = ev && ev[0] == '1';
@@ -170,6 +211,7 @@ void autotune_cgne(const CoarseLevel& L, int nrhs, hipStream_t st) {
   }
   KDMG_HIP(hipEventDestroy(e0));
   KDMG_HIP(hipEventDestroy(e1));
+  best = publish_shape(L, key, best);
   std::lock_guard<std::mutex> g(*L.tune_mu);
   L.tuned.emplace(key, best);
 }
