@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_dn_adj(c64* X, const c64* Ninv, const c
 // rhs tile holds no active rhs returns at once (its partial sums are never
 // read: k_dn_reduce skips inactive rhs).
 template <int NT>
-__global__ __launch_bounds__(256) void k_dn_apply(c64* part, const c64* __restrict__ X, const c64* __restrict__ b,
+__global__ __launch_bounds__(256, 3) void k_dn_apply(c64* part, const c64* __restrict__ X, const c64* __restrict__ b,
                                                   long n, int nrhs, long kc, const int* act) {
   constexpr int RW = 16 * NT;
   __shared__ c64 Xs[64][33];
