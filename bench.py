@@ -40,12 +40,12 @@ WORKLOAD = {"workload": "2D U(1) staggered KD-MG solve", "lattice": [256, 256], 
 #   * the headline's coarsest product, k_dn_apply + k_dn_reduce per call
 #     (average over the calls with an active rhs; calls whose rhs had all
 #     converged return at once and are not counted, as in the live timing):
-#     FETCH 310799.3 + 11958.5 KiB, WRITE 24576.0 + 2986.0 KiB;
+#     FETCH 309822.5 + 14944.1 KiB, WRITE 30720.0 + 2986.0 KiB;
 #   * the Table 1 form's fused CGNE pair k_cgne_A / k_cgne_B (average of the
 #     pair, 32 rhs, the tuned MFMA shape).
 TRAFFIC = {"dense": {"file": "coarsest_dense.hip",
-                     "sha256": "e8d42c868366113a4838bd84ec06ca5f594e94baa5cd5c907380c6241c912f6e",
-                     "bytes_per_launch": ((310799.3 + 11958.5) * 2.0 + (24576.0 + 2986.0) * 1.0) * 1024},
+                     "sha256": "9f21871bd08ab275d4459958c4bcc9f0d4d19f00f64c86bebffa15388a5528ac",
+                     "bytes_per_launch": ((309822.5 + 14944.1) * 2.0 + (30720.0 + 2986.0) * 1.0) * 1024},
            "cgne": {"file": "coarse_fast.h",
                     "sha256": "ef7256408755d5ae044f1bb7fa62d08e7c1c28a7ce0478d42ec5b3e42db524ee",
                     "n_vec_2": 12,

@@ -187,8 +187,12 @@ __global__ __launch_bounds__(256) void k_dn_adj(c64* X, const c64* Ninv, const c
     if (i0 + u < ndc) X[((long)Z * ndc + i0 + u) * n + c] = acc[u];
 }
 
+// k-chunk width of the product and its workgroups per CU (the register
+// budget is set so that this many fit: 256 threads each)
+constexpr int DN_KC = 16, DN_WPC = 4;
+
 // part[s][r][i] = sum_{k in split s} X[i][k] b[r][k] for a 64-row x (16 NT)-rhs
-// tile.  Each 32-wide k-chunk of X and b is staged in LDS from coalesced
+// tile.  Each DN_KC-wide k-chunk of X and b is staged in LDS from coalesced
 // loads; the next chunk's loads are issued into registers before the current
 // chunk is contracted, so their latency overlaps the MFMAs.  Wave w contracts
 // rows 16w..16w+15 against NT 16-rhs tiles with v_mfma_f64_16x16x4 (Gauss:
@@ -197,11 +201,11 @@ __global__ __launch_bounds__(256) void k_dn_adj(c64* X, const c64* Ninv, const c
 // rhs tile holds no active rhs returns at once (its partial sums are never
 // read: k_dn_reduce skips inactive rhs).
 template <int NT>
-__global__ __launch_bounds__(256, 3) void k_dn_apply(c64* part, const c64* __restrict__ X, const c64* __restrict__ b,
+__global__ __launch_bounds__(256, DN_WPC) void k_dn_apply(c64* part, const c64* __restrict__ X, const c64* __restrict__ b,
                                                   long n, int nrhs, long kc, const int* act) {
-  constexpr int RW = 16 * NT;
-  __shared__ c64 Xs[64][33];
-  __shared__ c64 Bs[RW][33];
+  constexpr int RW = 16 * NT, KC = DN_KC;
+  __shared__ c64 Xs[64][KC + 1];
+  __shared__ c64 Bs[RW][KC + 1];
   using M = Mfma<double>;
   typedef M::v4 v4;
   const int rb = blockIdx.z * RW;
@@ -220,39 +224,40 @@ __global__ __launch_bounds__(256, 3) void k_dn_apply(c64* part, const c64* __res
     p2[t] = v4{0, 0, 0, 0};
     p3[t] = v4{0, 0, 0, 0};
   }
-  c64 rx[8], rbv[2 * NT];
+  constexpr int NX = 64 * KC / 256, NB = RW * KC / 256;
+  c64 rx[NX], rbv[NB];
   auto fetch = [&](long kb) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int e = j * 256 + threadIdx.x, r = e >> 5, k = e & 31;
+    for (int j = 0; j < NX; ++j) {
+      const int e = j * 256 + threadIdx.x, r = e / KC, k = e % KC;
       const long gr = min(row0 + r, n - 1), gk = kb + k;
       const c64 v = X[gr * n + min(gk, n - 1)];
       rx[j] = gk < k1 ? v : c64{0, 0};
     }
 #pragma unroll
-    for (int j = 0; j < 2 * NT; ++j) {
-      const int e = j * 256 + threadIdx.x, c = e >> 5, k = e & 31;
+    for (int j = 0; j < NB; ++j) {
+      const int e = j * 256 + threadIdx.x, c = e / KC, k = e % KC;
       const long gc = min(rb + c, nrhs - 1), gk = kb + k;
       const c64 v = b[gc * n + min(gk, n - 1)];
       rbv[j] = gk < k1 ? v : c64{0, 0};
     }
   };
   fetch(k0);
-  for (long kb = k0; kb < k1; kb += 32) {
+  for (long kb = k0; kb < k1; kb += KC) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NX; ++j) {
       const int e = j * 256 + threadIdx.x;
-      Xs[e >> 5][e & 31] = rx[j];
+      Xs[e / KC][e % KC] = rx[j];
     }
 #pragma unroll
-    for (int j = 0; j < 2 * NT; ++j) {
+    for (int j = 0; j < NB; ++j) {
       const int e = j * 256 + threadIdx.x;
-      Bs[e >> 5][e & 31] = rbv[j];
+      Bs[e / KC][e % KC] = rbv[j];
     }
     __syncthreads();
-    if (kb + 32 < k1) fetch(kb + 32);  // in flight during the contraction below
+    if (kb + KC < k1) fetch(kb + KC);  // in flight during the contraction below
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < KC / 4; ++s) {
       const c64 a = Xs[16 * w + (l & 15)][4 * s + (l >> 4)];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -264,22 +269,26 @@ __global__ __launch_bounds__(256, 3) void k_dn_apply(c64* part, const c64* __res
     }
     __syncthreads();
   }
-  // fragments -> LDS tile O[rhs][row] (in Xs' storage) -> coalesced rows
+  // fragments -> LDS tile O[rhs][row] (in Xs' storage, one 16-rhs tile at a
+  // time) -> coalesced rows
+  static_assert(64 * (KC + 1) >= 16 * 64, "the output tile must fit in Xs");
   c64* O = &Xs[0][0];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int t = 0; t < NT; ++t) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = 16 * w + M::row(l, v), c = 16 * t + (l & 15);
+      const int i = 16 * w + M::row(l, v), c = l & 15;
       const double q1 = p1[t][v], q2 = p2[t][v], q3 = p3[t][v];
       O[c * 64 + i] = c64{q1 - q2, q3 - q1 - q2};
     }
-  __syncthreads();
-  for (int e = threadIdx.x; e < RW * 64; e += 256) {
-    const int c = e >> 6, i = e & 63;
-    const long gr = row0 + i;
-    const int gc = rb + c;
-    if (gr < n && gc < nrhs) part[((long)blockIdx.y * nrhs + gc) * n + gr] = O[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int c = e >> 6, i = e & 63;
+      const long gr = row0 + i;
+      const int gc = rb + 16 * t + c;
+      if (gr < n && gc < nrhs) part[((long)blockIdx.y * nrhs + gc) * n + gr] = O[e];
+    }
+    __syncthreads();
   }
 }
 
@@ -310,9 +319,9 @@ __global__ __launch_bounds__(256) void k_dn_reduce(c64* out, const c64* part, lo
 
 long split_width(long n, int nrhs) {
   const long tiles = (long)cdiv(n, 64) * cdiv(nrhs, nrhs > 16 ? 32 : 16);
-  long s = (768 + tiles - 1) / tiles;  // about three resident workgroups per CU
-  s = std::max(1L, std::min(s, (long)cdiv(n, 32)));
-  return (long)cdiv(cdiv(n, s), 32) * 32;
+  long s = 256L * DN_WPC / tiles;  // as many splits as stay resident at once
+  s = std::max(1L, std::min(s, (long)cdiv(n, DN_KC)));
+  return (long)cdiv(cdiv(n, s), DN_KC) * DN_KC;
 }
 
 }  // namespace
